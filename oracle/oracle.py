@@ -1,0 +1,335 @@
+"""ctypes wrapper of the CPU oracle (bdm_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the CPU-baseline leg
+of the benchmark, never by the GPU library or its Python binding.  Arrays are numpy, in agent-id
+order (index == id).  Every function mirrors one C entry point; see bdm_oracle.c for the
+definitions and the paper passages they follow.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+OK, EINVAL, ENOMEM, ENONFINITE, ETOOMANYBOXES = 0, -1, -2, -3, -4
+RNG_INIT, RNG_MOVE, RNG_REC, RNG_INF, RNG_DIV = 1, 2, 3, 4, 5
+SIR_S, SIR_I, SIR_R = 0, 1, 2
+
+
+class OracleError(RuntimeError):
+    def __init__(self, rc: int, what: str):
+        super().__init__(f"oracle {what} failed with code {rc}")
+        self.rc = rc
+
+
+class _Grid(C.Structure):
+    _fields_ = [("b", C.c_double), ("periodic", C.c_int32), ("L", C.c_double),
+                ("cmin", C.c_int64 * 3), ("dims", C.c_int64 * 3), ("nboxes", C.c_int64)]
+
+
+class _MechParams(C.Structure):
+    _fields_ = [("k", C.c_double), ("gamma", C.c_double), ("dt", C.c_double),
+                ("max_disp", C.c_double), ("box", C.c_double), ("force_bits", C.c_int32),
+                ("max_boxes", C.c_int64)]
+
+
+class _SpheroidParams(C.Structure):
+    _fields_ = [("mech", _MechParams), ("grow", C.c_double), ("div_d", C.c_double),
+                ("half_cbrt", C.c_double), ("seed", C.c_uint64), ("salt", C.c_uint64)]
+
+
+class _SirParams(C.Structure):
+    _fields_ = [("L", C.c_double), ("box", C.c_double), ("r_inf", C.c_double),
+                ("p_inf", C.c_double), ("p_rec", C.c_double), ("walk", C.c_double),
+                ("max_boxes", C.c_int64), ("seed", C.c_uint64), ("salt", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _build  # noqa: WPS433 (local build step)
+            _build.build()
+        _lib = C.CDLL(LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+def _p(a, ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+_D = C.POINTER(C.c_double)
+_U8 = C.POINTER(C.c_uint8)
+_U32 = C.POINTER(C.c_uint32)
+_U64 = C.POINTER(C.c_uint64)
+_I32 = C.POINTER(C.c_int32)
+_I64 = C.POINTER(C.c_int64)
+
+
+def _declare(L):
+    L.orc_philox4x64_10.argtypes = [_U64, _U64, _U64]
+    L.orc_philox4x64_10.restype = None
+    L.orc_draw.argtypes = [C.c_uint64] * 6 + [_U64]
+    L.orc_draw.restype = None
+    L.orc_u01.argtypes = [C.c_uint64]
+    L.orc_u01.restype = C.c_double
+    L.orc_bernoulli.argtypes = [C.c_uint64, C.c_double]
+    L.orc_bernoulli.restype = C.c_int
+    L.orc_generate_cube.argtypes = [C.c_int64, C.c_uint64, C.c_uint64, C.c_double, C.c_double,
+                                    C.c_double, C.c_double, _D, _D, _D, _D, _D]
+    L.orc_generate_ball.argtypes = L.orc_generate_cube.argtypes
+    L.orc_generate_sir.argtypes = [C.c_int64, C.c_uint64, C.c_uint64, C.c_double, C.c_int64,
+                                   _D, _D, _D, _U8]
+    L.orc_grid_setup.argtypes = [C.c_int64, _D, _D, _D, _D, C.c_double, C.c_int32, C.c_double,
+                                 C.c_int64, C.POINTER(_Grid)]
+    L.orc_grid_sort.argtypes = [C.c_int64, _D, _D, _D, C.POINTER(_Grid), _U32, _U32, _U32]
+    L.orc_pair_force_f64.argtypes = [C.c_double] * 10 + [_D]
+    L.orc_pair_force_f32.argtypes = [C.c_double] * 10 + [_D]
+    L.orc_displacement.argtypes = [C.c_double] * 6 + [_D]
+    L.orc_mech_step.argtypes = [C.c_int64, _D, _D, _D, _D, _D, C.POINTER(_MechParams), _D, _D,
+                                _D, _U32, _U8]
+    L.orc_contacts.argtypes = [C.c_int64, _D, _D, _D, _D, C.c_double, C.c_int32, C.c_double,
+                               C.c_double, C.c_int32, C.c_int64, _U32, _I64, _U32]
+    L.orc_division_axis.argtypes = [C.c_uint64] * 4 + [_D]
+    L.orc_division_axis.restype = None
+    L.orc_grow_divide.argtypes = [_I64, C.c_int64, _D, _D, _D, _D, _D,
+                                  C.POINTER(_SpheroidParams), C.c_int64, _I32]
+    L.orc_spheroid_step.argtypes = [_I64, C.c_int64, _D, _D, _D, _D, _D,
+                                    C.POINTER(_SpheroidParams), C.c_int64, _D, _D, _D, _I32]
+    L.orc_sir_step.argtypes = [C.c_int64, _D, _D, _D, _U8, C.POINTER(_SirParams), C.c_int64, _I64]
+    for name in ("orc_generate_cube", "orc_generate_ball", "orc_generate_sir", "orc_grid_setup",
+                 "orc_grid_sort", "orc_pair_force_f64", "orc_pair_force_f32", "orc_displacement",
+                 "orc_mech_step", "orc_contacts", "orc_grow_divide", "orc_spheroid_step",
+                 "orc_sir_step"):
+        getattr(L, name).restype = C.c_int
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise OracleError(rc, what)
+
+
+# ---------------------------------------------------------------------------------------------
+# RNG
+# ---------------------------------------------------------------------------------------------
+def philox(ctr, key) -> np.ndarray:
+    c = np.asarray(ctr, dtype=np.uint64).copy()
+    k = np.asarray(key, dtype=np.uint64).copy()
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64_10(_p(c, C.c_uint64), _p(k, C.c_uint64), _p(out, C.c_uint64))
+    return out
+
+
+def draw(seed, salt, purpose, attempt, agent_id, step) -> np.ndarray:
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_draw(seed, salt, purpose, attempt, agent_id, step, _p(out, C.c_uint64))
+    return out
+
+
+def u01(w: int) -> float:
+    return lib().orc_u01(int(w))
+
+
+def bernoulli(w: int, p: float) -> bool:
+    return bool(lib().orc_bernoulli(int(w), float(p)))
+
+
+# ---------------------------------------------------------------------------------------------
+# Generators
+# ---------------------------------------------------------------------------------------------
+def _zeros(n, dt=np.float64):
+    return np.zeros(max(int(n), 0), dtype=dt)
+
+
+def generate_cube(n, seed, L, dmin, dmax, adh, salt=0):
+    x, y, z, d, a = (_zeros(n) for _ in range(5))
+    _check(lib().orc_generate_cube(n, seed, salt, L, dmin, dmax, adh, _p(x, C.c_double),
+                                   _p(y, C.c_double), _p(z, C.c_double), _p(d, C.c_double),
+                                   _p(a, C.c_double)), "generate_cube")
+    return dict(x=x, y=y, z=z, d=d, adh=a)
+
+
+def generate_ball(n, seed, R, dlo, dhi, adh, salt=0):
+    x, y, z, d, a = (_zeros(n) for _ in range(5))
+    _check(lib().orc_generate_ball(n, seed, salt, R, dlo, dhi, adh, _p(x, C.c_double),
+                                   _p(y, C.c_double), _p(z, C.c_double), _p(d, C.c_double),
+                                   _p(a, C.c_double)), "generate_ball")
+    return dict(x=x, y=y, z=z, d=d, adh=a)
+
+
+def generate_sir(n, seed, L, n_infected, salt=0):
+    x, y, z = (_zeros(n) for _ in range(3))
+    s = _zeros(n, np.uint8)
+    _check(lib().orc_generate_sir(n, seed, salt, L, n_infected, _p(x, C.c_double),
+                                  _p(y, C.c_double), _p(z, C.c_double), _p(s, C.c_uint8)),
+           "generate_sir")
+    return dict(x=x, y=y, z=z, state=s)
+
+
+# ---------------------------------------------------------------------------------------------
+# Grid
+# ---------------------------------------------------------------------------------------------
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def grid(x, y, z, d=None, box=0.0, periodic=False, L=0.0, max_boxes=1 << 31):
+    """Grid parameters plus keys[n] (id order), order[n] (ids sorted by (key, id)) and
+    start[nboxes + 1]."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    d = None if d is None else _f64(d)
+    n = len(x)
+    g = _Grid()
+    _check(lib().orc_grid_setup(n, _p(x, C.c_double), _p(y, C.c_double), _p(z, C.c_double),
+                                _p(d, C.c_double), box, int(periodic), L, max_boxes, C.byref(g)),
+           "grid_setup")
+    key = _zeros(n, np.uint32)
+    order = _zeros(n, np.uint32)
+    start = np.zeros(g.nboxes + 1, dtype=np.uint32)
+    if n:
+        _check(lib().orc_grid_sort(n, _p(x, C.c_double), _p(y, C.c_double), _p(z, C.c_double),
+                                   C.byref(g), _p(key, C.c_uint32), _p(order, C.c_uint32),
+                                   _p(start, C.c_uint32)), "grid_sort")
+    info = dict(b=g.b, cmin=tuple(g.cmin), dims=tuple(g.dims), nboxes=g.nboxes)
+    return info, key, order, start
+
+
+# ---------------------------------------------------------------------------------------------
+# Mechanics
+# ---------------------------------------------------------------------------------------------
+def pair_force(pi, di, pj, dj, k=2.0, gamma=1.0, bits=64):
+    out = np.zeros(3)
+    fn = lib().orc_pair_force_f64 if bits == 64 else lib().orc_pair_force_f32
+    hit = fn(*map(float, pi), float(di), *map(float, pj), float(dj), k, gamma, _p(out, C.c_double))
+    return bool(hit), out
+
+
+def displacement(f, adh, dt, max_disp):
+    out = np.zeros(3)
+    flag = lib().orc_displacement(*map(float, f), adh, dt, max_disp, _p(out, C.c_double))
+    return flag, out
+
+
+def mech_params(k=2.0, gamma=1.0, dt=0.01, max_disp=3.0, box=0.0, force_bits=64,
+                max_boxes=1 << 31):
+    return _MechParams(k, gamma, dt, max_disp, box, force_bits, max_boxes)
+
+
+def mech_step(state, k=2.0, gamma=1.0, dt=0.01, max_disp=3.0, box=0.0, force_bits=64,
+              max_boxes=1 << 31, with_contacts=False):
+    """One mechanical step, in place on state['x'|'y'|'z'].  Returns (fx, fy, fz, ncontact, flags)."""
+    for key in ("x", "y", "z", "d", "adh"):
+        state[key] = _f64(state[key])
+    n = len(state["x"])
+    p = mech_params(k, gamma, dt, max_disp, box, force_bits, max_boxes)
+    fx, fy, fz = _zeros(n), _zeros(n), _zeros(n)
+    nc = _zeros(n, np.uint32)
+    fl = _zeros(n, np.uint8)
+    _check(lib().orc_mech_step(n, _p(state["x"], C.c_double), _p(state["y"], C.c_double),
+                               _p(state["z"], C.c_double), _p(state["d"], C.c_double),
+                               _p(state["adh"], C.c_double), C.byref(p), _p(fx, C.c_double),
+                               _p(fy, C.c_double), _p(fz, C.c_double), _p(nc, C.c_uint32),
+                               _p(fl, C.c_uint8)), "mech_step")
+    return fx, fy, fz, nc, fl
+
+
+def contacts(x, y, z, d=None, box=0.0, periodic=False, L=0.0, radius=0.0, force_bits=64,
+             max_boxes=1 << 31):
+    """Contact lists in canonical order as (counts[n], offsets[n], ids[sum])."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    d = None if d is None else _f64(d)
+    n = len(x)
+    counts = _zeros(n, np.uint32)
+    args = (n, _p(x, C.c_double), _p(y, C.c_double), _p(z, C.c_double), _p(d, C.c_double), box,
+            int(periodic), L, radius, force_bits, max_boxes)
+    _check(lib().orc_contacts(*args, _p(counts, C.c_uint32), None, None), "contacts")
+    offsets = np.zeros(n, dtype=np.int64)
+    if n:
+        offsets[1:] = np.cumsum(counts.astype(np.int64))[:-1]
+    ids = np.zeros(int(counts.sum()), dtype=np.uint32)
+    _check(lib().orc_contacts(*args, _p(counts, C.c_uint32), _p(offsets, C.c_int64),
+                              _p(ids, C.c_uint32)), "contacts")
+    return counts, offsets, ids
+
+
+# ---------------------------------------------------------------------------------------------
+# Spheroid
+# ---------------------------------------------------------------------------------------------
+def spheroid_params(grow, div_d, half_cbrt, seed, salt=0, **mech):
+    return _SpheroidParams(mech_params(**mech), grow, div_d, half_cbrt, seed, salt)
+
+
+def division_axis(seed, agent_id, step, salt=0):
+    out = np.zeros(3)
+    lib().orc_division_axis(seed, salt, agent_id, step, _p(out, C.c_double))
+    return out
+
+
+class SpheroidState:
+    """Spheroid population with room for `capacity` agents (arrays sized to capacity)."""
+
+    def __init__(self, init: dict, capacity: int):
+        n = len(init["x"])
+        self.capacity = int(capacity)
+        self.n = np.array([n], dtype=np.int64)
+        self.arr = {}
+        for key in ("x", "y", "z", "d", "adh"):
+            a = np.zeros(self.capacity, dtype=np.float64)
+            a[:n] = init[key]
+            self.arr[key] = a
+        self.f = [np.zeros(self.capacity) for _ in range(3)]
+
+    def view(self, key):
+        return self.arr[key][: int(self.n[0])]
+
+    def step(self, params: _SpheroidParams, step: int):
+        ov = np.zeros(1, dtype=np.int32)
+        a = self.arr
+        _check(lib().orc_spheroid_step(_p(self.n, C.c_int64), self.capacity,
+                                       _p(a["x"], C.c_double), _p(a["y"], C.c_double),
+                                       _p(a["z"], C.c_double), _p(a["d"], C.c_double),
+                                       _p(a["adh"], C.c_double), C.byref(params), step,
+                                       _p(self.f[0], C.c_double), _p(self.f[1], C.c_double),
+                                       _p(self.f[2], C.c_double), _p(ov, C.c_int32)),
+               "spheroid_step")
+        return bool(ov[0])
+
+    def grow_divide(self, params: _SpheroidParams, step: int):
+        ov = np.zeros(1, dtype=np.int32)
+        a = self.arr
+        _check(lib().orc_grow_divide(_p(self.n, C.c_int64), self.capacity,
+                                     _p(a["x"], C.c_double), _p(a["y"], C.c_double),
+                                     _p(a["z"], C.c_double), _p(a["d"], C.c_double),
+                                     _p(a["adh"], C.c_double), C.byref(params), step,
+                                     _p(ov, C.c_int32)), "grow_divide")
+        return bool(ov[0])
+
+
+# ---------------------------------------------------------------------------------------------
+# SIR
+# ---------------------------------------------------------------------------------------------
+def sir_params(L, box, r_inf, p_inf, p_rec, walk, seed, salt=0, max_boxes=1 << 31):
+    return _SirParams(L, box, r_inf, p_inf, p_rec, walk, max_boxes, seed, salt)
+
+
+def sir_step(state, params: _SirParams, step: int):
+    """One SIR step in place on state['x'|'y'|'z'|'state']; returns the S, I, R counts."""
+    for key in ("x", "y", "z"):
+        state[key] = _f64(state[key])
+    state["state"] = np.ascontiguousarray(state["state"], dtype=np.uint8)
+    counts = np.zeros(3, dtype=np.int64)
+    n = len(state["x"])
+    _check(lib().orc_sir_step(n, _p(state["x"], C.c_double), _p(state["y"], C.c_double),
+                              _p(state["z"], C.c_double), _p(state["state"], C.c_uint8),
+                              C.byref(params), step, _p(counts, C.c_int64)), "sir_step")
+    return counts

@@ -1,0 +1,61 @@
+"""Seeded synthetic inputs shared by the oracle tests and the GPU parity tests.
+
+This module only places agents (numpy's own seeded generator, fixed lattices, hand-made edge
+cases); it holds none of the method's arithmetic.  The method's own seeded generator (Philox
+keyed by seed and agent id) is implemented separately by the oracle and by the GPU library.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def uniform_cube(n, L, dmin=10.0, dmax=15.0, adh=0.4, seed=0):
+    """n spheres uniform in [0, L)^3, diameters uniform in [dmin, dmax)."""
+    r = np.random.default_rng(seed)
+    return dict(x=r.uniform(0, L, n), y=r.uniform(0, L, n), z=r.uniform(0, L, n),
+                d=r.uniform(dmin, dmax, n), adh=np.full(n, adh))
+
+
+def cube_side_for(n, density_n=4096, density_L=200.0):
+    """Edge of the cube holding n agents at the density of density_n agents in density_L^3."""
+    return density_L * (n / density_n) ** (1.0 / 3.0)
+
+
+def box_face_adversarial(n, b, cells=6, d=None, seed=0):
+    """Agents whose coordinates sit exactly on box faces x = m*b (and a few just below/above),
+    diameter b (so b is the box edge)."""
+    r = np.random.default_rng(seed)
+    m = r.integers(0, cells, size=(n, 3)).astype(np.float64)
+    pos = m * b
+    jitter_kind = r.integers(0, 3, size=(n, 3))
+    pos = np.where(jitter_kind == 1, np.nextafter(pos, -np.inf), pos)
+    pos = np.where(jitter_kind == 2, np.nextafter(pos, np.inf), pos)
+    dd = np.full(n, b if d is None else d)
+    dd[0] = b  # the largest diameter fixes the box edge
+    return dict(x=pos[:, 0].copy(), y=pos[:, 1].copy(), z=pos[:, 2].copy(), d=dd,
+                adh=np.full(n, 0.4))
+
+
+def lattice(k, spacing, d, origin=0.0, adh=0.4):
+    """k^3 spheres on a cubic lattice, x fastest."""
+    g = origin + spacing * np.arange(k, dtype=np.float64)
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    n = k ** 3
+    return dict(x=x.ravel().copy(), y=y.ravel().copy(), z=z.ravel().copy(), d=np.full(n, float(d)),
+                adh=np.full(n, adh))
+
+
+def clustered(n, L, clusters=8, spread=6.0, dmin=8.0, dmax=12.0, seed=0):
+    """Strongly non-uniform placement: Gaussian clumps (many agents per box)."""
+    r = np.random.default_rng(seed)
+    centres = r.uniform(0.2 * L, 0.8 * L, size=(clusters, 3))
+    which = r.integers(0, clusters, n)
+    pos = centres[which] + r.normal(0.0, spread, size=(n, 3))
+    return dict(x=pos[:, 0].copy(), y=pos[:, 1].copy(), z=pos[:, 2].copy(),
+                d=r.uniform(dmin, dmax, n), adh=np.full(n, 0.4))
+
+
+def sir_uniform(n, L, infected_fraction=0.01, seed=0):
+    r = np.random.default_rng(seed)
+    st = (r.random(n) < infected_fraction).astype(np.uint8)
+    return dict(x=r.uniform(0, L, n), y=r.uniform(0, L, n), z=r.uniform(0, L, n), state=st)
