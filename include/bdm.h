@@ -1,0 +1,226 @@
+/*
+ * bdm.h -- C ABI of libbdm.so, the MI355X (gfx950) hot path of the BioDynaMo agent-based engine
+ * (Breitwieser et al., arXiv 2006.06775): each timestep's mechanical interaction of spherical
+ * agents -- a uniform-grid neighbour search followed by the sphere-sphere force and an
+ * adherence-gated, clamped displacement -- plus the two workloads the paper runs on the same
+ * grid (tumour-spheroid growth/division, SIR epidemiology) and a seeded generator.
+ *
+ * Conventions that hold for every entry point:
+ *   - All array pointers are DEVICE pointers owned by the caller, unless a parameter says
+ *     "host".  The library never allocates device memory inside these calls, never frees and
+ *     never creates streams.  `stream` is a hipStream_t (NULL = the default stream); every
+ *     call is asynchronous on it unless it says "synchronises".
+ *   - Arguments are validated synchronously on the host; a violation returns a negative
+ *     BDM_E* code and launches nothing.  Conditions only the device can see (capacity or box
+ *     overflow, non-finite data, box smaller than the largest agent) set sticky bits in the
+ *     workspace that bdm_status() returns; a step that meets one leaves the agent state
+ *     untouched.  No C++ exception crosses this boundary.
+ *   - Agent state lives in structure-of-arrays form (bdm_soa).  After a grid build the library
+ *     keeps agents in box-sorted order, lexicographic in (box key, agent id); every step writes
+ *     its results back into the caller's arrays in that order.  id[] says which agent sits in
+ *     each slot; bdm_read_agents() restores id order.
+ *   - Floating point: binary64 without contraction, correctly rounded sqrt and division, so
+ *     results are reproducible bit for bit from run to run.
+ */
+#ifndef BDM_H
+#define BDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------------------------ */
+#define BDM_OK 0
+#define BDM_EINVAL (-1)   /* an argument is out of its documented range */
+#define BDM_ENOWS (-2)    /* workspace missing, too small, or sized for smaller arrays */
+#define BDM_EHIP (-3)     /* a HIP runtime call failed; bdm_last_error() has the text */
+#define BDM_ENODEV (-4)   /* no usable gfx950 device */
+
+/* ---- sticky device status bits (bdm_status) ---------------------------------------------- */
+#define BDM_FLAG_CAPACITY 0x1u   /* a division found no free slot below capacity */
+#define BDM_FLAG_BOXES 0x2u      /* the grid needed more than max_boxes boxes */
+#define BDM_FLAG_NONFINITE 0x4u  /* a position or diameter was NaN/Inf, or too far out */
+#define BDM_FLAG_BOXSMALL 0x8u   /* explicit box edge below the largest diameter */
+#define BDM_FLAG_NOGRID 0x10u    /* a step ran without a valid grid of the same agents */
+#define BDM_FLAG_SCAN 0x20u      /* a prefix-scan look-back exceeded its spin bound */
+#define BDM_FLAG_BADCOUNT 0x40u  /* the live count was outside [0, capacity] */
+#define BDM_FLAG_BADID 0x80u     /* an agent id was outside [0, n) where ids must be dense */
+
+/* ---- models for bdm_sim_step ------------------------------------------------------------- */
+#define BDM_MODEL_MECH 0      /* grid build + mechanical step (open space) */
+#define BDM_MODEL_SPHEROID 1  /* growth + division, then grid build + mechanical step */
+#define BDM_MODEL_SIR 2       /* periodic grid build + SIR infection/recovery/movement */
+
+/* ---- generator kinds for bdm_generate ---------------------------------------------------- */
+#define BDM_GEN_CUBE 0  /* uniform in [0, L)^3, diameter uniform in [dlo, dhi) */
+#define BDM_GEN_BALL 1  /* uniform in the ball of radius L about the origin (rejection) */
+#define BDM_GEN_SIR 2   /* points uniform in [0, L)^3, ids < n_infected infected */
+
+/* Agent state.  Every array has `capacity` elements; `n` points to the device-resident live
+ * count (int64).  diam/adh may be NULL for point agents (SIR); fx/fy/fz may be NULL when the
+ * forces are not wanted; state may be NULL except for SIR (0 = S, 1 = I, 2 = R). */
+typedef struct bdm_soa {
+    int64_t capacity;
+    int64_t *n;
+    double *x, *y, *z;
+    double *diam, *adh;
+    double *fx, *fy, *fz;
+    uint32_t *id;
+    uint8_t *state;
+} bdm_soa;
+
+/* Parameters.  Fields a model does not use are ignored. */
+typedef struct bdm_params {
+    double k, gamma;       /* force F = k*delta - gamma*sqrt(rhat*delta) */
+    double dt;             /* displacement = dt * F (> 0) */
+    double max_disp;       /* displacement clamp length (> 0) */
+    double box;            /* > 0: explicit box edge (>= largest diameter); <= 0: largest diameter */
+    int32_t force_bits;    /* 64: binary64 pair force; 32: binary32 pair force, binary64 sums */
+    int32_t periodic;      /* 1 only for SIR: periodic cube [0, L)^3 */
+    double L;              /* periodic cube edge */
+    double r_inf, p_inf, p_rec, walk;  /* SIR radius (inclusive), probabilities, step bound */
+    double grow;           /* spheroid: diameter factor per step */
+    double div_d;          /* spheroid: division threshold diameter */
+    double half_cbrt;      /* spheroid: daughter diameter factor (cube root of 1/2) */
+    uint64_t seed, salt;   /* Philox4x64-10 key */
+} bdm_params;
+
+/* Seeded initial state. */
+typedef struct bdm_gen {
+    int32_t kind;          /* BDM_GEN_* */
+    int64_t n;             /* agents to create (<= capacity) */
+    double L;              /* cube edge, or ball radius */
+    double dlo, dhi;       /* diameter range */
+    double adh;            /* adherence of every agent */
+    int64_t n_infected;    /* SIR: agents with id < n_infected start infected */
+    uint64_t seed, salt;   /* Philox4x64-10 key */
+} bdm_gen;
+
+/* Caller-owned scratch memory sized by bdm_workspace_bytes for at most `capacity` agents and
+ * `max_boxes` grid boxes.  It also holds the sorted copies, the grid and the status bits, so
+ * one workspace serves one population at a time. */
+typedef struct bdm_workspace {
+    void *ptr;             /* device, 256-byte aligned */
+    size_t bytes;
+    int64_t capacity;
+    int64_t max_boxes;
+} bdm_workspace;
+
+/* Read-back of the device-resident grid description (bdm_grid_info). */
+typedef struct bdm_grid_desc {
+    double b;              /* box edge */
+    int32_t cmin[3];       /* lattice coordinate of box 0 (open space) */
+    int32_t dims[3];       /* boxes per axis */
+    int64_t nboxes;
+    int64_t n;             /* agents binned */
+    int32_t valid;         /* 1 when the last build succeeded */
+    uint32_t flags;        /* sticky BDM_FLAG_* bits */
+} bdm_grid_desc;
+
+/* Size in bytes of the workspace for `capacity` agents and `max_boxes` boxes; 0 when either is
+ * negative or the size overflows. */
+size_t bdm_workspace_bytes(int64_t capacity, int64_t max_boxes);
+
+/* Prepare a workspace for first use: clears counters, status bits and the box histogram.
+ * Must precede every other call that takes `ws`.  Errors: BDM_ENOWS, BDM_EHIP. */
+int bdm_workspace_init(const bdm_workspace *ws, void *stream);
+
+/* Seeded generator of the initial state [paper Sec. 3.2 places cells in a ball; Sec. 3.3
+ * distributes agents randomly in a cube].  Agent i (0 <= i < gen->n) takes Philox4x64-10 block
+ * (counter (1 + attempt*2^8, i, 0, 0), key (seed, salt)); u = (word >> 11) * 2^-53.  CUBE:
+ * x, y, z = L*u from words 0..2, diam = dlo + (dhi - dlo)*u(word 3).  BALL: attempt t gives
+ * v = 2u - 1 per axis, accepted when |v|^2 <= 1, position L*v.  SIR: CUBE positions, state
+ * 1 for id < n_infected else 0.  Writes arrays in id order (id[i] = i) and *soa->n = gen->n.
+ * Errors: BDM_EINVAL (n > capacity, missing array). */
+int bdm_generate(const bdm_soa *soa, const bdm_gen *gen, void *stream);
+
+/* Uniform grid [paper Sec. 2.1: equal boxes, agents assigned by centre of mass, box edge from
+ * the largest agent, neighbourhood = 27 boxes].  Box edge b = params->box or the largest
+ * diameter; lattice c = floor(x / b) per axis, box 0 at the minimum c, key = cx + nx*(cy +
+ * ny*cz); periodic (SIR): nb = floor(L / box) >= 3 boxes per axis, b = L / nb.  Builds the
+ * histogram, its exclusive scan (start offsets) and the sorted copies of the agents in
+ * (key, id) order inside the workspace.  Does not modify `soa`.  Errors: BDM_EINVAL, BDM_ENOWS;
+ * device: BDM_FLAG_BOXES, BDM_FLAG_NONFINITE, BDM_FLAG_BOXSMALL. */
+int bdm_grid_build(const bdm_soa *soa, const bdm_params *params, const bdm_workspace *ws,
+                   void *stream);
+
+/* Mechanical step on the grid of the last bdm_grid_build of the same agents [paper Sec. 2.1,
+ * "calculate mechanical forces" agent operation; force model of Zubler & Douglas that Sec. 3.4
+ * says BioDynaMo shares with Cortex3D].  For each agent i, over candidates j != i in the 27
+ * boxes in ascending (key, id) order: delta = (d_i + d_j)/2 - |x_i - x_j|; when delta > 0,
+ * F = k*delta - gamma*sqrt(rhat*delta) with rhat = r_i*r_j/(r_i + r_j), and F_i += (F/|.|) *
+ * (x_i - x_j).  Then: |F_i| < adh_i -> no move; else disp = dt*F_i, clamped to length
+ * max_disp; x_i += disp, synchronously for all agents.  Writes x, y, z, diam, adh, id (and
+ * state) in box-sorted order and fx, fy, fz = the summed pre-gate forces.  Errors: BDM_EINVAL,
+ * BDM_ENOWS; device: BDM_FLAG_NOGRID. */
+int bdm_mech_step(const bdm_soa *soa, const bdm_params *params, const bdm_workspace *ws,
+                  void *stream);
+
+/* One full timestep of `model` at step index `step` (used as the Philox counter word 2):
+ *   BDM_MODEL_MECH     bdm_grid_build + bdm_mech_step.
+ *   BDM_MODEL_SPHEROID [paper Sec. 3.2] every diameter *= grow; each agent with diam >= div_d
+ *                      divides: d' = diam*half_cbrt, axis u by rejection from Philox block
+ *                      (5 + attempt*2^8, id, step, 0), mother at x - (d'/4)u, daughter at
+ *                      x + (d'/4)u with id n + (rank of the mother among dividing mothers by
+ *                      id) and the mother's adherence; divisions with no slot below capacity
+ *                      are skipped and set BDM_FLAG_CAPACITY; then grid + mechanics.
+ *   BDM_MODEL_SIR      [paper Sec. 3.3] on the periodic grid of positions at t: a susceptible
+ *                      agent with m infected agents within r_inf (minimum image, inclusive)
+ *                      becomes infected iff one of the draws (4 + c*2^8, id, step, 0), c < m,
+ *                      has word 0 < floor(p_inf*2^64); an infected agent recovers iff draw
+ *                      (3, id, step, 0) has word 0 < floor(p_rec*2^64); every agent moves by
+ *                      walk*(2u - 1) per axis (words 0..2 of draw (2, id, step, 0)) and wraps
+ *                      into [0, L).  S/I/R totals are kept for bdm_sir_counts.
+ * Errors: as the underlying steps. */
+int bdm_sim_step(const bdm_soa *soa, int32_t model, const bdm_params *params, int64_t step,
+                 const bdm_workspace *ws, void *stream);
+
+/* Copy agents from box-sorted slots into id order: out_*[id[s]] = soa->*[s] for s < n.  Any
+ * out pointer may be NULL.  Each out array needs n elements.  Errors: BDM_EINVAL. */
+int bdm_read_agents(const bdm_soa *soa, double *out_x, double *out_y, double *out_z,
+                    double *out_diam, double *out_fx, double *out_fy, double *out_fz,
+                    uint8_t *out_state, void *stream);
+
+/* Sticky status bits of the workspace into *flags (host); clears them when `clear` != 0.
+ * Synchronises the stream.  Errors: BDM_ENOWS, BDM_EHIP. */
+int bdm_status(const bdm_workspace *ws, uint32_t *flags, int32_t clear, void *stream);
+
+/* S, I, R totals after the last SIR step into counts[3] (host).  Synchronises the stream. */
+int bdm_sir_counts(const bdm_workspace *ws, int64_t *counts, void *stream);
+
+/* Grid description of the last build into *desc (host).  Synchronises the stream. */
+int bdm_grid_info(const bdm_workspace *ws, bdm_grid_desc *desc, void *stream);
+
+/* Test hook: copies of the last grid build -- key[n] per agent in the input order of that
+ * build, order[n] = agent ids in box-sorted order, start[nboxes + 1].  Any pointer may be NULL.
+ * Synchronises the stream (it needs n and nboxes). */
+int bdm_grid_export(const bdm_workspace *ws, uint32_t *key, uint32_t *order, uint32_t *start,
+                    void *stream);
+
+/* Test hook: contact lists of the last grid build, per box-sorted slot s, candidates in the
+ * force-sum order.  Mechanical contact (delta > 0 with params->force_bits arithmetic) in open
+ * space, or SIR contact (minimum-image squared distance <= r_inf^2, any state) when
+ * params->periodic.  Call with ids == NULL to get counts[n]; then with offsets[n] (exclusive
+ * prefix of counts, int64) and ids[sum(counts)] to get the agent ids.  Errors: BDM_EINVAL. */
+int bdm_contacts(const bdm_workspace *ws, const bdm_params *params, uint32_t *counts,
+                 const int64_t *offsets, uint32_t *ids, void *stream);
+
+/* Test hook: element-wise IEEE operations as the kernels compute them, for bitwise checks
+ * against the host: out_sqrt[i] = sqrt(a[i]), out_div[i] = a[i] / b[i] in binary64;
+ * out_sqrtf[i] = sqrtf((float)a[i]), out_divf[i] = (float)a[i] / (float)b[i] in binary32. */
+int bdm_fp_probe(const double *a, const double *b, int64_t n, double *out_sqrt, double *out_div,
+                 float *out_sqrtf, float *out_divf, void *stream);
+
+/* Text of a return code; bdm_last_error() gives the detail of the last failure on this
+ * thread (empty when none). */
+const char *bdm_strerror(int code);
+const char *bdm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BDM_H */

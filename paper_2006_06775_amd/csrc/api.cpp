@@ -1,0 +1,396 @@
+// api.cpp -- the C ABI of libbdm.so (declared in include/bdm.h).
+//
+// Host side only: synchronous argument validation, workspace layout, kernel launches on the
+// caller's stream, error codes.  No allocation, no stream creation, no exceptions across the ABI.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_check(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(BDM_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return BDM_OK;
+}
+
+inline hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+// Resolve and check a workspace handle.
+int get_ws(const bdm_workspace *ws, bdm::Ws *out) {
+    if (!ws || !ws->ptr) return fail(BDM_ENOWS, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws->ptr) % 256 != 0)
+        return fail(BDM_ENOWS, "workspace pointer is not 256-byte aligned");
+    bdm::WsLayout lay;
+    if (!bdm::ws_layout(ws->capacity, ws->max_boxes, &lay))
+        return fail(BDM_ENOWS, "workspace capacity %lld / max_boxes %lld out of range",
+                    (long long)ws->capacity, (long long)ws->max_boxes);
+    if (ws->bytes < lay.total)
+        return fail(BDM_ENOWS, "workspace has %zu bytes, needs %zu", ws->bytes, lay.total);
+    *out = bdm::ws_view(ws->ptr, lay);
+    return BDM_OK;
+}
+
+int check_soa(const bdm_soa *s, const bdm::Ws &w, bool need_sphere, bool need_state) {
+    if (!s) return fail(BDM_EINVAL, "soa is NULL");
+    if (!s->n || !s->x || !s->y || !s->z || !s->id)
+        return fail(BDM_EINVAL, "soa needs n, x, y, z and id");
+    if (s->capacity < 0) return fail(BDM_EINVAL, "negative capacity");
+    if (s->capacity > w.lay.capacity)
+        return fail(BDM_ENOWS, "soa capacity %lld exceeds the workspace capacity %lld",
+                    (long long)s->capacity, (long long)w.lay.capacity);
+    if (need_sphere && (!s->diam || !s->adh)) return fail(BDM_EINVAL, "soa needs diam and adh");
+    if (need_state && !s->state) return fail(BDM_EINVAL, "soa needs state");
+    return BDM_OK;
+}
+
+int check_mech_params(const bdm_params *p) {
+    if (!p) return fail(BDM_EINVAL, "params is NULL");
+    if (!(p->dt > 0.0) || !is_fin(p->dt)) return fail(BDM_EINVAL, "dt must be > 0");
+    if (!(p->max_disp > 0.0) || !is_fin(p->max_disp)) return fail(BDM_EINVAL, "max_disp must be > 0");
+    if (!is_fin(p->k) || !is_fin(p->gamma)) return fail(BDM_EINVAL, "k and gamma must be finite");
+    if (p->force_bits != 64 && p->force_bits != 32) return fail(BDM_EINVAL, "force_bits must be 32 or 64");
+    if (!is_fin(p->box)) return fail(BDM_EINVAL, "box must be finite");
+    if (p->periodic) return fail(BDM_EINVAL, "the mechanical step runs in open space (periodic = 0)");
+    return BDM_OK;
+}
+
+int periodic_boxes(const bdm_params *p, const bdm::Ws &w, int32_t *nb) {
+    if (!(p->L > 0.0) || !is_fin(p->L)) return fail(BDM_EINVAL, "periodic L must be > 0");
+    if (!(p->box > 0.0) || !is_fin(p->box)) return fail(BDM_EINVAL, "periodic grids need box > 0");
+    double q = std::floor(p->L / p->box);
+    if (q < 3.0) return fail(BDM_EINVAL, "periodic grid needs at least 3 boxes per axis");
+    if (q > 2097151.0 || q * q * q > double(w.lay.max_boxes))
+        return fail(BDM_ENOWS, "periodic grid of %.0f^3 boxes exceeds max_boxes %lld", q,
+                    (long long)w.lay.max_boxes);
+    *nb = int32_t(q);
+    return BDM_OK;
+}
+
+int do_grid_build(const bdm_soa *s, const bdm_params *p, bool periodic, const bdm::Ws &w,
+                  hipStream_t st) {
+    bdm::FinalizeArgs fa{};
+    fa.box = p->box;
+    fa.L = p->L;
+    fa.periodic = periodic ? 1 : 0;
+    fa.has_d = s->diam ? 1 : 0;
+    fa.max_boxes = w.lay.max_boxes;
+    if (periodic) {
+        int rc = periodic_boxes(p, w, &fa.nb);
+        if (rc) return rc;
+    }
+    bdm::launch_grid_build(*s, fa, w, st);
+    return hip_check("grid_build launch");
+}
+
+bdm::Threshold threshold(double prob) {
+    bdm::Threshold t{0, 0};
+    if (!(prob > 0.0)) return t;
+    if (prob >= 1.0) {
+        t.mode = 2;
+        return t;
+    }
+    t.mode = 1;
+    t.t = static_cast<uint64_t>(std::ldexp(prob, 64));  // exact scaling, truncation = floor
+    return t;
+}
+
+bdm::MechArgs mech_args(const bdm_params *p) {
+    bdm::MechArgs a{};
+    a.k = p->k;
+    a.gamma = p->gamma;
+    a.dt = p->dt;
+    a.max_disp = p->max_disp;
+    a.kf = float(p->k);
+    a.gf = float(p->gamma);
+    return a;
+}
+
+int check_sir_params(const bdm_params *p) {
+    if (!p) return fail(BDM_EINVAL, "params is NULL");
+    if (!(p->r_inf >= 0.0) || !is_fin(p->r_inf)) return fail(BDM_EINVAL, "r_inf must be >= 0");
+    if (p->box < p->r_inf) return fail(BDM_EINVAL, "box must be >= r_inf");
+    if (!(p->walk >= 0.0) || !(p->walk <= p->L)) return fail(BDM_EINVAL, "walk must be in [0, L]");
+    if (std::isnan(p->p_inf) || std::isnan(p->p_rec)) return fail(BDM_EINVAL, "probabilities must not be NaN");
+    return BDM_OK;
+}
+
+int check_spheroid_params(const bdm_params *p) {
+    if (!(p->grow > 0.0) || !is_fin(p->grow)) return fail(BDM_EINVAL, "grow must be > 0");
+    if (!(p->div_d > 0.0) || !is_fin(p->div_d)) return fail(BDM_EINVAL, "div_d must be > 0");
+    if (!(p->half_cbrt > 0.0) || !(p->half_cbrt < 1.0)) return fail(BDM_EINVAL, "half_cbrt must be in (0, 1)");
+    return BDM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t bdm_workspace_bytes(int64_t capacity, int64_t max_boxes) {
+    bdm::WsLayout lay;
+    if (!bdm::ws_layout(capacity, max_boxes, &lay)) return 0;
+    return lay.total;
+}
+
+int bdm_workspace_init(const bdm_workspace *ws, void *stream) {
+    g_last_error.clear();
+    bdm::Ws w;
+    int rc = get_ws(ws, &w);
+    if (rc) return rc;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(BDM_ENODEV, "no HIP device");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(BDM_ENODEV, "no HIP device properties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(BDM_ENODEV, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+    bdm::launch_ws_init(w, as_stream(stream));
+    return hip_check("workspace_init launch");
+}
+
+int bdm_generate(const bdm_soa *soa, const bdm_gen *gen, void *stream) {
+    g_last_error.clear();
+    if (!soa || !gen) return fail(BDM_EINVAL, "soa and gen are required");
+    if (!soa->n || !soa->x || !soa->y || !soa->z || !soa->id) return fail(BDM_EINVAL, "soa needs n, x, y, z, id");
+    if (gen->n < 0 || gen->n > soa->capacity) return fail(BDM_EINVAL, "gen n %lld outside [0, capacity]", (long long)gen->n);
+    if (gen->n > (int64_t(1) << 32) - 2) return fail(BDM_EINVAL, "at most 2^32 - 2 agents");
+    if (gen->kind != BDM_GEN_CUBE && gen->kind != BDM_GEN_BALL && gen->kind != BDM_GEN_SIR)
+        return fail(BDM_EINVAL, "unknown generator kind %d", gen->kind);
+    if (!is_fin(gen->L) || !is_fin(gen->dlo) || !is_fin(gen->dhi) || !is_fin(gen->adh))
+        return fail(BDM_EINVAL, "generator parameters must be finite");
+    if (gen->kind == BDM_GEN_SIR && !soa->state) return fail(BDM_EINVAL, "SIR generator needs state");
+    bdm::GenArgs a{gen->kind, gen->n, gen->L, gen->dlo, gen->dhi, gen->adh, gen->n_infected, gen->seed, gen->salt};
+    bdm::launch_generate(*soa, a, as_stream(stream));
+    return hip_check("generate launch");
+}
+
+int bdm_grid_build(const bdm_soa *soa, const bdm_params *params, const bdm_workspace *ws, void *stream) {
+    g_last_error.clear();
+    bdm::Ws w;
+    int rc = get_ws(ws, &w);
+    if (rc) return rc;
+    if (!params) return fail(BDM_EINVAL, "params is NULL");
+    rc = check_soa(soa, w, false, false);
+    if (rc) return rc;
+    if (!is_fin(params->box)) return fail(BDM_EINVAL, "box must be finite");
+    return do_grid_build(soa, params, params->periodic != 0, w, as_stream(stream));
+}
+
+int bdm_mech_step(const bdm_soa *soa, const bdm_params *params, const bdm_workspace *ws, void *stream) {
+    g_last_error.clear();
+    bdm::Ws w;
+    int rc = get_ws(ws, &w);
+    if (rc) return rc;
+    rc = check_soa(soa, w, true, false);
+    if (rc) return rc;
+    rc = check_mech_params(params);
+    if (rc) return rc;
+    bdm::launch_mech(*soa, mech_args(params), params->force_bits, w, as_stream(stream));
+    return hip_check("mech_step launch");
+}
+
+int bdm_sim_step(const bdm_soa *soa, int32_t model, const bdm_params *params, int64_t step,
+                 const bdm_workspace *ws, void *stream) {
+    g_last_error.clear();
+    bdm::Ws w;
+    int rc = get_ws(ws, &w);
+    if (rc) return rc;
+    if (!params) return fail(BDM_EINVAL, "params is NULL");
+    if (step < 0) return fail(BDM_EINVAL, "step must be >= 0");
+    hipStream_t st = as_stream(stream);
+    switch (model) {
+    case BDM_MODEL_MECH:
+    case BDM_MODEL_SPHEROID: {
+        rc = check_soa(soa, w, true, false);
+        if (rc) return rc;
+        rc = check_mech_params(params);
+        if (rc) return rc;
+        if (model == BDM_MODEL_SPHEROID) {
+            rc = check_spheroid_params(params);
+            if (rc) return rc;
+            bdm::DivArgs a{params->grow, params->div_d, params->half_cbrt, params->seed, params->salt,
+                           uint64_t(step)};
+            bdm::launch_grow_divide(*soa, a, w, st);
+            rc = hip_check("grow_divide launch");
+            if (rc) return rc;
+        }
+        rc = do_grid_build(soa, params, false, w, st);
+        if (rc) return rc;
+        bdm::launch_mech(*soa, mech_args(params), params->force_bits, w, st);
+        return hip_check("mech_step launch");
+    }
+    case BDM_MODEL_SIR: {
+        rc = check_soa(soa, w, false, true);
+        if (rc) return rc;
+        rc = check_sir_params(params);
+        if (rc) return rc;
+        rc = do_grid_build(soa, params, true, w, st);
+        if (rc) return rc;
+        bdm::SirArgs a{};
+        a.L = params->L;
+        a.half = 0.5 * params->L;
+        a.r2 = params->r_inf * params->r_inf;
+        a.walk = params->walk;
+        a.tinf = threshold(params->p_inf);
+        a.trec = threshold(params->p_rec);
+        a.seed = params->seed;
+        a.salt = params->salt;
+        a.step = uint64_t(step);
+        bdm::launch_sir(*soa, a, w, st);
+        return hip_check("sir_step launch");
+    }
+    default:
+        return fail(BDM_EINVAL, "unknown model %d", model);
+    }
+}
+
+int bdm_read_agents(const bdm_soa *soa, double *out_x, double *out_y, double *out_z, double *out_diam,
+                    double *out_fx, double *out_fy, double *out_fz, uint8_t *out_state, void *stream) {
+    g_last_error.clear();
+    if (!soa || !soa->n || !soa->id) return fail(BDM_EINVAL, "soa needs n and id");
+    if ((out_x && !soa->x) || (out_y && !soa->y) || (out_z && !soa->z) || (out_diam && !soa->diam) ||
+        (out_fx && !soa->fx) || (out_fy && !soa->fy) || (out_fz && !soa->fz) || (out_state && !soa->state))
+        return fail(BDM_EINVAL, "an output was requested for an array the soa does not have");
+    bdm::ReadOut o{out_x, out_y, out_z, out_diam, out_fx, out_fy, out_fz, out_state};
+    bdm::launch_read_agents(*soa, o, as_stream(stream));
+    return hip_check("read_agents launch");
+}
+
+int bdm_status(const bdm_workspace *ws, uint32_t *flags, int32_t clear, void *stream) {
+    g_last_error.clear();
+    bdm::Ws w;
+    int rc = get_ws(ws, &w);
+    if (rc) return rc;
+    if (!flags) return fail(BDM_EINVAL, "flags is NULL");
+    hipStream_t st = as_stream(stream);
+    if (hipMemcpyAsync(flags, &w.grid->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return hip_check("status read");
+    if (clear) {
+        if (hipMemsetAsync(&w.grid->flags, 0, sizeof(uint32_t), st) != hipSuccess) return hip_check("status clear");
+    }
+    return BDM_OK;
+}
+
+int bdm_sir_counts(const bdm_workspace *ws, int64_t *counts, void *stream) {
+    g_last_error.clear();
+    bdm::Ws w;
+    int rc = get_ws(ws, &w);
+    if (rc) return rc;
+    if (!counts) return fail(BDM_EINVAL, "counts is NULL");
+    hipStream_t st = as_stream(stream);
+    unsigned long long c[3];
+    if (hipMemcpyAsync(c, w.grid->sir_counts, sizeof c, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return hip_check("sir_counts read");
+    for (int i = 0; i < 3; ++i) counts[i] = int64_t(c[i]);
+    return BDM_OK;
+}
+
+int bdm_grid_info(const bdm_workspace *ws, bdm_grid_desc *desc, void *stream) {
+    g_last_error.clear();
+    bdm::Ws w;
+    int rc = get_ws(ws, &w);
+    if (rc) return rc;
+    if (!desc) return fail(BDM_EINVAL, "desc is NULL");
+    hipStream_t st = as_stream(stream);
+    bdm::GridDev g;
+    if (hipMemcpyAsync(&g, w.grid, sizeof g, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return hip_check("grid_info read");
+    desc->b = g.b;
+    for (int i = 0; i < 3; ++i) {
+        desc->cmin[i] = g.cmin[i];
+        desc->dims[i] = g.dims[i];
+    }
+    desc->nboxes = g.nboxes;
+    desc->n = g.n;
+    desc->valid = g.valid;
+    desc->flags = g.flags;
+    return BDM_OK;
+}
+
+int bdm_grid_export(const bdm_workspace *ws, uint32_t *key, uint32_t *order, uint32_t *start, void *stream) {
+    bdm_grid_desc d;
+    int rc = bdm_grid_info(ws, &d, stream);
+    if (rc) return rc;
+    if (!d.valid) return fail(BDM_EINVAL, "no valid grid in the workspace");
+    bdm::Ws w;
+    get_ws(ws, &w);
+    hipStream_t st = as_stream(stream);
+    size_t n = size_t(d.n);
+    if (key && n && hipMemcpyAsync(key, w.key, 4 * n, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return hip_check("grid_export key");
+    if (order && n && hipMemcpyAsync(order, w.ids, 4 * n, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return hip_check("grid_export order");
+    if (start && hipMemcpyAsync(start, w.start, 4 * (size_t(d.nboxes) + 1), hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return hip_check("grid_export start");
+    if (hipStreamSynchronize(st) != hipSuccess) return hip_check("grid_export sync");
+    return BDM_OK;
+}
+
+int bdm_contacts(const bdm_workspace *ws, const bdm_params *params, uint32_t *counts, const int64_t *offsets,
+                 uint32_t *ids, void *stream) {
+    g_last_error.clear();
+    bdm::Ws w;
+    int rc = get_ws(ws, &w);
+    if (rc) return rc;
+    if (!params || !counts) return fail(BDM_EINVAL, "params and counts are required");
+    if (ids && !offsets) return fail(BDM_EINVAL, "ids need offsets");
+    bdm::ContactArgs a{};
+    if (params->periodic) {
+        a.mode = 2;
+        a.L = params->L;
+        a.half = 0.5 * params->L;
+        a.r2 = params->r_inf * params->r_inf;
+    } else {
+        if (params->force_bits != 32 && params->force_bits != 64) return fail(BDM_EINVAL, "force_bits must be 32 or 64");
+        a.mode = params->force_bits == 32 ? 1 : 0;
+    }
+    bdm::launch_contacts(a, w, counts, offsets, ids, as_stream(stream));
+    return hip_check("contacts launch");
+}
+
+int bdm_fp_probe(const double *a, const double *b, int64_t n, double *out_sqrt, double *out_div,
+                 float *out_sqrtf, float *out_divf, void *stream) {
+    g_last_error.clear();
+    if (n < 0 || (n > 0 && (!a || !b))) return fail(BDM_EINVAL, "fp_probe needs a and b");
+    if (n == 0) return BDM_OK;
+    bdm::launch_fp_probe(a, b, n, out_sqrt, out_div, out_sqrtf, out_divf, as_stream(stream));
+    return hip_check("fp_probe launch");
+}
+
+const char *bdm_strerror(int code) {
+    switch (code) {
+    case BDM_OK: return "ok";
+    case BDM_EINVAL: return "invalid argument";
+    case BDM_ENOWS: return "workspace missing or too small";
+    case BDM_EHIP: return "HIP runtime error";
+    case BDM_ENODEV: return "no usable gfx950 device";
+    default: return "unknown error";
+    }
+}
+
+const char *bdm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,211 @@
+// common.hpp -- internals shared by the gfx950 kernels and the C-ABI layer of libbdm.so.
+//
+// Workspace layout, the device-resident grid record, Philox4x64-10 (Salmon et al., SC'11), the
+// order-preserving integer encoding of binary64 used by the min/max reductions, and the box
+// coordinate rule of the uniform grid (paper Sec. 2.1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bdm.h"
+
+namespace bdm {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts of 64)
+constexpr int kScanItems = 8;        // items per thread in the decoupled look-back scan
+constexpr int kScanTile = kBlock * kScanItems;
+constexpr uint32_t kScanSpinLimit = 1u << 22;  // polls before a look-back gives up
+
+// Philox draw purposes: counter word 0 = purpose + (attempt << 8).
+enum : uint64_t { kRngInit = 1, kRngMove = 2, kRngRec = 3, kRngInf = 4, kRngDiv = 5 };
+
+// Device-resident grid description and step bookkeeping; lives at the head of the workspace.
+struct GridDev {
+    double b;                       // box edge
+    int32_t cmin[3];                // lattice coordinate of box 0
+    int32_t dims[3];                // boxes per axis
+    int64_t nboxes;                 // dims product
+    int64_t n;                      // agents binned by the last build
+    int32_t valid;                  // 1 when the last build succeeded
+    uint32_t flags;                 // sticky BDM_FLAG_* bits
+    unsigned long long red_min[3];  // order-encoded running minima of x, y, z
+    unsigned long long red_max[3];  // order-encoded running maxima
+    unsigned long long red_dmax;    // order-encoded running maximum diameter
+    uint32_t red_bad;               // a non-finite coordinate or diameter was seen
+    uint32_t scan_ticket;           // dynamic tile index of the running scan
+    unsigned long long sir_counts[3];
+};
+static_assert(sizeof(GridDev) <= 256, "grid record must fit its slot");
+
+// Byte offsets of every workspace region (256-byte aligned), derived from capacity/max_boxes.
+struct WsLayout {
+    size_t grid, count, start, tiles, key, rank, tmpid, pos4, adh, ids, state, flagid, rankid;
+    size_t total;
+    int64_t capacity, max_boxes, max_tiles;
+};
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+inline bool ws_layout(int64_t capacity, int64_t max_boxes, WsLayout *L) {
+    if (capacity < 0 || max_boxes < 0 || capacity > (int64_t(1) << 32) - 2 ||
+        max_boxes > (int64_t(1) << 32) - 2)
+        return false;
+    size_t cap = size_t(capacity), mb = size_t(max_boxes);
+    size_t longest = cap > mb ? cap : mb;
+    size_t tiles = (longest + 1 + kScanTile - 1) / kScanTile + 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    L->grid = take(256);
+    L->count = take(4 * (mb + 1));
+    L->start = take(4 * (mb + 1));
+    L->tiles = take(8 * tiles);
+    L->key = take(4 * cap);
+    L->rank = take(4 * cap);
+    L->tmpid = take(4 * cap);
+    L->pos4 = take(32 * cap);
+    L->adh = take(8 * cap);
+    L->ids = take(4 * cap);
+    L->state = take(cap);
+    L->flagid = take(4 * (cap + 1));
+    L->rankid = take(4 * (cap + 1));
+    L->total = off;
+    L->capacity = capacity;
+    L->max_boxes = max_boxes;
+    L->max_tiles = int64_t(tiles);
+    return true;
+}
+
+// Typed views of one workspace.
+struct Ws {
+    GridDev *grid;
+    uint32_t *count, *start;
+    unsigned long long *tiles;
+    uint32_t *key, *rank, *tmpid;
+    double4 *pos4;
+    double *adh;
+    uint32_t *ids;
+    uint8_t *state;
+    uint32_t *flagid, *rankid;
+    WsLayout lay;
+};
+
+inline Ws ws_view(void *base, const WsLayout &L) {
+    char *p = static_cast<char *>(base);
+    Ws w;
+    w.grid = reinterpret_cast<GridDev *>(p + L.grid);
+    w.count = reinterpret_cast<uint32_t *>(p + L.count);
+    w.start = reinterpret_cast<uint32_t *>(p + L.start);
+    w.tiles = reinterpret_cast<unsigned long long *>(p + L.tiles);
+    w.key = reinterpret_cast<uint32_t *>(p + L.key);
+    w.rank = reinterpret_cast<uint32_t *>(p + L.rank);
+    w.tmpid = reinterpret_cast<uint32_t *>(p + L.tmpid);
+    w.pos4 = reinterpret_cast<double4 *>(p + L.pos4);
+    w.adh = reinterpret_cast<double *>(p + L.adh);
+    w.ids = reinterpret_cast<uint32_t *>(p + L.ids);
+    w.state = reinterpret_cast<uint8_t *>(p + L.state);
+    w.flagid = reinterpret_cast<uint32_t *>(p + L.flagid);
+    w.rankid = reinterpret_cast<uint32_t *>(p + L.rankid);
+    w.lay = L;
+    return w;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------------------------
+
+// Philox4x64-10: per round, words 0 and 2 are multiplied (64x64 -> 128) by the two round
+// multipliers; the new block is (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2), hi(M0*c0) ^ c3 ^ k1,
+// lo(M0*c0)); the key advances by the two Weyl increments before every round but the first.
+struct Block4 {
+    uint64_t w[4];
+};
+
+__device__ __forceinline__ Block4 philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                         uint64_t k0, uint64_t k1) {
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+    return Block4{{c0, c1, c2, c3}};
+}
+
+__device__ __forceinline__ Block4 draw(uint64_t seed, uint64_t salt, uint64_t purpose,
+                                       uint64_t attempt, uint64_t id, uint64_t step) {
+    return philox(purpose + (attempt << 8), id, step, 0, seed, salt);
+}
+
+// Uniform binary64 in [0, 1) from the top 53 bits of a word (exact).
+__device__ __forceinline__ double u01(uint64_t w) {
+    return double(w >> 11) * 0x1.0p-53;
+}
+
+// Bernoulli threshold prepared on the host: mode 0 never, 1 compare, 2 always.
+struct Threshold {
+    uint64_t t;
+    int32_t mode;
+};
+
+__device__ __forceinline__ bool bernoulli(uint64_t w, Threshold th) {
+    return th.mode == 2 || (th.mode == 1 && w < th.t);
+}
+
+// Order-preserving map from binary64 to unsigned 64-bit (for atomic min/max).
+__device__ __forceinline__ unsigned long long ord_enc(double v) {
+    unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double ord_dec(unsigned long long e) {
+    unsigned long long b = (e >> 63) ? (e & 0x7fffffffffffffffull) : ~e;
+    return __longlong_as_double(static_cast<long long>(b));
+}
+
+// Box coordinate along one axis: floor(v / b) relative to the grid origin (open space) or as
+// is (periodic cube), clamped into [0, nb - 1].  In open space the clamp never binds (the
+// origin and dims come from the min/max of the same positions) and only guards memory.
+__device__ __forceinline__ int box_coord(double v, double b, int cmin, int nb, bool periodic) {
+    double f = floor(v / b);
+    if (!periodic) f -= double(cmin);
+    if (f < 0.0) f = 0.0;
+    if (f > double(nb - 1)) f = double(nb - 1);
+    return int(f);
+}
+
+// Live count clamped to the array capacity (a corrupted count must not index out of bounds).
+__device__ __forceinline__ int64_t live_count(const int64_t *n_ptr, int64_t capacity) {
+    const int64_t n = *n_ptr;
+    return n < 0 ? 0 : (n > capacity ? capacity : n);
+}
+
+// Wavefront-wide inclusive prefix sum (64 lanes).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+}  // namespace bdm

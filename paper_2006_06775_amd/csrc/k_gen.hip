@@ -1,0 +1,109 @@
+// k_gen.hip -- seeded initial state, workspace initialisation and the IEEE probe (gfx950).
+//
+// Generator: agent i draws Philox4x64-10 blocks at counter (INIT + attempt*2^8, i, 0, 0) keyed
+// by (seed, salt); u = (word >> 11) * 2^-53.  Cube: words 0..2 give x, y, z = L*u, word 3 the
+// diameter dlo + (dhi - dlo)*u.  Ball: v = 2u - 1 per axis, accepted when |v|^2 <= 1 (at most 64
+// attempts, else the origin), position L*v.  SIR: cube positions, state 1 for id < n_infected.
+// The paper places tumour cells in a ball (Sec. 3.2) and persons at random in a cube (Sec. 3.3).
+#include "kernels.hpp"
+
+namespace bdm {
+
+__global__ __launch_bounds__(kBlock) void k_generate(bdm_soa s, GenArgs a) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i == 0) *s.n = a.n;
+    if (i >= a.n) return;
+    double x = 0.0, y = 0.0, z = 0.0, u3 = 0.0;
+    if (a.kind == BDM_GEN_BALL) {
+        for (uint64_t attempt = 0; attempt < 64; ++attempt) {
+            const Block4 w = draw(a.seed, a.salt, kRngInit, attempt, uint64_t(i), 0);
+            const double vx = 2.0 * u01(w.w[0]) - 1.0;
+            const double vy = 2.0 * u01(w.w[1]) - 1.0;
+            const double vz = 2.0 * u01(w.w[2]) - 1.0;
+            if ((vx * vx + vy * vy) + vz * vz <= 1.0) {
+                x = a.L * vx;
+                y = a.L * vy;
+                z = a.L * vz;
+                u3 = u01(w.w[3]);
+                break;
+            }
+        }
+    } else {
+        const Block4 w = draw(a.seed, a.salt, kRngInit, 0, uint64_t(i), 0);
+        x = a.L * u01(w.w[0]);
+        y = a.L * u01(w.w[1]);
+        z = a.L * u01(w.w[2]);
+        u3 = u01(w.w[3]);
+    }
+    s.x[i] = x;
+    s.y[i] = y;
+    s.z[i] = z;
+    if (s.diam) s.diam[i] = a.dlo + (a.dhi - a.dlo) * u3;
+    if (s.adh) s.adh[i] = a.adh;
+    if (s.fx) s.fx[i] = 0.0;
+    if (s.fy) s.fy[i] = 0.0;
+    if (s.fz) s.fz[i] = 0.0;
+    s.id[i] = uint32_t(i);
+    if (s.state) s.state[i] = (a.kind == BDM_GEN_SIR && i < a.n_infected) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fp_probe(const double *a, const double *b, int64_t n,
+                                                     double *os, double *od, float *osf, float *odf) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = a[i], y = b[i];
+    if (os) os[i] = __builtin_sqrt(x);
+    if (od) od[i] = x / y;
+    if (osf) osf[i] = __builtin_sqrtf(float(x));
+    if (odf) odf[i] = float(x) / float(y);
+}
+
+// Zero the grid record, the histogram and the scan tiles; reductions start at their identities.
+__global__ __launch_bounds__(kBlock) void k_ws_init(GridDev *g, uint32_t *count, int64_t ncount,
+                                                    unsigned long long *tiles, int64_t ntiles) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t k = i; k < ncount; k += stride) count[k] = 0u;
+    for (int64_t k = i; k < ntiles; k += stride) tiles[k] = 0ull;
+    if (i == 0) {
+        g->b = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            g->cmin[a] = 0;
+            g->dims[a] = 0;
+            g->red_min[a] = ~0ull;
+            g->red_max[a] = 0ull;
+            g->sir_counts[a] = 0ull;
+        }
+        g->nboxes = 0;
+        g->n = 0;
+        g->valid = 0;
+        g->flags = 0u;
+        g->red_dmax = 0ull;
+        g->red_bad = 0u;
+        g->scan_ticket = 0u;
+    }
+}
+
+static inline unsigned nblocks(int64_t n, int64_t cap_blocks) {
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (cap_blocks > 0 && b > cap_blocks) b = cap_blocks;
+    return unsigned(b);
+}
+
+void launch_generate(const bdm_soa &s, const GenArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(k_generate, dim3(nblocks(a.n, 0)), dim3(kBlock), 0, st, s, a);
+}
+
+void launch_fp_probe(const double *a, const double *b, int64_t n, double *os, double *od, float *osf,
+                     float *odf, hipStream_t st) {
+    hipLaunchKernelGGL(k_fp_probe, dim3(nblocks(n, 0)), dim3(kBlock), 0, st, a, b, n, os, od, osf, odf);
+}
+
+void launch_ws_init(const Ws &w, hipStream_t st) {
+    const int64_t ncount = w.lay.max_boxes + 1;
+    hipLaunchKernelGGL(k_ws_init, dim3(nblocks(ncount, 4096)), dim3(kBlock), 0, st, w.grid, w.count, ncount,
+                       w.tiles, w.lay.max_tiles);
+}
+
+}  // namespace bdm

@@ -1,0 +1,151 @@
+// k_sir.hip -- SIR epidemiology step on gfx950 (paper Sec. 3.3: infection with a probability
+// when an infected agent is within the infection radius, recovery with a probability each
+// step, bounded random movement, agents counted per group).
+//
+// One lane per agent in box-sorted order on the periodic grid of positions at t.  Everything
+// reads state/positions at t (the sorted copies in the workspace) and writes t+1 into the
+// caller's arrays, so the update is synchronous.  Random numbers are Philox blocks keyed by
+// (seed, salt) at counter (purpose + attempt*2^8, agent id, step, 0): the outcome of every agent
+// depends only on its id and the step, never on the order of the lanes.
+#include "kernels.hpp"
+
+namespace bdm {
+
+__device__ __forceinline__ double min_image(double v, double L, double half) {
+    if (v > half) return v - L;
+    if (v < -half) return v + L;
+    return v;
+}
+
+__device__ __forceinline__ double wrap(double v, double L) {
+    if (v < 0.0) v += L;
+    if (v >= L) v -= L;
+    if (v == L) v = 0.0;
+    return v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sir(const GridDev *__restrict__ g,
+                                                const double4 *__restrict__ pos4,
+                                                const uint8_t *__restrict__ state_s,
+                                                const uint32_t *__restrict__ id_s,
+                                                const uint32_t *__restrict__ start, SirArgs a,
+                                                bdm_soa out, unsigned long long *counts) {
+    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool live = g->valid && s < g->n && s < out.capacity;
+    uint8_t ns = 3;  // no agent
+    if (live) {
+        const double4 p = pos4[s];
+        const uint8_t st = state_s[s];
+        const uint32_t me = id_s[s];
+        ns = st;
+        if (st == 0) {
+            const int nb = g->dims[0];
+            const double b = g->b;
+            const int cx = box_coord(p.x, b, 0, nb, true);
+            const int cy = box_coord(p.y, b, 0, nb, true);
+            const int cz = box_coord(p.z, b, 0, nb, true);
+            uint32_t m = 0;
+            for (int oz = -1; oz <= 1; ++oz) {
+                const int zz = (cz + oz + nb) % nb;
+                for (int oy = -1; oy <= 1; ++oy) {
+                    const int yy = (cy + oy + nb) % nb;
+                    for (int ox = -1; ox <= 1; ++ox) {
+                        const int xx = (cx + ox + nb) % nb;
+                        const uint32_t kb = uint32_t(xx) + uint32_t(nb) * (uint32_t(yy) + uint32_t(nb) * uint32_t(zz));
+                        const uint32_t j1 = start[kb + 1];
+                        for (uint32_t j = start[kb]; j < j1; ++j) {
+                            if (j == uint32_t(s) || state_s[j] != 1) continue;
+                            const double4 q = pos4[j];
+                            const double dx = min_image(p.x - q.x, a.L, a.half);
+                            const double dy = min_image(p.y - q.y, a.L, a.half);
+                            const double dz = min_image(p.z - q.z, a.L, a.half);
+                            m += ((dx * dx + dy * dy) + dz * dz) <= a.r2;
+                        }
+                    }
+                }
+            }
+            for (uint32_t c = 0; c < m; ++c) {
+                if (bernoulli(draw(a.seed, a.salt, kRngInf, c, me, a.step).w[0], a.tinf)) {
+                    ns = 1;
+                    break;
+                }
+            }
+        } else if (st == 1) {
+            if (bernoulli(draw(a.seed, a.salt, kRngRec, 0, me, a.step).w[0], a.trec)) ns = 2;
+        }
+        const Block4 w = draw(a.seed, a.salt, kRngMove, 0, me, a.step);
+        out.x[s] = wrap(p.x + a.walk * (2.0 * u01(w.w[0]) - 1.0), a.L);
+        out.y[s] = wrap(p.y + a.walk * (2.0 * u01(w.w[1]) - 1.0), a.L);
+        out.z[s] = wrap(p.z + a.walk * (2.0 * u01(w.w[2]) - 1.0), a.L);
+        out.state[s] = ns;
+        out.id[s] = me;
+    }
+    // S/I/R totals: one atomic per wavefront and group
+    const uint32_t cs = wave_sum(ns == 0), ci = wave_sum(ns == 1), cr = wave_sum(ns == 2);
+    if ((threadIdx.x & 63) == 0) {
+        if (cs) atomicAdd(&counts[0], static_cast<unsigned long long>(cs));
+        if (ci) atomicAdd(&counts[1], static_cast<unsigned long long>(ci));
+        if (cr) atomicAdd(&counts[2], static_cast<unsigned long long>(cr));
+    }
+}
+
+// Test hook: SIR contacts (any state) per sorted slot, boxes visited in (dz, dy, dx) order.
+__global__ __launch_bounds__(kBlock) void k_contacts_periodic(const GridDev *__restrict__ g,
+                                                              const double4 *__restrict__ pos4,
+                                                              const uint32_t *__restrict__ id_s,
+                                                              const uint32_t *__restrict__ start,
+                                                              ContactArgs a, uint32_t *counts,
+                                                              const int64_t *offsets, uint32_t *ids) {
+    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (!g->valid || s >= g->n) return;
+    const double4 p = pos4[s];
+    const int nb = g->dims[0];
+    const double b = g->b;
+    const int cx = box_coord(p.x, b, 0, nb, true);
+    const int cy = box_coord(p.y, b, 0, nb, true);
+    const int cz = box_coord(p.z, b, 0, nb, true);
+    uint32_t c = 0;
+    for (int oz = -1; oz <= 1; ++oz) {
+        const int zz = (cz + oz + nb) % nb;
+        for (int oy = -1; oy <= 1; ++oy) {
+            const int yy = (cy + oy + nb) % nb;
+            for (int ox = -1; ox <= 1; ++ox) {
+                const int xx = (cx + ox + nb) % nb;
+                const uint32_t kb = uint32_t(xx) + uint32_t(nb) * (uint32_t(yy) + uint32_t(nb) * uint32_t(zz));
+                for (uint32_t j = start[kb]; j < start[kb + 1]; ++j) {
+                    if (j == uint32_t(s)) continue;
+                    const double4 q = pos4[j];
+                    const double dx = min_image(p.x - q.x, a.L, a.half);
+                    const double dy = min_image(p.y - q.y, a.L, a.half);
+                    const double dz = min_image(p.z - q.z, a.L, a.half);
+                    if (((dx * dx + dy * dy) + dz * dz) <= a.r2) {
+                        if (ids) ids[offsets[s] + c] = id_s[j];
+                        ++c;
+                    }
+                }
+            }
+        }
+    }
+    counts[s] = c;
+}
+
+void launch_sir(const bdm_soa &s, const SirArgs &a, const Ws &w, hipStream_t st) {
+    int64_t nb = (s.capacity + kBlock - 1) / kBlock;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_sir, dim3(unsigned(nb)), dim3(kBlock), 0, st, w.grid, w.pos4, w.state, w.ids,
+                       w.start, a, s, w.grid->sir_counts);
+}
+
+void launch_contacts(const ContactArgs &a, const Ws &w, uint32_t *counts, const int64_t *offsets,
+                     uint32_t *ids, hipStream_t st) {
+    if (a.mode != 2) {
+        launch_contacts_mech(a.mode == 1, w, counts, offsets, ids, st);
+        return;
+    }
+    int64_t nb = (w.lay.capacity + kBlock - 1) / kBlock;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_contacts_periodic, dim3(unsigned(nb)), dim3(kBlock), 0, st, w.grid, w.pos4,
+                       w.ids, w.start, a, counts, offsets, ids);
+}
+
+}  // namespace bdm

@@ -1,0 +1,104 @@
+// k_spheroid.hip -- tumour-spheroid growth and division on gfx950 (paper Sec. 3.2: cell growth
+// and duplication; the cell growth & division benchmark of Sec. 3.4).
+//
+//   grow_flag  diam *= grow for every live agent; division flag by agent id (diam >= div_d);
+//              also clears the scan tiles for the rank scan that follows
+//   scan       exclusive scan of the flags in id order: rank of each dividing mother by id
+//   divide     mother of rank r puts its daughter in slot n + r (id n + r) when that is below
+//              capacity; random axis by rejection from Philox (DIV, attempt, id, step)
+//   append     n += number of daughters that fitted
+// The live count stays on the device; nothing is read back to the host.
+#include "kernels.hpp"
+
+namespace bdm {
+
+__global__ __launch_bounds__(kBlock) void k_grow_flag(const int64_t *n_ptr, int64_t capacity,
+                                                      double *diam, const uint32_t *__restrict__ id,
+                                                      DivArgs a, uint32_t *flagid,
+                                                      unsigned long long *tiles, int64_t max_tiles,
+                                                      uint32_t *ticket, GridDev *g) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < max_tiles) tiles[i] = 0ull;
+    if (i == 0) *ticket = 0u;
+    const int64_t n = live_count(n_ptr, capacity);
+    if (i >= n) return;
+    const double d = diam[i] * a.grow;
+    diam[i] = d;
+    const uint32_t me = id[i];
+    if (me >= n) {
+        atomicOr(&g->flags, BDM_FLAG_BADID);
+        return;
+    }
+    flagid[me] = d >= a.div_d ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_divide(const int64_t *n_ptr, int64_t capacity, bdm_soa s,
+                                                   const uint32_t *__restrict__ rankid, DivArgs a,
+                                                   GridDev *g) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t n = live_count(n_ptr, capacity);
+    if (i >= n) return;
+    const double d = s.diam[i];
+    if (!(d >= a.div_d)) return;
+    const uint32_t me = s.id[i];
+    if (me >= n) return;
+    const int64_t slot = n + int64_t(rankid[me]);
+    if (slot >= capacity) {
+        atomicOr(&g->flags, BDM_FLAG_CAPACITY);
+        return;
+    }
+    double ux = 1.0, uy = 0.0, uz = 0.0;
+    for (uint64_t attempt = 0; attempt < 64; ++attempt) {
+        const Block4 w = draw(a.seed, a.salt, kRngDiv, attempt, me, a.step);
+        const double vx = 2.0 * u01(w.w[0]) - 1.0;
+        const double vy = 2.0 * u01(w.w[1]) - 1.0;
+        const double vz = 2.0 * u01(w.w[2]) - 1.0;
+        const double q = (vx * vx + vy * vy) + vz * vz;
+        if (q > 0.0 && q <= 1.0) {
+            const double norm = __builtin_sqrt(q);
+            ux = vx / norm;
+            uy = vy / norm;
+            uz = vz / norm;
+            break;
+        }
+    }
+    const double dp = d * a.half_cbrt;
+    const double qd = 0.25 * dp;
+    const double ox = qd * ux, oy = qd * uy, oz = qd * uz;
+    const double x = s.x[i], y = s.y[i], z = s.z[i];
+    s.x[slot] = x + ox;
+    s.y[slot] = y + oy;
+    s.z[slot] = z + oz;
+    s.diam[slot] = dp;
+    s.adh[slot] = s.adh[i];
+    s.id[slot] = uint32_t(slot);
+    s.x[i] = x - ox;
+    s.y[i] = y - oy;
+    s.z[i] = z - oz;
+    s.diam[i] = dp;
+}
+
+__global__ void k_append(int64_t *n_ptr, int64_t capacity, const uint32_t *rankid) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int64_t n = live_count(n_ptr, capacity);
+    int64_t nn = n + int64_t(rankid[n]);
+    if (nn > capacity) nn = capacity;
+    *n_ptr = nn;
+}
+
+void launch_grow_divide(const bdm_soa &s, const DivArgs &a, const Ws &w, hipStream_t st) {
+    const int64_t cap = s.capacity;  // daughters must land inside the caller's arrays
+    int64_t nb = (cap + kBlock - 1) / kBlock;
+    if (nb < 1) nb = 1;
+    const int64_t need = w.lay.max_tiles;
+    int64_t nb_flag = nb;
+    if (nb_flag * kBlock < need) nb_flag = (need + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_grow_flag, dim3(unsigned(nb_flag)), dim3(kBlock), 0, st, s.n, cap, s.diam, s.id,
+                       a, w.flagid, w.tiles, w.lay.max_tiles, &w.grid->scan_ticket, w.grid);
+    launch_scan(w.flagid, w.rankid, s.n, nullptr, cap, w, 0, false, st);
+    hipLaunchKernelGGL(k_divide, dim3(unsigned(nb)), dim3(kBlock), 0, st, s.n, cap, s, w.rankid, a,
+                       w.grid);
+    hipLaunchKernelGGL(k_append, dim3(1), dim3(64), 0, st, s.n, cap, w.rankid);
+}
+
+}  // namespace bdm

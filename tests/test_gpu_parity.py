@@ -1,0 +1,373 @@
+"""GPU parity: the gfx950 path through the C ABI against the CPU oracle, on the same seeded
+inputs.  Integer work (keys, order, start offsets, contact sets, SIR states, division ids and
+counts) must be bit-exact.  Binary64 forces and positions must agree within
+1e-9 * max(|x_ref|, L) (positions) and 1e-9 * sum_j |F_ij| (forces); the design aims at bit
+equality, and the tests report how many agents are bit-equal.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - the gpu marker deselects these on CPU
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2006_06775_amd import bdm  # noqa: E402
+from oracle import oracle as orc  # noqa: E402
+
+TOL = 1e-9
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def population(arrays, capacity=None, max_boxes=1 << 22, spheres=True, state=False):
+    n = len(arrays["x"])
+    pop = bdm.Population(capacity or max(n, 1), max_boxes, spheres=spheres, with_state=state)
+    pop.load(arrays)
+    return pop
+
+
+def mech_p(**kw):
+    base = dict(k=2.0, gamma=1.0, dt=0.01, max_disp=3.0, box=0.0, force_bits=64)
+    base.update(kw)
+    return bdm.params(**base)
+
+
+# ---------------------------------------------------------------------------------------------
+def test_ieee_sqrt_div_bitwise():
+    say("case: fp_probe")
+    r = np.random.default_rng(0)
+    a = np.concatenate([r.uniform(0, 1e3, 200000), r.uniform(0, 1e-3, 50000),
+                        np.exp(r.uniform(-700, 700, 50000)), [0.0, 1.0, 2.0, 4.0, 1e-310, 5e-324]])
+    b = np.concatenate([r.uniform(1e-3, 1e3, len(a) - 6), [1.0, 3.0, 7.0, 1e-300, 3.0, 2.0]])
+    ta = torch.tensor(a, device="cuda")
+    tb = torch.tensor(b, device="cuda")
+    s, d, sf, df = (o.cpu().numpy() for o in bdm.fp_probe(ta, tb))
+    assert np.array_equal(s.view(np.uint64), np.sqrt(a).view(np.uint64))
+    assert np.array_equal(d.view(np.uint64), (a / b).view(np.uint64))
+    with np.errstate(over="ignore"):
+        fa, fb = a.astype(np.float32), b.astype(np.float32)
+    ok = np.isfinite(fa) & np.isfinite(fb) & (fb != 0)
+    assert np.array_equal(sf[ok].view(np.uint32), np.sqrt(fa[ok]).view(np.uint32))
+    assert np.array_equal(df[ok].view(np.uint32), (fa[ok] / fb[ok]).view(np.uint32))
+
+
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,n", [("cube", 4096), ("cube", 4097), ("ball", 10000), ("sir", 5003),
+                                    ("cube", 0), ("cube", 1)])
+def test_generator_bit_exact(kind, n):
+    say(f"case: generate {kind} n={n}")
+    cap = max(n, 1)
+    if kind == "cube":
+        ref = orc.generate_cube(n, 7, 200.0, 10.0, 15.0, 0.4, salt=3)
+        g = bdm.gen(bdm.GEN_CUBE, n, 200.0, 10.0, 15.0, 0.4, seed=7, salt=3)
+        pop = bdm.Population(cap, 1 << 14)
+    elif kind == "ball":
+        h = 0.5 ** (1 / 3)
+        ref = orc.generate_ball(n, 1, 60.0, 14.0 * h, 14.0, 0.4)
+        g = bdm.gen(bdm.GEN_BALL, n, 60.0, 14.0 * h, 14.0, 0.4, seed=1)
+        pop = bdm.Population(cap, 1 << 14)
+    else:
+        ref = orc.generate_sir(n, 5, 5000.0, 5)
+        g = bdm.gen(bdm.GEN_SIR, n, 5000.0, 0.0, 0.0, 0.0, n_infected=5, seed=5)
+        pop = bdm.Population(cap, 1 << 14, spheres=False, with_state=True)
+    bdm.generate(pop.soa, g)
+    assert pop.n == n
+    got = pop.read()
+    for k in ("x", "y", "z"):
+        assert np.array_equal(got[k].view(np.uint64), ref[k].view(np.uint64)), k
+    if kind != "sir":
+        assert np.array_equal(got["diam"].view(np.uint64), ref["d"].view(np.uint64))
+    else:
+        assert np.array_equal(got["state"], ref["state"])
+
+
+# ---------------------------------------------------------------------------------------------
+def grid_cases():
+    return {
+        "c0": orc.generate_cube(4096, 0, 200.0, 10.0, 15.0, 0.4),
+        "ragged": inputs.uniform_cube(5001, 230.0, seed=4),
+        "faces": inputs.box_face_adversarial(3000, 12.0, seed=2),
+        "clustered": inputs.clustered(4000, 300.0, seed=3),
+        "negative": {k: (v - 500.0 if k in "xyz" else v) for k, v in inputs.uniform_cube(2000, 150.0, seed=5).items()},
+        "single": dict(x=np.array([3.0]), y=np.array([4.0]), z=np.array([5.0]), d=np.array([10.0]), adh=np.array([0.4])),
+        "empty": dict(x=np.zeros(0), y=np.zeros(0), z=np.zeros(0), d=np.zeros(0), adh=np.zeros(0)),
+        "onebox": dict(x=np.full(300, 1.0) + np.arange(300) * 1e-3, y=np.ones(300), z=np.ones(300), d=np.full(300, 10.0), adh=np.full(300, 0.4)),
+    }
+
+
+@pytest.mark.parametrize("case", list(grid_cases().keys()))
+def test_grid_lockstep_bit_exact(case):
+    say(f"case: grid {case}")
+    s = grid_cases()[case]
+    n = len(s["x"])
+    pop = population(s, capacity=max(n, 1))
+    bdm.grid_build(pop.soa, mech_p(), pop.ws)
+    info, key, order, start = bdm.grid_export(pop.ws)
+    assert info["valid"] == 1 and info["flags"] == 0
+    ref_info, rk, ro, rs = orc.grid(s["x"], s["y"], s["z"], s["d"])
+    if n == 0:
+        assert info["nboxes"] == 0 and start.tolist() == [0]
+        return
+    assert info["b"] == ref_info["b"]
+    assert info["cmin"] == tuple(ref_info["cmin"]) and info["dims"] == tuple(ref_info["dims"])
+    assert np.array_equal(key, rk)
+    assert np.array_equal(order, ro)
+    assert np.array_equal(start, rs)
+
+
+def test_grid_periodic_bit_exact():
+    say("case: grid periodic")
+    s = inputs.sir_uniform(20000, 100.0, seed=1)
+    pop = population(s, spheres=False, state=True, max_boxes=30 ** 3)
+    p = bdm.params(box=4.0, periodic=1, L=100.0)
+    bdm.grid_build(pop.soa, p, pop.ws)
+    info, key, order, start = bdm.grid_export(pop.ws)
+    ref_info, rk, ro, rs = orc.grid(s["x"], s["y"], s["z"], None, box=4.0, periodic=True, L=100.0)
+    assert info["dims"] == (25, 25, 25)
+    assert np.array_equal(key, rk) and np.array_equal(order, ro) and np.array_equal(start, rs)
+
+
+def test_grid_explicit_box_and_flags():
+    say("case: grid flags")
+    s = inputs.uniform_cube(1000, 100.0, seed=9)
+    pop = population(s, max_boxes=1 << 16)
+    bdm.grid_build(pop.soa, mech_p(box=20.0), pop.ws)
+    info, key, order, start = bdm.grid_export(pop.ws)
+    _, rk, ro, rs = orc.grid(s["x"], s["y"], s["z"], s["d"], box=20.0)
+    assert np.array_equal(key, rk) and np.array_equal(order, ro) and np.array_equal(start, rs)
+    # box below the largest diameter: flagged, grid invalid, a following step moves nothing
+    bdm.grid_build(pop.soa, mech_p(box=5.0), pop.ws)
+    assert bdm.status(pop.ws, clear=True) & bdm.FLAG_BOXSMALL
+    assert bdm.grid_info(pop.ws)["valid"] == 0
+    x0 = pop.t["x"][:1000].clone()
+    bdm.mech_step(pop.soa, mech_p(box=5.0), pop.ws)
+    assert torch.equal(pop.t["x"][:1000], x0)
+    # too many boxes for the workspace
+    small = population(s, max_boxes=10)
+    bdm.grid_build(small.soa, mech_p(), small.ws)
+    assert bdm.status(small.ws) & bdm.FLAG_BOXES
+    # non-finite input
+    s2 = {k: v.copy() for k, v in s.items()}
+    s2["y"][17] = np.inf
+    bad = population(s2)
+    bdm.grid_build(bad.soa, mech_p(), bad.ws)
+    assert bdm.status(bad.ws) & bdm.FLAG_NONFINITE
+
+
+def test_argument_validation():
+    say("case: validation")
+    pop = population(inputs.uniform_cube(100, 50.0, seed=1))
+    for kw in (dict(dt=0.0), dict(max_disp=-1.0), dict(force_bits=16), dict(periodic=1)):
+        with pytest.raises(bdm.BdmError) as e:
+            bdm.mech_step(pop.soa, mech_p(**kw), pop.ws)
+        assert e.value.rc == bdm.EINVAL
+    ws = bdm.Workspace(pop.ws.ptr, 100, pop.ws.capacity, pop.ws.max_boxes)
+    with pytest.raises(bdm.BdmError) as e:
+        bdm.grid_build(pop.soa, mech_p(), ws)
+    assert e.value.rc == bdm.ENOWS
+
+
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("case,bits", [("c0", 64), ("c0", 32), ("faces", 64), ("clustered", 64),
+                                       ("clustered", 32)])
+def test_contacts_bit_exact(case, bits):
+    say(f"case: contacts {case} bits={bits}")
+    s = grid_cases()[case]
+    n = len(s["x"])
+    pop = population(s)
+    bdm.grid_build(pop.soa, mech_p(), pop.ws)
+    counts, offsets, ids = bdm.contacts(pop.ws, mech_p(force_bits=bits), n)
+    _, _, order, _ = bdm.grid_export(pop.ws)
+    rc, ro, ri = orc.contacts(s["x"], s["y"], s["z"], s["d"], force_bits=bits)
+    for slot in range(n):
+        a = order[slot]
+        got = ids[offsets[slot]: offsets[slot] + counts[slot]]
+        exp = ri[ro[a]: ro[a] + rc[a]]
+        assert np.array_equal(got, exp), (slot, a)
+
+
+def test_sir_contacts_bit_exact():
+    say("case: sir contacts")
+    s = inputs.sir_uniform(20000, 100.0, seed=2)
+    pop = population(s, spheres=False, state=True, max_boxes=40 ** 3)
+    p = bdm.params(box=4.0, periodic=1, L=100.0, r_inf=3.0)
+    bdm.grid_build(pop.soa, p, pop.ws)
+    counts, offsets, ids = bdm.contacts(pop.ws, p, 20000)
+    _, _, order, _ = bdm.grid_export(pop.ws)
+    rc, ro, ri = orc.contacts(s["x"], s["y"], s["z"], None, box=4.0, periodic=True, L=100.0,
+                              radius=3.0)
+    for slot in range(20000):
+        a = order[slot]
+        assert sorted(ids[offsets[slot]: offsets[slot] + counts[slot]].tolist()) == \
+            sorted(ri[ro[a]: ro[a] + rc[a]].tolist())
+
+
+# ---------------------------------------------------------------------------------------------
+def pair_abs_sum(s, force_bits=64):
+    """sum_j |F_ij| per agent (oracle pair law) for the force tolerance."""
+    counts, offsets, ids = orc.contacts(s["x"], s["y"], s["z"], s["d"], force_bits=force_bits)
+    out = np.zeros(len(s["x"]))
+    for i in range(len(s["x"])):
+        for j in ids[offsets[i]: offsets[i] + counts[i]]:
+            _, f = orc.pair_force((s["x"][i], s["y"][i], s["z"][i]), s["d"][i],
+                                  (s["x"][j], s["y"][j], s["z"][j]), s["d"][j], 2.0, 1.0, force_bits)
+            out[i] += np.linalg.norm(f)
+    return out
+
+
+def compare_state(got, ref, L, what, fabs=None, fref=None):
+    n = len(ref["x"])
+    scale = L
+    if n:
+        scale = max(L, float(np.max(np.abs(np.concatenate([ref["x"], ref["y"], ref["z"]])))))
+    bit = np.ones(n, dtype=bool)
+    for k in ("x", "y", "z"):
+        err = np.abs(got[k] - ref[k])
+        assert np.all(err <= TOL * scale), (what, k, float(err.max()))
+        bit &= got[k].view(np.uint64) == ref[k].view(np.uint64)
+    if fref is not None:
+        for k, rk in zip(("fx", "fy", "fz"), fref):
+            err = np.abs(got[k] - rk)
+            assert np.all(err <= TOL * np.maximum(fabs, 1e-300)), (what, k, float(err.max()))
+            bit &= got[k].view(np.uint64) == rk.view(np.uint64)
+    say(f"{what}: {int(bit.sum())}/{n} agents bit-equal")
+    return bit
+
+
+@pytest.mark.parametrize("case,bits", [("c0", 64), ("ragged", 64), ("clustered", 64), ("faces", 64),
+                                       ("c0", 32), ("clustered", 32), ("single", 64), ("empty", 64)])
+def test_mech_step_lockstep(case, bits):
+    say(f"case: mech lockstep {case} bits={bits}")
+    s = grid_cases()[case]
+    n = len(s["x"])
+    pop = population(s)
+    p = mech_p(force_bits=bits)
+    bdm.grid_build(pop.soa, p, pop.ws)
+    bdm.mech_step(pop.soa, p, pop.ws)
+    assert bdm.status(pop.ws) == 0
+    got = pop.read()
+    ref = {k: v.copy() for k, v in s.items()}
+    fx, fy, fz, nc, fl = orc.mech_step(ref, force_bits=bits)
+    fabs = pair_abs_sum(s, bits) if n else np.zeros(0)
+    bit = compare_state(got, ref, 200.0, f"mech {case}/{bits}", fabs, (fx, fy, fz))
+    assert bit.all(), "expected bit equality with the oracle (same operations, same order)"
+
+
+def test_mech_clamp_and_gate_regimes():
+    say("case: mech clamp/gate")
+    s = inputs.uniform_cube(3000, 200.0, seed=21)  # with dt 0.5 all three regimes occur
+    pop = population(s)
+    p = mech_p(dt=0.5, max_disp=0.7)
+    bdm.grid_build(pop.soa, p, pop.ws)
+    bdm.mech_step(pop.soa, p, pop.ws)
+    got = pop.read()
+    ref = {k: v.copy() for k, v in s.items()}
+    fx, fy, fz, nc, fl = orc.mech_step(ref, dt=0.5, max_disp=0.7)
+    assert (fl == 2).sum() > 100 and (fl == 1).sum() > 100 and (fl == 0).sum() > 100
+    bit = compare_state(got, ref, 200.0, "clamp/gate", pair_abs_sum(s), (fx, fy, fz))
+    assert bit.all()
+
+
+def test_c0_ten_steps_fp64():
+    """4096 agents in a 200 um cube, d in [10, 15), adh 0.4, k 2, gamma 1, dt 0.01, 10 steps."""
+    say("case: C0 trajectory")
+    n = 4096
+    pop = bdm.Population(n, 1 << 14)
+    bdm.generate(pop.soa, bdm.gen(bdm.GEN_CUBE, n, 200.0, 10.0, 15.0, 0.4, seed=0))
+    ref = orc.generate_cube(n, 0, 200.0, 10.0, 15.0, 0.4)
+    p = mech_p()
+    for step in range(10):
+        bdm.sim_step(pop.soa, bdm.MODEL_MECH, p, step, pop.ws)
+        fx, fy, fz, nc, fl = orc.mech_step(ref)
+    assert bdm.status(pop.ws) == 0
+    got = pop.read()
+    bit = compare_state(got, ref, 200.0, "C0 10 steps")
+    assert bit.all()
+
+
+def test_fp32_force_error_report():
+    say("case: FP32 vs FP64 oracle")
+    n = 4096
+    pop = bdm.Population(n, 1 << 14)
+    bdm.generate(pop.soa, bdm.gen(bdm.GEN_CUBE, n, 200.0, 10.0, 15.0, 0.4, seed=0))
+    ref64 = orc.generate_cube(n, 0, 200.0, 10.0, 15.0, 0.4)
+    ref32 = {k: v.copy() for k, v in ref64.items()}
+    p = mech_p(force_bits=32)
+    for step in range(10):
+        bdm.sim_step(pop.soa, bdm.MODEL_MECH, p, step, pop.ws)
+        orc.mech_step(ref64)
+        orc.mech_step(ref32, force_bits=32)
+    got = pop.read()
+    compare_state(got, ref32, 200.0, "FP32 path vs FP32 oracle")
+    err = max(float(np.abs(got[k] - ref64[k]).max()) for k in ("x", "y", "z"))
+    say(f"FP32-force max position error vs FP64 oracle after 10 steps: {err:.3e} um "
+        f"({err / 200.0:.3e} of L)")
+    assert err < 1e-3
+
+
+# ---------------------------------------------------------------------------------------------
+def test_sir_states_bit_exact():
+    say("case: SIR dense")
+    n, L = 200000, 200.0  # about 4 contacts per agent at radius 2
+    pop = bdm.Population(n, 110 ** 3, spheres=False, with_state=True)
+    bdm.generate(pop.soa, bdm.gen(bdm.GEN_SIR, n, L, n_infected=n // 100, seed=3))
+    ref = orc.generate_sir(n, 3, L, n // 100)
+    p = bdm.params(box=2.0, periodic=1, L=L, r_inf=2.0, p_inf=0.3, p_rec=0.01, walk=1.0, seed=3)
+    op = orc.sir_params(L, 2.0, 2.0, 0.3, 0.01, 1.0, 3)
+    for step in range(12):
+        bdm.sim_step(pop.soa, bdm.MODEL_SIR, p, step, pop.ws)
+        rc = orc.sir_step(ref, op, step)
+        assert bdm.sir_counts(pop.ws) == rc.tolist(), step
+    got = pop.read()
+    assert np.array_equal(got["state"], ref["state"])
+    for k in ("x", "y", "z"):
+        assert np.array_equal(got[k].view(np.uint64), ref[k].view(np.uint64))
+    assert bdm.status(pop.ws) == 0
+
+
+def test_spheroid_growth_division():
+    say("case: spheroid")
+    n0, cap = 1000, 40000
+    h = 0.5 ** (1 / 3)
+    g = 1.05 ** (1 / 3)
+    pop = bdm.Population(cap, 1 << 18)
+    bdm.generate(pop.soa, bdm.gen(bdm.GEN_BALL, n0, 28.0, 14.0 * h, 14.0, 0.4, seed=2))
+    st = orc.SpheroidState(orc.generate_ball(n0, 2, 28.0, 14.0 * h, 14.0, 0.4), cap)
+    p = bdm.params(grow=g, div_d=14.0, half_cbrt=h, seed=2)
+    op = orc.spheroid_params(g, 14.0, h, 2)
+    for step in range(25):
+        bdm.sim_step(pop.soa, bdm.MODEL_SPHEROID, p, step, pop.ws)
+        st.step(op, step)
+        assert pop.n == int(st.n[0]), step
+    got = pop.read()
+    ref = {k: st.view(k) for k in ("x", "y", "z", "d")}
+    assert np.array_equal(got["diam"].view(np.uint64), ref["d"].view(np.uint64))
+    bit = compare_state(got, ref, 100.0, "spheroid 25 steps")
+    assert bit.all()
+    assert bdm.status(pop.ws) == 0
+
+
+def test_spheroid_capacity_overflow():
+    say("case: spheroid overflow")
+    n = 64
+    s = dict(x=np.arange(n) * 30.0, y=np.zeros(n), z=np.zeros(n), d=np.full(n, 13.99),
+             adh=np.full(n, 0.4))
+    pop = population(s, capacity=80)
+    p = bdm.params(grow=1.05 ** (1 / 3), div_d=14.0, half_cbrt=0.5 ** (1 / 3), seed=1)
+    bdm.sim_step(pop.soa, bdm.MODEL_SPHEROID, p, 0, pop.ws)
+    assert pop.n == 80
+    assert bdm.status(pop.ws) & bdm.FLAG_CAPACITY
+    st = orc.SpheroidState(s, 80)
+    st.step(orc.spheroid_params(1.05 ** (1 / 3), 14.0, 0.5 ** (1 / 3), 1), 0)
+    got = pop.read()
+    assert np.array_equal(got["diam"], st.view("d"))
