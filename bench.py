@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Throughput of the mechanical hot path on one MI355X.
+
+Workload: 2^24 spheres uniform in a 3200 um cube (the density of 4096 agents in a 200 um cube),
+diameters uniform in [8, 12) um, adherence 0.4, k = 2, gamma = 1, dt = 0.01, clamp 3 um, box
+edge = largest diameter, grid rebuilt every step.  One timed step = one full pass of the hot
+path over all agents: grid build (bounds, key/histogram, scan, scatter, canonical order) then
+the mechanical step (27-box gather, pair force, gate, clamp, integrate), in binary64.
+
+Prints ONE JSON line: agent-updates/s of the whole step (value), per-phase times, the
+dominant kernel's roofline (algorithmic bytes / measured kernel time against 8 TB/s), the same
+run with binary32 pair forces and its position difference, and the single-thread CPU oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+N_DEFAULT = 1 << 24
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=N_DEFAULT, help="agents (default 2^24)")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the binary32-force run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 22,
+                    help="agents in the oracle's bounded sample (same density)")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_mech_fp64_n16m.json"),
+                    help="HBM bytes per mech_step launch from rocprofv3 counters (optional)")
+    return ap.parse_args()
+
+
+def cube_edge(n):
+    return 200.0 * (n / 4096.0) ** (1.0 / 3.0)
+
+
+def run_variant(bdm, torch, n, L, steps, warmup, force_bits):
+    """Generate, warm up, then time `steps` full steps.  Returns timings and the population."""
+    b_guess = 11.9
+    max_boxes = bdm.box_count_hint(L, b_guess, margin=3)
+    pop = bdm.Population(n, max_boxes)
+    bdm.generate(pop.soa, bdm.gen(bdm.GEN_CUBE, n, L, 8.0, 12.0, 0.4, seed=0))
+    p = bdm.params(k=2.0, gamma=1.0, dt=0.01, max_disp=3.0, box=0.0, force_bits=force_bits)
+    stream = torch.cuda.current_stream()
+    for step in range(warmup):
+        bdm.grid_build(pop.soa, p, pop.ws)
+        bdm.mech_step(pop.soa, p, pop.ws)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for step in range(steps):
+        e0, e1, e2 = ev[step]
+        e0.record(stream)
+        bdm.grid_build(pop.soa, p, pop.ws)
+        e1.record(stream)
+        bdm.mech_step(pop.soa, p, pop.ws)
+        e2.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    grid_ms = sum(a.elapsed_time(b) for a, b, _ in ev) / steps
+    mech_ms = sum(b.elapsed_time(c) for _, b, c in ev) / steps
+    flags = bdm.status(pop.ws)
+    info = bdm.grid_info(pop.ws)
+    return dict(wall=wall, grid_ms=grid_ms, mech_ms=mech_ms, flags=flags, info=info, pop=pop)
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def source_digest(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+MECH_SOURCES = ("paper_2006_06775_amd/csrc/k_mech.hip", "paper_2006_06775_amd/csrc/common.hpp")
+
+
+def measured_traffic(path, n):
+    """HBM bytes per mech_step launch from the rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None
+    when there is none for this size or the kernel source changed since it was taken."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("n") != n or t.get("source_digest") != source_digest(MECH_SOURCES):
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(n_sample):
+    """Single-thread oracle: one mechanical step (grid + forces + move) of n_sample agents at
+    the workload's density."""
+    from oracle import oracle as orc
+    L = cube_edge(n_sample)
+    s = orc.generate_cube(n_sample, 0, L, 8.0, 12.0, 0.4)
+    t0 = time.perf_counter()
+    orc.mech_step(s, k=2.0, gamma=1.0, dt=0.01, max_disp=3.0)
+    dt = time.perf_counter() - t0
+    return dict(value=n_sample / dt, unit="agent-updates/s", cores=1, kind="oracle",
+                sample=f"one mechanical step (grid build + forces + move, binary64) of "
+                       f"{n_sample} agents at the benchmark's density (cube edge {L:.1f} um), "
+                       f"single thread, {dt:.1f} s")
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2006_06775_amd import bdm
+
+    torch.cuda.set_device(0)
+    n, L = args.n, cube_edge(args.n)
+    r64 = run_variant(bdm, torch, n, L, args.steps, args.warmup, 64)
+    if r64["flags"]:
+        print(f"device status flags {r64['flags']:#x}", file=sys.stderr)
+        sys.exit(1)
+    ms_step = r64["wall"] * 1e3 / args.steps
+    value = n * args.steps / r64["wall"]
+    nboxes = r64["info"]["nboxes"]
+
+    # dominant-kernel roofline: the mechanical step's algorithmic traffic per agent-update is
+    # read x, y, z, d, adh (40 B) + box starts (4 (B + 1) / N) + write forces (24) and
+    # positions (24)
+    mech_bytes = n * (40.0 + 24.0 + 24.0) + 4.0 * (nboxes + 1)
+    mech_gbps = mech_bytes / (r64["mech_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(args.traffic_json, n)
+    roofline = dict(bound="hbm", kernel="k_mech<binary64>", achieved=round(mech_gbps, 1),
+                    peak=HBM_PEAK_GBPS, unit="GB/s", frac=round(mech_gbps / HBM_PEAK_GBPS, 4),
+                    traffic=traffic, algorithmic_bytes_per_launch=int(mech_bytes),
+                    launch_ms=round(r64["mech_ms"], 4))
+    fp32 = None
+    if not args.no_fp32:
+        r32 = run_variant(bdm, torch, n, L, args.steps, args.warmup, 32)
+        # position difference vs the binary64 path after the same steps (the binary64 path is
+        # bit-identical to the oracle in the parity tests)
+        a, b = r32["pop"].read(("x", "y", "z")), r64["pop"].read(("x", "y", "z"))
+        err = max(float(abs(a[k] - b[k]).max()) for k in ("x", "y", "z"))
+        fp32 = dict(value=n * args.steps / r32["wall"], ms_per_step=r32["wall"] * 1e3 / args.steps,
+                    grid_ms=round(r32["grid_ms"], 4), mech_ms=round(r32["mech_ms"], 4),
+                    max_pos_diff_vs_fp64_um=err, max_pos_diff_rel_L=err / L,
+                    steps_compared=args.warmup + args.steps, flags=r32["flags"])
+        del r32, a, b
+    del r64["pop"]
+    torch.cuda.empty_cache()
+
+    copy_gbps = copy_bandwidth(torch)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_sample)
+    out = {
+        "metric": "agent-updates/sec in mech_step",
+        "value": value,
+        "unit": "agent-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"mechanics, {n} spheres in a {L:.0f} um cube, d in [8,12) um, "
+                               f"grid rebuilt every step", "n_agents": n, "cube_edge_um": L,
+                   "boxes": nboxes, "box_edge_um": r64["info"]["b"], "force_precision": "fp64",
+                   "step": "grid_build + mech_step"},
+        "phases_ms": {"grid_build": round(r64["grid_ms"], 4), "mech_step": round(r64["mech_ms"], 4)},
+        "mech_step_only_agent_updates_per_s": n / (r64["mech_ms"] * 1e-3),
+        "roofline": roofline,
+        "fp32_forces": fp32,
+        "copy_kernel_GBps": round(copy_gbps, 1),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
