@@ -54,6 +54,10 @@ extern "C" {
 #define BDM_MODEL_SPHEROID 1  /* growth + division, then grid build + mechanical step */
 #define BDM_MODEL_SIR 2       /* periodic grid build + SIR infection/recovery/movement */
 
+/* ---- batched form ------------------------------------------------------------------------ */
+#define BDM_MAX_SLOTS 4096      /* slots of one batch */
+#define BDM_SLOT_ALIGN 1024     /* a slot's first agent index is a multiple of this */
+
 /* ---- generator kinds for bdm_generate ---------------------------------------------------- */
 #define BDM_GEN_CUBE 0  /* uniform in [0, L)^3, diameter uniform in [dlo, dhi) */
 #define BDM_GEN_BALL 1  /* uniform in the ball of radius L about the origin (rejection) */
@@ -119,6 +123,20 @@ typedef struct bdm_grid_desc {
     int32_t valid;         /* 1 when the last build succeeded */
     uint32_t flags;        /* sticky BDM_FLAG_* bits */
 } bdm_grid_desc;
+
+/* A batch: many independent mechanical simulations packed into one population.  Slot s owns
+ * the agent indices [agent_off, agent_off + capacity) of the packed arrays (agent_off a
+ * multiple of BDM_SLOT_ALIGN) and the histogram entries [box_off, box_off + max_boxes); its live
+ * count is soa->n[s] (soa->n points to `slots` int64 counts).  Each slot has its own grid, box
+ * edge and parameters, so every agent's arithmetic is the same as in a plain call on that slot
+ * alone.  The caller keeps slot ranges disjoint. */
+typedef struct bdm_batch {
+    void *ptr;             /* device workspace, 256-byte aligned */
+    size_t bytes;
+    int64_t capacity;      /* length of the packed agent arrays */
+    int64_t max_boxes;     /* length of the packed histogram */
+    int32_t slots;         /* number of slots (1..BDM_MAX_SLOTS) */
+} bdm_batch;
 
 /* Size in bytes of the workspace for `capacity` agents and `max_boxes` boxes; 0 when either is
  * negative or the size overflows. */
@@ -207,6 +225,41 @@ int bdm_grid_export(const bdm_workspace *ws, uint32_t *key, uint32_t *order, uin
  * prefix of counts, int64) and ids[sum(counts)] to get the agent ids.  Errors: BDM_EINVAL. */
 int bdm_contacts(const bdm_workspace *ws, const bdm_params *params, uint32_t *counts,
                  const int64_t *offsets, uint32_t *ids, void *stream);
+
+/* ---- batched form --------------------------------------------------------------------------
+ * Callers: many independent simulations of uneven sizes stepped together (one launch per
+ * phase for all of them, capturable in a graph).  The per-slot work is the plain mechanical
+ * step (bdm_sim_step with BDM_MODEL_MECH) [paper Sec. 2.1 grid, Sec. 3.4 force model]. */
+
+/* Workspace bytes of a batch; 0 when an argument is out of range. */
+size_t bdm_batch_workspace_bytes(int64_t capacity, int64_t max_boxes, int32_t slots);
+
+/* Prepare a batch workspace: every slot idle, histogram and grids cleared.  Errors: BDM_ENOWS,
+ * BDM_EINVAL, BDM_EHIP, BDM_ENODEV. */
+int bdm_batch_init(const bdm_batch *b, void *stream);
+
+/* Make slot `slot` run `steps` mechanical steps of the agents in [agent_off, agent_off +
+ * capacity) with its own histogram range and parameters (k, gamma, dt, max_disp, box,
+ * force_bits).  Asynchronous on `stream` (kernel writes, no host copy), so it may sit between
+ * graph replays.  The agents themselves are written by the caller (e.g. bdm_generate on a view
+ * of the slot's range with n = &soa->n[slot]).  Errors: BDM_EINVAL (range, alignment, params). */
+int bdm_batch_set_slot(const bdm_batch *b, int32_t slot, int64_t agent_off, int64_t capacity,
+                       int64_t box_off, int64_t max_boxes, int64_t steps, const bdm_params *p,
+                       void *stream);
+
+/* Idle slot `slot` and detach its agent range [agent_off, agent_off + capacity) from it. */
+int bdm_batch_clear_slot(const bdm_batch *b, int32_t slot, int64_t agent_off, int64_t capacity,
+                         void *stream);
+
+/* One mechanical step (grid build + mechanics) of every slot with steps left, then each of
+ * those slots' step count drops by one.  Agents of slot s stay in its range, box-sorted.  Fixed
+ * launch geometry: the same call sequence is replayable as a graph.  Device conditions set the
+ * slot's status bits (bdm_batch_slot_status).  Errors: BDM_EINVAL, BDM_ENOWS. */
+int bdm_batch_step(const bdm_soa *packed, const bdm_batch *b, void *stream);
+
+/* Status bits and remaining steps of one slot (host).  Synchronises the stream. */
+int bdm_batch_slot_status(const bdm_batch *b, int32_t slot, uint32_t *flags, int64_t *steps_left,
+                          void *stream);
 
 /* Test hook: element-wise IEEE operations as the kernels compute them, for bitwise checks
  * against the host: out_sqrt[i] = sqrt(a[i]), out_div[i] = a[i] / b[i] in binary64;

@@ -28,9 +28,11 @@ GEN_CUBE, GEN_BALL, GEN_SIR = 0, 1, 2
 SYMBOLS = (
     "bdm_workspace_bytes", "bdm_workspace_init", "bdm_generate", "bdm_grid_build",
     "bdm_mech_step", "bdm_sim_step", "bdm_read_agents", "bdm_status", "bdm_sir_counts",
-    "bdm_grid_info", "bdm_grid_export", "bdm_contacts", "bdm_fp_probe", "bdm_strerror",
-    "bdm_last_error",
+    "bdm_grid_info", "bdm_grid_export", "bdm_contacts", "bdm_batch_workspace_bytes",
+    "bdm_batch_init", "bdm_batch_set_slot", "bdm_batch_clear_slot", "bdm_batch_step",
+    "bdm_batch_slot_status", "bdm_fp_probe", "bdm_strerror", "bdm_last_error",
 )
+MAX_SLOTS, SLOT_ALIGN = 4096, 1024
 
 
 class BdmError(RuntimeError):
@@ -70,6 +72,11 @@ class Workspace(C.Structure):
                 ("max_boxes", C.c_int64)]
 
 
+class BatchRec(C.Structure):
+    _fields_ = [("ptr", C.c_void_p), ("bytes", C.c_size_t), ("capacity", C.c_int64),
+                ("max_boxes", C.c_int64), ("slots", C.c_int32)]
+
+
 class GridDesc(C.Structure):
     _fields_ = [("b", C.c_double), ("cmin", C.c_int32 * 3), ("dims", C.c_int32 * 3),
                 ("nboxes", C.c_int64), ("n", C.c_int64), ("valid", C.c_int32),
@@ -95,6 +102,13 @@ def _load():
         "bdm_grid_export": ([P, P, P, P, P], C.c_int),
         "bdm_contacts": ([P, P, P, P, P, P], C.c_int),
         "bdm_fp_probe": ([P, P, C.c_int64, P, P, P, P, P], C.c_int),
+        "bdm_batch_workspace_bytes": ([C.c_int64, C.c_int64, C.c_int32], C.c_size_t),
+        "bdm_batch_init": ([P, P], C.c_int),
+        "bdm_batch_set_slot": ([P, C.c_int32, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
+                                C.c_int64, P, P], C.c_int),
+        "bdm_batch_clear_slot": ([P, C.c_int32, C.c_int64, C.c_int64, P], C.c_int),
+        "bdm_batch_step": ([P, P, P], C.c_int),
+        "bdm_batch_slot_status": ([P, C.c_int32, P, P, P], C.c_int),
         "bdm_strerror": ([C.c_int], C.c_char_p),
         "bdm_last_error": ([], C.c_char_p),
     }
@@ -303,6 +317,92 @@ def fp_probe(a: torch.Tensor, b: torch.Tensor, stream=None):
     _check(_lib.bdm_fp_probe(_ptr(a), _ptr(b), n, *(_ptr(o) for o in outs), _stream(stream)),
            "fp_probe")
     return outs
+
+
+# ---------------------------------------------------------------------------------------------
+# Batched form
+# ---------------------------------------------------------------------------------------------
+def batch_workspace_bytes(capacity: int, max_boxes: int, slots: int) -> int:
+    return int(_lib.bdm_batch_workspace_bytes(capacity, max_boxes, slots))
+
+
+def batch_init(b: BatchRec, stream=None):
+    _check(_lib.bdm_batch_init(_ref(b), _stream(stream)), "batch_init")
+
+
+def batch_set_slot(b: BatchRec, slot: int, agent_off: int, capacity: int, box_off: int,
+                   max_boxes: int, steps: int, p: Params, stream=None):
+    _check(_lib.bdm_batch_set_slot(_ref(b), slot, agent_off, capacity, box_off, max_boxes, steps,
+                                   _ref(p), _stream(stream)), "batch_set_slot")
+
+
+def batch_clear_slot(b: BatchRec, slot: int, agent_off: int, capacity: int, stream=None):
+    _check(_lib.bdm_batch_clear_slot(_ref(b), slot, agent_off, capacity, _stream(stream)),
+           "batch_clear_slot")
+
+
+def batch_step(soa: Soa, b: BatchRec, stream=None):
+    _check(_lib.bdm_batch_step(_ref(soa), _ref(b), _stream(stream)), "batch_step")
+
+
+def batch_slot_status(b: BatchRec, slot: int, stream=None):
+    f = C.c_uint32(0)
+    left = C.c_int64(0)
+    _check(_lib.bdm_batch_slot_status(_ref(b), slot, C.byref(f), C.byref(left), _stream(stream)),
+           "batch_slot_status")
+    return int(f.value), int(left.value)
+
+
+class Batch:
+    """Packed population of `slots` independent mechanical simulations: caller-owned arrays of
+    `capacity` agents, per-slot live counts, and the batch workspace (torch allocations)."""
+
+    FIELDS = ("x", "y", "z", "diam", "adh", "fx", "fy", "fz")
+
+    def __init__(self, capacity: int, max_boxes: int, slots: int, device: str = "cuda"):
+        self.capacity, self.max_boxes, self.slots = int(capacity), int(max_boxes), int(slots)
+        self.t = {k: torch.zeros(self.capacity, dtype=torch.float64, device=device)
+                  for k in self.FIELDS}
+        self.t["id"] = torch.zeros(self.capacity, dtype=torch.int32, device=device)
+        self.n = torch.zeros(self.slots, dtype=torch.int64, device=device)
+        nbytes = batch_workspace_bytes(self.capacity, self.max_boxes, self.slots)
+        if nbytes == 0:
+            raise BdmError(ENOWS, "batch_workspace_bytes",
+                           f"capacity={capacity} max_boxes={max_boxes} slots={slots}")
+        self.ws_tensor = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.rec = BatchRec(self.ws_tensor.data_ptr(), nbytes, self.capacity, self.max_boxes,
+                            self.slots)
+        self.soa = Soa(self.capacity, _ptr(self.n), *(_ptr(self.t[k]) for k in self.FIELDS),
+                       _ptr(self.t["id"]), None)
+        batch_init(self.rec)
+
+    def view(self, slot: int, agent_off: int, capacity: int) -> Soa:
+        """The slot's agent range as a plain population (n points at the slot's count)."""
+        def at(k, size):
+            return self.t[k].data_ptr() + agent_off * size
+        return Soa(capacity, self.n.data_ptr() + 8 * slot, *(at(k, 8) for k in self.FIELDS),
+                   at("id", 4), None)
+
+    def set_slot(self, slot, agent_off, capacity, box_off, max_boxes, steps, p: Params, stream=None):
+        batch_set_slot(self.rec, slot, agent_off, capacity, box_off, max_boxes, steps, p, stream)
+
+    def clear_slot(self, slot, agent_off, capacity, stream=None):
+        batch_clear_slot(self.rec, slot, agent_off, capacity, stream)
+
+    def step(self, stream=None):
+        batch_step(self.soa, self.rec, stream)
+
+    def slot_status(self, slot, stream=None):
+        return batch_slot_status(self.rec, slot, stream)
+
+    def read_slot(self, slot: int, agent_off: int, capacity: int, keys=("x", "y", "z", "fx", "fy", "fz")):
+        """The slot's agents in id order, as host numpy arrays."""
+        v = self.view(slot, agent_off, capacity)
+        n = int(self.n[slot].item())
+        dev = {k: torch.empty(n, dtype=torch.float64, device=self.n.device) for k in keys}
+        read_agents(v, dev.get("x"), dev.get("y"), dev.get("z"), dev.get("diam"), dev.get("fx"),
+                    dev.get("fy"), dev.get("fz"), None)
+        return {k: t.cpu().numpy() for k, t in dev.items()}
 
 
 def box_count_hint(L: float, b: float, margin: int = 2) -> int:

@@ -2,6 +2,7 @@
 //
 // Host side only: synchronous argument validation, workspace layout, kernel launches on the
 // caller's stream, error codes.  No allocation, no stream creation, no exceptions across the ABI.
+// A plain call is a batch of one slot whose record travels by value in the kernel arguments.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -37,29 +38,46 @@ inline hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 
 bool is_fin(double v) { return std::isfinite(v); }
 
-// Resolve and check a workspace handle.
-int get_ws(const bdm_workspace *ws, bdm::Ws *out) {
-    if (!ws || !ws->ptr) return fail(BDM_ENOWS, "workspace is NULL");
-    if (reinterpret_cast<uintptr_t>(ws->ptr) % 256 != 0)
-        return fail(BDM_ENOWS, "workspace pointer is not 256-byte aligned");
-    bdm::WsLayout lay;
-    if (!bdm::ws_layout(ws->capacity, ws->max_boxes, &lay))
-        return fail(BDM_ENOWS, "workspace capacity %lld / max_boxes %lld out of range",
-                    (long long)ws->capacity, (long long)ws->max_boxes);
-    if (ws->bytes < lay.total)
-        return fail(BDM_ENOWS, "workspace has %zu bytes, needs %zu", ws->bytes, lay.total);
-    *out = bdm::ws_view(ws->ptr, lay);
+int check_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(BDM_ENODEV, "no HIP device");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(BDM_ENODEV, "no HIP device properties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(BDM_ENODEV, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
     return BDM_OK;
 }
 
-int check_soa(const bdm_soa *s, const bdm::Ws &w, bool need_sphere, bool need_state) {
+int view(void *ptr, size_t bytes, int64_t capacity, int64_t max_boxes, int64_t slots, bdm::Ws *out) {
+    if (!ptr) return fail(BDM_ENOWS, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ptr) % 256 != 0) return fail(BDM_ENOWS, "workspace pointer is not 256-byte aligned");
+    bdm::WsLayout lay;
+    if (!bdm::ws_layout(capacity, max_boxes, slots, &lay))
+        return fail(BDM_ENOWS, "workspace capacity %lld / max_boxes %lld / slots %lld out of range",
+                    (long long)capacity, (long long)max_boxes, (long long)slots);
+    if (bytes < lay.total) return fail(BDM_ENOWS, "workspace has %zu bytes, needs %zu", bytes, lay.total);
+    *out = bdm::ws_view(ptr, lay);
+    return BDM_OK;
+}
+
+int get_ws(const bdm_workspace *ws, bdm::Ws *out) {
+    if (!ws) return fail(BDM_ENOWS, "workspace is NULL");
+    return view(ws->ptr, ws->bytes, ws->capacity, ws->max_boxes, 0, out);
+}
+
+int get_batch(const bdm_batch *b, bdm::Ws *out) {
+    if (!b) return fail(BDM_ENOWS, "batch is NULL");
+    if (b->slots < 1 || b->slots > BDM_MAX_SLOTS) return fail(BDM_EINVAL, "batch slots must be in [1, %d]", BDM_MAX_SLOTS);
+    return view(b->ptr, b->bytes, b->capacity, b->max_boxes, b->slots, out);
+}
+
+int check_soa(const bdm_soa *s, int64_t ws_capacity, bool need_sphere, bool need_state) {
     if (!s) return fail(BDM_EINVAL, "soa is NULL");
-    if (!s->n || !s->x || !s->y || !s->z || !s->id)
-        return fail(BDM_EINVAL, "soa needs n, x, y, z and id");
+    if (!s->n || !s->x || !s->y || !s->z || !s->id) return fail(BDM_EINVAL, "soa needs n, x, y, z and id");
     if (s->capacity < 0) return fail(BDM_EINVAL, "negative capacity");
-    if (s->capacity > w.lay.capacity)
-        return fail(BDM_ENOWS, "soa capacity %lld exceeds the workspace capacity %lld",
-                    (long long)s->capacity, (long long)w.lay.capacity);
+    if (s->capacity > ws_capacity)
+        return fail(BDM_ENOWS, "soa capacity %lld exceeds the workspace capacity %lld", (long long)s->capacity,
+                    (long long)ws_capacity);
     if (need_sphere && (!s->diam || !s->adh)) return fail(BDM_EINVAL, "soa needs diam and adh");
     if (need_state && !s->state) return fail(BDM_EINVAL, "soa needs state");
     return BDM_OK;
@@ -76,31 +94,62 @@ int check_mech_params(const bdm_params *p) {
     return BDM_OK;
 }
 
-int periodic_boxes(const bdm_params *p, const bdm::Ws &w, int32_t *nb) {
+int periodic_boxes(const bdm_params *p, int64_t max_boxes, int32_t *nb) {
     if (!(p->L > 0.0) || !is_fin(p->L)) return fail(BDM_EINVAL, "periodic L must be > 0");
     if (!(p->box > 0.0) || !is_fin(p->box)) return fail(BDM_EINVAL, "periodic grids need box > 0");
     double q = std::floor(p->L / p->box);
     if (q < 3.0) return fail(BDM_EINVAL, "periodic grid needs at least 3 boxes per axis");
-    if (q > 2097151.0 || q * q * q > double(w.lay.max_boxes))
-        return fail(BDM_ENOWS, "periodic grid of %.0f^3 boxes exceeds max_boxes %lld", q,
-                    (long long)w.lay.max_boxes);
+    if (q > 2097151.0 || q * q * q > double(max_boxes))
+        return fail(BDM_ENOWS, "periodic grid of %.0f^3 boxes exceeds max_boxes %lld", q, (long long)max_boxes);
     *nb = int32_t(q);
     return BDM_OK;
 }
 
-int do_grid_build(const bdm_soa *s, const bdm_params *p, bool periodic, const bdm::Ws &w,
-                  hipStream_t st) {
-    bdm::FinalizeArgs fa{};
-    fa.box = p->box;
-    fa.L = p->L;
-    fa.periodic = periodic ? 1 : 0;
-    fa.has_d = s->diam ? 1 : 0;
-    fa.max_boxes = w.lay.max_boxes;
+// Slot record of a plain call (or of one batch slot).
+bdm::SlotDev slot_record(const bdm_params *p, int64_t agent_off, int64_t capacity, int64_t box_off,
+                         int64_t max_boxes, int64_t steps, bool has_d) {
+    bdm::SlotDev r{};
+    r.agent_off = agent_off;
+    r.capacity = capacity;
+    r.box_off = box_off;
+    r.max_boxes = max_boxes;
+    r.steps_left = steps;
+    r.k = p->k;
+    r.gamma = p->gamma;
+    r.dt = p->dt;
+    r.max_disp = p->max_disp;
+    r.box = p->box;
+    r.L = p->L;
+    r.kf = float(p->k);
+    r.gf = float(p->gamma);
+    r.force_bits = p->force_bits;
+    r.periodic = p->periodic ? 1 : 0;
+    r.nb = 0;
+    r.has_d = has_d ? 1 : 0;
+    return r;
+}
+
+bdm::Slots plain_slots(const bdm::Ws &w, const bdm::SlotDev &rec) {
+    bdm::Slots sl{};
+    sl.table = nullptr;
+    sl.tilemap = nullptr;
+    sl.grids = w.grid;
+    sl.nslots = 1;
+    sl.one = rec;
+    return sl;
+}
+
+// Grid build of a plain call; `periodic` selects the SIR grid.
+int plain_grid(const bdm_soa *s, const bdm_params *p, bool periodic, const bdm::Ws &w, hipStream_t st,
+               bdm::SlotDev *rec_out) {
+    bdm::SlotDev rec = slot_record(p, 0, s->capacity, 0, w.lay.max_boxes, 1, s->diam != nullptr);
+    rec.periodic = periodic ? 1 : 0;
     if (periodic) {
-        int rc = periodic_boxes(p, w, &fa.nb);
+        int rc = periodic_boxes(p, w.lay.max_boxes, &rec.nb);
         if (rc) return rc;
     }
-    bdm::launch_grid_build(*s, fa, w, st);
+    bdm::launch_grid_build(*s, plain_slots(w, rec), s->capacity, w, st);
+    if (rec_out) *rec_out = rec;
     return hip_check("grid_build launch");
 }
 
@@ -114,17 +163,6 @@ bdm::Threshold threshold(double prob) {
     t.mode = 1;
     t.t = static_cast<uint64_t>(std::ldexp(prob, 64));  // exact scaling, truncation = floor
     return t;
-}
-
-bdm::MechArgs mech_args(const bdm_params *p) {
-    bdm::MechArgs a{};
-    a.k = p->k;
-    a.gamma = p->gamma;
-    a.dt = p->dt;
-    a.max_disp = p->max_disp;
-    a.kf = float(p->k);
-    a.gf = float(p->gamma);
-    return a;
 }
 
 int check_sir_params(const bdm_params *p) {
@@ -143,13 +181,20 @@ int check_spheroid_params(const bdm_params *p) {
     return BDM_OK;
 }
 
+int read_grid(const bdm::GridDev *src, bdm::GridDev *dst, hipStream_t st) {
+    if (hipMemcpyAsync(dst, src, sizeof *dst, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return hip_check("grid read");
+    return BDM_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 size_t bdm_workspace_bytes(int64_t capacity, int64_t max_boxes) {
     bdm::WsLayout lay;
-    if (!bdm::ws_layout(capacity, max_boxes, &lay)) return 0;
+    if (!bdm::ws_layout(capacity, max_boxes, 0, &lay)) return 0;
     return lay.total;
 }
 
@@ -158,12 +203,8 @@ int bdm_workspace_init(const bdm_workspace *ws, void *stream) {
     bdm::Ws w;
     int rc = get_ws(ws, &w);
     if (rc) return rc;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return fail(BDM_ENODEV, "no HIP device");
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(BDM_ENODEV, "no HIP device properties");
-    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-        return fail(BDM_ENODEV, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+    rc = check_device();
+    if (rc) return rc;
     bdm::launch_ws_init(w, as_stream(stream));
     return hip_check("workspace_init launch");
 }
@@ -172,7 +213,8 @@ int bdm_generate(const bdm_soa *soa, const bdm_gen *gen, void *stream) {
     g_last_error.clear();
     if (!soa || !gen) return fail(BDM_EINVAL, "soa and gen are required");
     if (!soa->n || !soa->x || !soa->y || !soa->z || !soa->id) return fail(BDM_EINVAL, "soa needs n, x, y, z, id");
-    if (gen->n < 0 || gen->n > soa->capacity) return fail(BDM_EINVAL, "gen n %lld outside [0, capacity]", (long long)gen->n);
+    if (gen->n < 0 || gen->n > soa->capacity)
+        return fail(BDM_EINVAL, "gen n %lld outside [0, capacity]", (long long)gen->n);
     if (gen->n > (int64_t(1) << 32) - 2) return fail(BDM_EINVAL, "at most 2^32 - 2 agents");
     if (gen->kind != BDM_GEN_CUBE && gen->kind != BDM_GEN_BALL && gen->kind != BDM_GEN_SIR)
         return fail(BDM_EINVAL, "unknown generator kind %d", gen->kind);
@@ -190,10 +232,10 @@ int bdm_grid_build(const bdm_soa *soa, const bdm_params *params, const bdm_works
     int rc = get_ws(ws, &w);
     if (rc) return rc;
     if (!params) return fail(BDM_EINVAL, "params is NULL");
-    rc = check_soa(soa, w, false, false);
+    rc = check_soa(soa, w.lay.capacity, false, false);
     if (rc) return rc;
     if (!is_fin(params->box)) return fail(BDM_EINVAL, "box must be finite");
-    return do_grid_build(soa, params, params->periodic != 0, w, as_stream(stream));
+    return plain_grid(soa, params, params->periodic != 0, w, as_stream(stream), nullptr);
 }
 
 int bdm_mech_step(const bdm_soa *soa, const bdm_params *params, const bdm_workspace *ws, void *stream) {
@@ -201,11 +243,12 @@ int bdm_mech_step(const bdm_soa *soa, const bdm_params *params, const bdm_worksp
     bdm::Ws w;
     int rc = get_ws(ws, &w);
     if (rc) return rc;
-    rc = check_soa(soa, w, true, false);
+    rc = check_soa(soa, w.lay.capacity, true, false);
     if (rc) return rc;
     rc = check_mech_params(params);
     if (rc) return rc;
-    bdm::launch_mech(*soa, mech_args(params), params->force_bits, w, as_stream(stream));
+    const bdm::SlotDev rec = slot_record(params, 0, soa->capacity, 0, w.lay.max_boxes, 1, true);
+    bdm::launch_mech(*soa, plain_slots(w, rec), soa->capacity, params->force_bits, w, as_stream(stream));
     return hip_check("mech_step launch");
 }
 
@@ -221,30 +264,32 @@ int bdm_sim_step(const bdm_soa *soa, int32_t model, const bdm_params *params, in
     switch (model) {
     case BDM_MODEL_MECH:
     case BDM_MODEL_SPHEROID: {
-        rc = check_soa(soa, w, true, false);
+        rc = check_soa(soa, w.lay.capacity, true, false);
         if (rc) return rc;
         rc = check_mech_params(params);
         if (rc) return rc;
+        const bdm::SlotDev rec = slot_record(params, 0, soa->capacity, 0, w.lay.max_boxes, 1, true);
         if (model == BDM_MODEL_SPHEROID) {
             rc = check_spheroid_params(params);
             if (rc) return rc;
-            bdm::DivArgs a{params->grow, params->div_d, params->half_cbrt, params->seed, params->salt,
-                           uint64_t(step)};
-            bdm::launch_grow_divide(*soa, a, w, st);
+            bdm::DivArgs a{params->grow, params->div_d, params->half_cbrt, params->seed, params->salt, uint64_t(step)};
+            bdm::launch_grow_divide(*soa, plain_slots(w, rec), soa->capacity, a, w, st);
             rc = hip_check("grow_divide launch");
             if (rc) return rc;
         }
-        rc = do_grid_build(soa, params, false, w, st);
+        bdm::launch_grid_build(*soa, plain_slots(w, rec), soa->capacity, w, st);
+        rc = hip_check("grid_build launch");
         if (rc) return rc;
-        bdm::launch_mech(*soa, mech_args(params), params->force_bits, w, st);
+        bdm::launch_mech(*soa, plain_slots(w, rec), soa->capacity, params->force_bits, w, st);
         return hip_check("mech_step launch");
     }
     case BDM_MODEL_SIR: {
-        rc = check_soa(soa, w, false, true);
+        rc = check_soa(soa, w.lay.capacity, false, true);
         if (rc) return rc;
         rc = check_sir_params(params);
         if (rc) return rc;
-        rc = do_grid_build(soa, params, true, w, st);
+        bdm::SlotDev rec;
+        rc = plain_grid(soa, params, true, w, st, &rec);
         if (rc) return rc;
         bdm::SirArgs a{};
         a.L = params->L;
@@ -256,7 +301,7 @@ int bdm_sim_step(const bdm_soa *soa, int32_t model, const bdm_params *params, in
         a.seed = params->seed;
         a.salt = params->salt;
         a.step = uint64_t(step);
-        bdm::launch_sir(*soa, a, w, st);
+        bdm::launch_sir(*soa, plain_slots(w, rec), soa->capacity, a, w, st);
         return hip_check("sir_step launch");
     }
     default:
@@ -298,12 +343,10 @@ int bdm_sir_counts(const bdm_workspace *ws, int64_t *counts, void *stream) {
     int rc = get_ws(ws, &w);
     if (rc) return rc;
     if (!counts) return fail(BDM_EINVAL, "counts is NULL");
-    hipStream_t st = as_stream(stream);
-    unsigned long long c[3];
-    if (hipMemcpyAsync(c, w.grid->sir_counts, sizeof c, hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-        return hip_check("sir_counts read");
-    for (int i = 0; i < 3; ++i) counts[i] = int64_t(c[i]);
+    bdm::GridDev g;
+    rc = read_grid(w.grid, &g, as_stream(stream));
+    if (rc) return rc;
+    for (int i = 0; i < 3; ++i) counts[i] = int64_t(g.sir_counts[i]);
     return BDM_OK;
 }
 
@@ -313,11 +356,9 @@ int bdm_grid_info(const bdm_workspace *ws, bdm_grid_desc *desc, void *stream) {
     int rc = get_ws(ws, &w);
     if (rc) return rc;
     if (!desc) return fail(BDM_EINVAL, "desc is NULL");
-    hipStream_t st = as_stream(stream);
     bdm::GridDev g;
-    if (hipMemcpyAsync(&g, w.grid, sizeof g, hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-        return hip_check("grid_info read");
+    rc = read_grid(w.grid, &g, as_stream(stream));
+    if (rc) return rc;
     desc->b = g.b;
     for (int i = 0; i < 3; ++i) {
         desc->cmin[i] = g.cmin[i];
@@ -367,7 +408,8 @@ int bdm_contacts(const bdm_workspace *ws, const bdm_params *params, uint32_t *co
         if (params->force_bits != 32 && params->force_bits != 64) return fail(BDM_EINVAL, "force_bits must be 32 or 64");
         a.mode = params->force_bits == 32 ? 1 : 0;
     }
-    bdm::launch_contacts(a, w, counts, offsets, ids, as_stream(stream));
+    const bdm::SlotDev rec = slot_record(params, 0, w.lay.capacity, 0, w.lay.max_boxes, 1, true);
+    bdm::launch_contacts(a, plain_slots(w, rec), w, counts, offsets, ids, as_stream(stream));
     return hip_check("contacts launch");
 }
 
@@ -378,6 +420,104 @@ int bdm_fp_probe(const double *a, const double *b, int64_t n, double *out_sqrt, 
     if (n == 0) return BDM_OK;
     bdm::launch_fp_probe(a, b, n, out_sqrt, out_div, out_sqrtf, out_divf, as_stream(stream));
     return hip_check("fp_probe launch");
+}
+
+// ---------------------------------------------------------------------------------------------
+// Batched form
+// ---------------------------------------------------------------------------------------------
+size_t bdm_batch_workspace_bytes(int64_t capacity, int64_t max_boxes, int32_t slots) {
+    bdm::WsLayout lay;
+    if (slots < 1 || !bdm::ws_layout(capacity, max_boxes, slots, &lay)) return 0;
+    return lay.total;
+}
+
+int bdm_batch_init(const bdm_batch *b, void *stream) {
+    g_last_error.clear();
+    bdm::Ws w;
+    int rc = get_batch(b, &w);
+    if (rc) return rc;
+    rc = check_device();
+    if (rc) return rc;
+    bdm::launch_ws_init(w, as_stream(stream));
+    return hip_check("batch_init launch");
+}
+
+int bdm_batch_set_slot(const bdm_batch *b, int32_t slot, int64_t agent_off, int64_t capacity, int64_t box_off,
+                       int64_t max_boxes, int64_t steps, const bdm_params *p, void *stream) {
+    g_last_error.clear();
+    bdm::Ws w;
+    int rc = get_batch(b, &w);
+    if (rc) return rc;
+    if (slot < 0 || slot >= b->slots) return fail(BDM_EINVAL, "slot %d outside [0, %d)", slot, b->slots);
+    if (agent_off < 0 || agent_off % BDM_SLOT_ALIGN != 0)
+        return fail(BDM_EINVAL, "agent_off must be a non-negative multiple of %d", BDM_SLOT_ALIGN);
+    if (capacity < 1 || agent_off + capacity > b->capacity)
+        return fail(BDM_EINVAL, "slot range [%lld, %lld) outside the batch", (long long)agent_off,
+                    (long long)(agent_off + capacity));
+    if (box_off < 0 || max_boxes < 1 || box_off + max_boxes > b->max_boxes)
+        return fail(BDM_EINVAL, "slot boxes [%lld, %lld) outside the batch", (long long)box_off,
+                    (long long)(box_off + max_boxes));
+    if (steps < 0) return fail(BDM_EINVAL, "steps must be >= 0");
+    rc = check_mech_params(p);
+    if (rc) return rc;
+    const bdm::SlotDev rec = slot_record(p, agent_off, capacity, box_off, max_boxes, steps, true);
+    const int64_t first = agent_off / bdm::kBlock;
+    const int64_t ntile = (agent_off + capacity + bdm::kBlock - 1) / bdm::kBlock - first;
+    bdm::launch_set_slot(w, slot, rec, first, ntile, slot, as_stream(stream));
+    return hip_check("batch_set_slot launch");
+}
+
+int bdm_batch_clear_slot(const bdm_batch *b, int32_t slot, int64_t agent_off, int64_t capacity, void *stream) {
+    g_last_error.clear();
+    bdm::Ws w;
+    int rc = get_batch(b, &w);
+    if (rc) return rc;
+    if (slot < 0 || slot >= b->slots) return fail(BDM_EINVAL, "slot %d outside [0, %d)", slot, b->slots);
+    if (agent_off < 0 || agent_off % BDM_SLOT_ALIGN != 0 || capacity < 0 || agent_off + capacity > b->capacity)
+        return fail(BDM_EINVAL, "slot range outside the batch or misaligned");
+    bdm::SlotDev rec{};
+    const int64_t first = agent_off / bdm::kBlock;
+    const int64_t ntile = (agent_off + capacity + bdm::kBlock - 1) / bdm::kBlock - first;
+    bdm::launch_set_slot(w, slot, rec, first, ntile, -1, as_stream(stream));
+    return hip_check("batch_clear_slot launch");
+}
+
+int bdm_batch_step(const bdm_soa *packed, const bdm_batch *b, void *stream) {
+    g_last_error.clear();
+    bdm::Ws w;
+    int rc = get_batch(b, &w);
+    if (rc) return rc;
+    rc = check_soa(packed, w.lay.capacity, true, false);
+    if (rc) return rc;
+    if (packed->capacity != b->capacity) return fail(BDM_EINVAL, "packed soa capacity must equal the batch capacity");
+    hipStream_t st = as_stream(stream);
+    bdm::Slots sl{};
+    sl.table = w.slots;
+    sl.tilemap = w.tilemap;
+    sl.grids = w.grid;
+    sl.nslots = b->slots;
+    bdm::launch_grid_build(*packed, sl, b->capacity, w, st);
+    bdm::launch_mech(*packed, sl, b->capacity, 0, w, st);
+    bdm::launch_batch_advance(w, st);
+    return hip_check("batch_step launch");
+}
+
+int bdm_batch_slot_status(const bdm_batch *b, int32_t slot, uint32_t *flags, int64_t *steps_left, void *stream) {
+    g_last_error.clear();
+    bdm::Ws w;
+    int rc = get_batch(b, &w);
+    if (rc) return rc;
+    if (slot < 0 || slot >= b->slots) return fail(BDM_EINVAL, "slot %d outside [0, %d)", slot, b->slots);
+    hipStream_t st = as_stream(stream);
+    bdm::GridDev g;
+    bdm::SlotDev s;
+    if (hipMemcpyAsync(&g, &w.grid[slot], sizeof g, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(&s, &w.slots[slot], sizeof s, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return hip_check("batch_slot_status read");
+    if (flags) *flags = g.flags;
+    if (steps_left) *steps_left = s.steps_left;
+    return BDM_OK;
 }
 
 const char *bdm_strerror(int code) {

@@ -1,8 +1,13 @@
 // common.hpp -- internals shared by the gfx950 kernels and the C-ABI layer of libbdm.so.
 //
-// Workspace layout, the device-resident grid record, Philox4x64-10 (Salmon et al., SC'11), the
-// order-preserving integer encoding of binary64 used by the min/max reductions, and the box
-// coordinate rule of the uniform grid (paper Sec. 2.1).
+// Workspace layout, the per-population ("slot") parameter record and grid record,
+// Philox4x64-10 (Salmon et al., SC'11), the order-preserving integer encoding of binary64 used by
+// the min/max reductions, and the box coordinate rule of the uniform grid (paper Sec. 2.1).
+//
+// Every kernel works on "slots": independent populations packed into one set of arrays.  A
+// plain call is one slot whose record travels by value in the kernel arguments; the batched
+// form keeps a table of slot records and a tile -> slot map in device memory.  Both run the
+// same per-agent code, so an agent's arithmetic does not depend on the other slots.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,7 +17,8 @@
 
 namespace bdm {
 
-constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts of 64)
+constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts of 64) = agents per tile
+constexpr int kBoundsTile = 1024;    // agents per workgroup of the bounds reduction
 constexpr int kScanItems = 8;        // items per thread in the decoupled look-back scan
 constexpr int kScanTile = kBlock * kScanItems;
 constexpr uint32_t kScanSpinLimit = 1u << 22;  // polls before a look-back gives up
@@ -20,7 +26,7 @@ constexpr uint32_t kScanSpinLimit = 1u << 22;  // polls before a look-back gives
 // Philox draw purposes: counter word 0 = purpose + (attempt << 8).
 enum : uint64_t { kRngInit = 1, kRngMove = 2, kRngRec = 3, kRngInf = 4, kRngDiv = 5 };
 
-// Device-resident grid description and step bookkeeping; lives at the head of the workspace.
+// Grid description and step bookkeeping of one slot (device memory, 256 bytes).
 struct GridDev {
     double b;                       // box edge
     int32_t cmin[3];                // lattice coordinate of box 0
@@ -33,34 +39,58 @@ struct GridDev {
     unsigned long long red_max[3];  // order-encoded running maxima
     unsigned long long red_dmax;    // order-encoded running maximum diameter
     uint32_t red_bad;               // a non-finite coordinate or diameter was seen
-    uint32_t scan_ticket;           // dynamic tile index of the running scan
+    uint32_t scan_ticket;           // dynamic tile index of the running scan (slot 0 only)
     unsigned long long sir_counts[3];
+    int64_t sorted_base;            // first sorted position of this slot (start[box_off])
 };
 static_assert(sizeof(GridDev) <= 256, "grid record must fit its slot");
 
-// Byte offsets of every workspace region (256-byte aligned), derived from capacity/max_boxes.
+// Parameters and placement of one slot.
+struct SlotDev {
+    int64_t agent_off;   // first array index of the slot (multiple of kBoundsTile in a batch)
+    int64_t capacity;    // agents the slot may hold
+    int64_t box_off;     // first histogram entry of the slot
+    int64_t max_boxes;   // histogram entries reserved for the slot
+    int64_t steps_left;  // batch: steps still to run (the slot idles at 0); plain: 1
+    double k, gamma, dt, max_disp;
+    double box;          // requested box edge (<= 0: largest diameter)
+    double L;            // periodic cube edge
+    float kf, gf;        // binary32 copies of k and gamma
+    int32_t force_bits;  // 64 or 32
+    int32_t periodic;
+    int32_t nb;          // periodic boxes per axis
+    int32_t has_d;       // spheres (diameters present) or points
+};
+
+// Byte offsets of every workspace region (256-byte aligned).  `slots` = 0 is a plain
+// workspace (one grid record, slot passed by value); > 0 is a batch of that many slots.
 struct WsLayout {
-    size_t grid, count, start, tiles, key, rank, tmpid, pos4, adh, ids, state, flagid, rankid;
+    size_t grid, slots, tilemap, count, start, tiles, key, rank, tmpid, pos4, adh, ids, state, flagid,
+        rankid;
     size_t total;
-    int64_t capacity, max_boxes, max_tiles;
+    int64_t capacity, max_boxes, max_tiles, nslots, ntiles;
 };
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-inline bool ws_layout(int64_t capacity, int64_t max_boxes, WsLayout *L) {
-    if (capacity < 0 || max_boxes < 0 || capacity > (int64_t(1) << 32) - 2 ||
-        max_boxes > (int64_t(1) << 32) - 2)
+inline bool ws_layout(int64_t capacity, int64_t max_boxes, int64_t slots, WsLayout *L) {
+    if (capacity < 0 || max_boxes < 0 || slots < 0 || slots > BDM_MAX_SLOTS ||
+        capacity > (int64_t(1) << 32) - 2 - kBoundsTile || max_boxes > (int64_t(1) << 32) - 2)
         return false;
     size_t cap = size_t(capacity), mb = size_t(max_boxes);
     size_t longest = cap > mb ? cap : mb;
     size_t tiles = (longest + 1 + kScanTile - 1) / kScanTile + 1;
+    size_t ngrid = slots > 0 ? size_t(slots) : 1;
+    size_t ntile = (cap + kBlock - 1) / kBlock;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t at = off;
         off = align_up(off + bytes, 256);
         return at;
     };
-    L->grid = take(256);
+    L->grid = take(256 * ngrid);
+    L->slots = take(slots > 0 ? sizeof(SlotDev) * size_t(slots) : 0);
+    L->tilemap = take(slots > 0 ? 4 * ntile : 0);
     L->count = take(4 * (mb + 1));
     L->start = take(4 * (mb + 1));
     L->tiles = take(8 * tiles);
@@ -77,12 +107,16 @@ inline bool ws_layout(int64_t capacity, int64_t max_boxes, WsLayout *L) {
     L->capacity = capacity;
     L->max_boxes = max_boxes;
     L->max_tiles = int64_t(tiles);
+    L->nslots = slots;
+    L->ntiles = int64_t(ntile);
     return true;
 }
 
 // Typed views of one workspace.
 struct Ws {
-    GridDev *grid;
+    GridDev *grid;       // [max(1, nslots)]
+    SlotDev *slots;      // batch only
+    int32_t *tilemap;    // batch only: tile -> slot (-1 = none)
     uint32_t *count, *start;
     unsigned long long *tiles;
     uint32_t *key, *rank, *tmpid;
@@ -98,6 +132,8 @@ inline Ws ws_view(void *base, const WsLayout &L) {
     char *p = static_cast<char *>(base);
     Ws w;
     w.grid = reinterpret_cast<GridDev *>(p + L.grid);
+    w.slots = L.nslots > 0 ? reinterpret_cast<SlotDev *>(p + L.slots) : nullptr;
+    w.tilemap = L.nslots > 0 ? reinterpret_cast<int32_t *>(p + L.tilemap) : nullptr;
     w.count = reinterpret_cast<uint32_t *>(p + L.count);
     w.start = reinterpret_cast<uint32_t *>(p + L.start);
     w.tiles = reinterpret_cast<unsigned long long *>(p + L.tiles);
@@ -112,6 +148,29 @@ inline Ws ws_view(void *base, const WsLayout &L) {
     w.rankid = reinterpret_cast<uint32_t *>(p + L.rankid);
     w.lay = L;
     return w;
+}
+
+// Slot addressing handed to every kernel by value.
+struct Slots {
+    const SlotDev *table;      // batch: slot records; plain: nullptr (use `one`)
+    const int32_t *tilemap;    // batch: tile -> slot; plain: nullptr (every tile is slot 0)
+    GridDev *grids;            // grid record per slot
+    int64_t nslots;            // 1 for a plain call
+    SlotDev one;               // the plain call's slot record
+};
+
+__device__ __forceinline__ int slot_of_tile(const Slots &sl, int64_t tile) {
+    return sl.tilemap ? sl.tilemap[tile] : 0;
+}
+
+__device__ __forceinline__ SlotDev slot_record(const Slots &sl, int slot) {
+    return sl.table ? sl.table[slot] : sl.one;
+}
+
+// Live count of a slot clamped to its capacity (a corrupted count must not index out of bounds).
+__device__ __forceinline__ int64_t live_count(const int64_t *n_ptr, int slot, int64_t capacity) {
+    const int64_t n = n_ptr[slot];
+    return n < 0 ? 0 : (n > capacity ? capacity : n);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -185,12 +244,6 @@ __device__ __forceinline__ int box_coord(double v, double b, int cmin, int nb, b
     return int(f);
 }
 
-// Live count clamped to the array capacity (a corrupted count must not index out of bounds).
-__device__ __forceinline__ int64_t live_count(const int64_t *n_ptr, int64_t capacity) {
-    const int64_t n = *n_ptr;
-    return n < 0 ? 0 : (n > capacity ? capacity : n);
-}
-
 // Wavefront-wide inclusive prefix sum (64 lanes).
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     const int lane = threadIdx.x & 63;
@@ -206,6 +259,13 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     return v;
+}
+
+// Workgroup `bid` of `nblocks` is dispatched to XCD bid % 8; give every XCD one contiguous
+// eighth of the tiles so that neighbouring rows of the box-sorted arrays share its L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t nblocks) {
+    const uint32_t per = nblocks / 8, rem = nblocks % 8, x = bid % 8, idx = bid / 8;
+    return x * per + (x < rem ? x : rem) + idx;
 }
 
 }  // namespace bdm

@@ -1,4 +1,4 @@
-// k_gen.hip -- seeded initial state, workspace initialisation and the IEEE probe (gfx950).
+// k_gen.hip -- seeded initial state, workspace and slot-table maintenance, and the IEEE probe.
 //
 // Generator: agent i draws Philox4x64-10 blocks at counter (INIT + attempt*2^8, i, 0, 0) keyed
 // by (seed, salt); u = (word >> 11) * 2^-53.  Cube: words 0..2 give x, y, z = L*u, word 3 the
@@ -58,30 +58,60 @@ __global__ __launch_bounds__(kBlock) void k_fp_probe(const double *a, const doub
     if (odf) odf[i] = float(x) / float(y);
 }
 
-// Zero the grid record, the histogram and the scan tiles; reductions start at their identities.
-__global__ __launch_bounds__(kBlock) void k_ws_init(GridDev *g, uint32_t *count, int64_t ncount,
-                                                    unsigned long long *tiles, int64_t ntiles) {
+__device__ void clear_grid(GridDev *g) {
+    g->b = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        g->cmin[a] = 0;
+        g->dims[a] = 0;
+        g->red_min[a] = ~0ull;
+        g->red_max[a] = 0ull;
+        g->sir_counts[a] = 0ull;
+    }
+    g->nboxes = 0;
+    g->n = 0;
+    g->valid = 0;
+    g->flags = 0u;
+    g->red_dmax = 0ull;
+    g->red_bad = 0u;
+    g->scan_ticket = 0u;
+    g->sorted_base = 0;
+}
+
+// Zero the grid records, the histogram and the scan tiles; empty the batch slot table.
+__global__ __launch_bounds__(kBlock) void k_ws_init(GridDev *g, int64_t ngrid, uint32_t *count, int64_t ncount,
+                                                    unsigned long long *tiles, int64_t ntiles, SlotDev *slots,
+                                                    int32_t *tilemap, int64_t ntilemap) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t k = i; k < ncount; k += stride) count[k] = 0u;
     for (int64_t k = i; k < ntiles; k += stride) tiles[k] = 0ull;
-    if (i == 0) {
-        g->b = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            g->cmin[a] = 0;
-            g->dims[a] = 0;
-            g->red_min[a] = ~0ull;
-            g->red_max[a] = 0ull;
-            g->sir_counts[a] = 0ull;
+    for (int64_t k = i; k < ntilemap; k += stride) tilemap[k] = -1;
+    for (int64_t k = i; k < ngrid; k += stride) {
+        clear_grid(&g[k]);
+        if (slots) {
+            SlotDev z{};
+            slots[k] = z;
         }
-        g->nboxes = 0;
-        g->n = 0;
-        g->valid = 0;
-        g->flags = 0u;
-        g->red_dmax = 0ull;
-        g->red_bad = 0u;
-        g->scan_ticket = 0u;
     }
+}
+
+// Write one slot record and point its tiles at it (rec.capacity < 0 clears the slot: its tiles
+// point nowhere and its record is zeroed).  Runs on the stream, so replays see it in order.
+__global__ __launch_bounds__(kBlock) void k_set_slot(SlotDev *slots, int32_t *tilemap, GridDev *grids,
+                                                     int32_t slot, SlotDev rec, int64_t first_tile,
+                                                     int64_t ntile, int32_t value) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < ntile) tilemap[first_tile + i] = value;
+    if (i == 0) {
+        slots[slot] = rec;
+        clear_grid(&grids[slot]);
+    }
+}
+
+// One step done for every slot that was running.
+__global__ void k_batch_advance(SlotDev *slots, int64_t nslots) {
+    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s < nslots && slots[s].steps_left > 0) slots[s].steps_left -= 1;
 }
 
 static inline unsigned nblocks(int64_t n, int64_t cap_blocks) {
@@ -102,8 +132,23 @@ void launch_fp_probe(const double *a, const double *b, int64_t n, double *os, do
 
 void launch_ws_init(const Ws &w, hipStream_t st) {
     const int64_t ncount = w.lay.max_boxes + 1;
-    hipLaunchKernelGGL(k_ws_init, dim3(nblocks(ncount, 4096)), dim3(kBlock), 0, st, w.grid, w.count, ncount,
-                       w.tiles, w.lay.max_tiles);
+    const int64_t ngrid = w.lay.nslots > 0 ? w.lay.nslots : 1;
+    const int64_t nmap = w.lay.nslots > 0 ? w.lay.ntiles : 0;
+    int64_t most = ncount > w.lay.max_tiles ? ncount : w.lay.max_tiles;
+    if (nmap > most) most = nmap;
+    hipLaunchKernelGGL(k_ws_init, dim3(nblocks(most, 4096)), dim3(kBlock), 0, st, w.grid, ngrid, w.count, ncount,
+                       w.tiles, w.lay.max_tiles, w.slots, w.tilemap, nmap);
+}
+
+void launch_set_slot(const Ws &w, int32_t slot, const SlotDev &rec, int64_t first_tile, int64_t ntile,
+                     int32_t value, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_slot, dim3(nblocks(ntile, 0)), dim3(kBlock), 0, st, w.slots, w.tilemap, w.grid, slot,
+                       rec, first_tile, ntile, value);
+}
+
+void launch_batch_advance(const Ws &w, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_advance, dim3(nblocks(w.lay.nslots, 0)), dim3(kBlock), 0, st, w.slots,
+                       w.lay.nslots);
 }
 
 }  // namespace bdm

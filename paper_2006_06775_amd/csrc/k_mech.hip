@@ -2,31 +2,42 @@
 // clamp and synchronous integration in one kernel (paper Sec. 2.1 "calculate mechanical forces"
 // agent operation; Zubler & Douglas force model shared with Cortex3D, Sec. 3.4).
 //
-// One lane per agent in box-sorted order.  The 27 neighbour boxes are walked as 9 contiguous
-// key runs (dz, dy in {-1, 0, 1}; dx = -1..+1 adjacent in key space because x varies fastest),
-// so candidates arrive in ascending (key, id) order -- the canonical summation order -- and each
-// run costs two start[] reads.  Neighbour records are packed double4 (x, y, z, d), one 32-byte
-// load per candidate.  A conservative squared-distance prefilter skips the sqrt of candidates
-// that cannot touch; every surviving pair is evaluated exactly as the definition spells it.
+// One lane per agent in box-sorted order.  The 27 neighbour boxes are 9 contiguous key runs
+// (dz, dy in {-1, 0, 1}; dx = -1..+1 adjacent in key space because x varies fastest), so
+// candidates arrive in ascending (key, id) order -- the canonical summation order.
+//
+// The work is split in two so that the wavefront does not pay the expensive exact law for
+// every candidate of every lane:
+//   1. candidate stream: each lane walks its 9 runs as one flattened stream (run table in LDS,
+//      the next 32-byte record prefetched while the current one is tested) and keeps the
+//      candidates that pass a cheap conservative squared-distance test in a small per-lane
+//      queue in LDS;
+//   2. exact pass: the queued candidates, still in canonical order, are re-read and evaluated
+//      exactly as the definition spells the law (binary64 or binary32) and summed.
+// The packed record holds (x, y, z, r) with r = d/2.
+//
+// Schedule: a tile is 256 consecutive sorted agents.  A plain call processes its tiles in the
+// pencil order built with the grid (rows grouped 16 at a time and swept along z) and gives each
+// XCD one contiguous part of that sequence, so the three z-planes a tile reads stay in that
+// XCD's L2.  Outputs are written with non-temporal stores: they are not read again in the step.
 #include "kernels.hpp"
 
 namespace bdm {
 
-// Accept when a contact is still possible: a contact needs |x_i - x_j| < r_i + r_j, i.e.
-// d2 < (r_i + r_j)^2 in exact arithmetic, and a 1e-4 relative margin covers every rounding of
-// both the binary64 and the binary32 evaluation of the test.
+constexpr int kQueue = 8;  // queued candidates per lane before an exact pass
+
+// A contact needs |x_i - x_j| < r_i + r_j, i.e. d2 < (r_i + r_j)^2 in exact arithmetic; the
+// 1e-4 relative margin covers every rounding of both the binary64 and binary32 evaluations.
 __device__ __forceinline__ bool maybe_touch(double d2, double s) { return d2 < s * s * 1.0001; }
 
 template <bool F32>
-__device__ __forceinline__ void pair_force(const double4 &p, double ri, float rif, const double4 &q,
-                                           const MechArgs &a, double &fx, double &fy, double &fz) {
+__device__ __forceinline__ void exact_pair(const double4 &p, const double4 &q, float rif, const SlotDev &a,
+                                           double &fx, double &fy, double &fz) {
     const double dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
-    const double rj = 0.5 * q.w;
-    const double s = ri + rj;
-    const double d2 = (dx * dx + dy * dy) + dz * dz;
-    if (!maybe_touch(d2, s)) return;
+    const double ri = p.w, rj = q.w;
     if constexpr (!F32) {
-        const double dist = __builtin_sqrt(d2);
+        const double s = ri + rj;
+        const double dist = __builtin_sqrt((dx * dx + dy * dy) + dz * dz);
         const double delta = s - dist;
         if (!(delta > 0.0) || dist == 0.0) return;
         const double rhat = (ri * rj) / s;
@@ -51,49 +62,131 @@ __device__ __forceinline__ void pair_force(const double4 &p, double ri, float ri
     }
 }
 
+// The 9 key runs of the box (cx, cy, cz) as [lo, hi) ranges of sorted positions.
+__device__ __forceinline__ void load_runs(const GridDev *__restrict__ g, const uint32_t *__restrict__ start,
+                                          int cx, int cy, int cz, uint2 (*s_run)[kBlock], int t) {
+    const int nx = g->dims[0], ny = g->dims[1], nz = g->dims[2];
+    const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < nx - 1 ? cx + 1 : nx - 1;
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        const int zz = cz + r / 3 - 1, yy = cy + r % 3 - 1;
+        uint32_t lo = 0, hi = 0;
+        if (zz >= 0 && zz < nz && yy >= 0 && yy < ny) {
+            const uint32_t kb = uint32_t(x0) + uint32_t(nx) * (uint32_t(yy) + uint32_t(ny) * uint32_t(zz));
+            lo = start[kb];
+            hi = start[kb + uint32_t(x1 - x0) + 1u];
+        }
+        s_run[r][t] = make_uint2(lo, hi);
+    }
+}
+
+// Summed force on the agent at sorted position q (canonical order), then gate/clamp/move.
 template <bool F32>
-__global__ __launch_bounds__(kBlock) void k_mech(const GridDev *__restrict__ g,
+__device__ __forceinline__ void mech_agent(const GridDev *__restrict__ g, const SlotDev &S, uint32_t q,
+                                           const double4 *__restrict__ pos4, const uint32_t *__restrict__ start,
+                                           uint2 (*s_run)[kBlock], uint32_t (*s_q)[kBlock], int t,
+                                           double &fx, double &fy, double &fz, double4 &p) {
+    const double b = g->b;
+    p = pos4[q];
+    const int cx = box_coord(p.x, b, g->cmin[0], g->dims[0], false);
+    const int cy = box_coord(p.y, b, g->cmin[1], g->dims[1], false);
+    const int cz = box_coord(p.z, b, g->cmin[2], g->dims[2], false);
+    load_runs(g, start, cx, cy, cz, s_run, t);
+    const float rif = float(p.w);
+    fx = 0.0;
+    fy = 0.0;
+    fz = 0.0;
+    int qn = 0;
+    // flattened candidate stream over the 9 runs; (r, j, end) is the next slot to fetch
+    int r = 0;
+    uint2 run = s_run[0][t];
+    uint32_t j = run.x, end = run.y;
+    while (j >= end && r < 8) {
+        run = s_run[++r][t];
+        j = run.x;
+        end = run.y;
+    }
+    bool have = j < end;
+    uint32_t jc = j;
+    double qx = 0.0, qy = 0.0, qz = 0.0, qr = 0.0;
+    if (have) {
+        const double4 c = pos4[jc];
+        qx = c.x; qy = c.y; qz = c.z; qr = c.w;
+    }
+    ++j;
+    while (have) {
+        while (j >= end && r < 8) {
+            run = s_run[++r][t];
+            j = run.x;
+            end = run.y;
+        }
+        const bool have_n = j < end;
+        const uint32_t jn = j;
+        double nx_ = 0.0, ny_ = 0.0, nz_ = 0.0, nr_ = 0.0;
+        if (have_n) {  // prefetch the next record while the current one is tested
+            const double4 c = pos4[jn];
+            nx_ = c.x; ny_ = c.y; nz_ = c.z; nr_ = c.w;
+        }
+        ++j;
+        const double dx = p.x - qx, dy = p.y - qy, dz = p.z - qz;
+        const double d2 = (dx * dx + dy * dy) + dz * dz;
+        if (maybe_touch(d2, p.w + qr) && jc != q) {
+            s_q[qn][t] = jc;
+            if (++qn == kQueue) {
+                for (int c = 0; c < kQueue; ++c) exact_pair<F32>(p, pos4[s_q[c][t]], rif, S, fx, fy, fz);
+                qn = 0;
+            }
+        }
+        jc = jn;
+        qx = nx_; qy = ny_; qz = nz_; qr = nr_;
+        have = have_n;
+    }
+    for (int c = 0; c < qn; ++c) exact_pair<F32>(p, pos4[s_q[c][t]], rif, S, fx, fy, fz);
+}
+
+// precision: 64 or 32 for a plain call; 0 = per slot (batch)
+template <int kPrec>
+__global__ __launch_bounds__(kBlock) void k_mech(Slots sl, const uint32_t *__restrict__ order,
                                                  const double4 *__restrict__ pos4,
                                                  const double *__restrict__ adh_s,
                                                  const uint32_t *__restrict__ id_s,
                                                  const uint8_t *__restrict__ state_s,
-                                                 const uint32_t *__restrict__ start, MechArgs a,
-                                                 bdm_soa out) {
-    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (!g->valid || s >= g->n || s >= out.capacity) return;
-    const double b = g->b;
-    const int nx = g->dims[0], ny = g->dims[1], nz = g->dims[2];
-    const double4 p = pos4[s];
-    const int cx = box_coord(p.x, b, g->cmin[0], nx, false);
-    const int cy = box_coord(p.y, b, g->cmin[1], ny, false);
-    const int cz = box_coord(p.z, b, g->cmin[2], nz, false);
-    const double ri = 0.5 * p.w;
-    const float rif = float(ri);
-    const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < nx - 1 ? cx + 1 : nx - 1;
-    double fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int oz = -1; oz <= 1; ++oz) {
-        const int zz = cz + oz;
-        if (zz < 0 || zz >= nz) continue;
-        for (int oy = -1; oy <= 1; ++oy) {
-            const int yy = cy + oy;
-            if (yy < 0 || yy >= ny) continue;
-            const uint32_t kb = uint32_t(x0) + uint32_t(nx) * (uint32_t(yy) + uint32_t(ny) * uint32_t(zz));
-            const uint32_t j0 = start[kb], j1 = start[kb + uint32_t(x1 - x0) + 1u];
-            for (uint32_t j = j0; j < j1; ++j) {
-                if (j == uint32_t(s)) continue;
-                pair_force<F32>(p, ri, rif, pos4[j], a, fx, fy, fz);
-            }
-        }
+                                                 const uint32_t *__restrict__ start, bdm_soa out) {
+    __shared__ uint2 s_run[9][kBlock];
+    __shared__ uint32_t s_q[kQueue][kBlock];
+    const int t = threadIdx.x;
+    int64_t tile = blockIdx.x;
+    if (order) {  // plain call: pencil order, one contiguous part of it per XCD
+        const GridDev *g0 = &sl.grids[0];
+        if (!g0->valid) return;
+        const uint32_t live_tiles = uint32_t((g0->n + kBlock - 1) / kBlock);
+        if (blockIdx.x >= live_tiles) return;
+        tile = order[xcd_tile(blockIdx.x, live_tiles)];
     }
+    const int slot = slot_of_tile(sl, tile);
+    if (slot < 0) return;
+    const GridDev *g = &sl.grids[slot];
+    const SlotDev S = slot_record(sl, slot);
+    const int64_t l = tile * kBlock + t - S.agent_off;  // local (sorted) index in the slot
+    if (!g->valid || l >= g->n || l >= S.capacity) return;
+    const uint32_t q = uint32_t(g->sorted_base + l);
+    double fx, fy, fz;
+    double4 p;
+    const bool f32 = kPrec == 32 || (kPrec == 0 && S.force_bits == 32);
+    if (f32)
+        mech_agent<true>(g, S, q, pos4, start + S.box_off, s_run, s_q, t, fx, fy, fz, p);
+    else
+        mech_agent<false>(g, S, q, pos4, start + S.box_off, s_run, s_q, t, fx, fy, fz, p);
+
     // adherence gate, clamp, integrate (binary64)
-    const double adh = adh_s[s];
+    const double adh = adh_s[q];
     double nxp = p.x, nyp = p.y, nzp = p.z;
     const double fn = __builtin_sqrt((fx * fx + fy * fy) + fz * fz);
     if (!(fn < adh)) {
-        double ux = a.dt * fx, uy = a.dt * fy, uz = a.dt * fz;
+        double ux = S.dt * fx, uy = S.dt * fy, uz = S.dt * fz;
         const double len = __builtin_sqrt((ux * ux + uy * uy) + uz * uz);
-        if (len > a.max_disp) {
-            const double sc = a.max_disp / len;
+        if (len > S.max_disp) {
+            const double sc = S.max_disp / len;
             ux = ux * sc;
             uy = uy * sc;
             uz = uz * sc;
@@ -102,84 +195,84 @@ __global__ __launch_bounds__(kBlock) void k_mech(const GridDev *__restrict__ g,
         nyp = p.y + uy;
         nzp = p.z + uz;
     }
-    out.x[s] = nxp;
-    out.y[s] = nyp;
-    out.z[s] = nzp;
-    out.diam[s] = p.w;
-    out.adh[s] = adh;
-    out.id[s] = id_s[s];
-    if (out.state) out.state[s] = state_s[s];
-    if (out.fx) out.fx[s] = fx;
-    if (out.fy) out.fy[s] = fy;
-    if (out.fz) out.fz[s] = fz;
+    const int64_t o = S.agent_off + l;
+    __builtin_nontemporal_store(nxp, &out.x[o]);
+    __builtin_nontemporal_store(nyp, &out.y[o]);
+    __builtin_nontemporal_store(nzp, &out.z[o]);
+    __builtin_nontemporal_store(2.0 * p.w, &out.diam[o]);
+    __builtin_nontemporal_store(adh, &out.adh[o]);
+    __builtin_nontemporal_store(id_s[q], &out.id[o]);
+    if (out.state) out.state[o] = state_s[q];
+    if (out.fx) __builtin_nontemporal_store(fx, &out.fx[o]);
+    if (out.fy) __builtin_nontemporal_store(fy, &out.fy[o]);
+    if (out.fz) __builtin_nontemporal_store(fz, &out.fz[o]);
 }
 
-// Test hook: contact lists per sorted slot in force-sum order (mechanical contact).
-__global__ __launch_bounds__(kBlock) void k_contacts_mech(const GridDev *__restrict__ g,
-                                                          const double4 *__restrict__ pos4,
+// Test hook: contact lists per sorted slot in force-sum order (mechanical contact, plain calls).
+__global__ __launch_bounds__(kBlock) void k_contacts_mech(Slots sl, const double4 *__restrict__ pos4,
                                                           const uint32_t *__restrict__ id_s,
-                                                          const uint32_t *__restrict__ start,
-                                                          int f32, uint32_t *counts,
-                                                          const int64_t *offsets, uint32_t *ids) {
-    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+                                                          const uint32_t *__restrict__ start, int f32,
+                                                          uint32_t *counts, const int64_t *offsets,
+                                                          uint32_t *ids) {
+    __shared__ uint2 s_run[9][kBlock];
+    const int t = threadIdx.x;
+    const int64_t s = int64_t(blockIdx.x) * blockDim.x + t;
+    const GridDev *g = &sl.grids[0];
     if (!g->valid || s >= g->n) return;
     const double b = g->b;
-    const int nx = g->dims[0], ny = g->dims[1], nz = g->dims[2];
     const double4 p = pos4[s];
-    const int cx = box_coord(p.x, b, g->cmin[0], nx, false);
-    const int cy = box_coord(p.y, b, g->cmin[1], ny, false);
-    const int cz = box_coord(p.z, b, g->cmin[2], nz, false);
-    const double ri = 0.5 * p.w;
+    const int cx = box_coord(p.x, b, g->cmin[0], g->dims[0], false);
+    const int cy = box_coord(p.y, b, g->cmin[1], g->dims[1], false);
+    const int cz = box_coord(p.z, b, g->cmin[2], g->dims[2], false);
+    load_runs(g, start, cx, cy, cz, s_run, t);
+    const double ri = p.w;
     const float rif = float(ri);
-    const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < nx - 1 ? cx + 1 : nx - 1;
     uint32_t c = 0;
-    for (int oz = -1; oz <= 1; ++oz) {
-        const int zz = cz + oz;
-        if (zz < 0 || zz >= nz) continue;
-        for (int oy = -1; oy <= 1; ++oy) {
-            const int yy = cy + oy;
-            if (yy < 0 || yy >= ny) continue;
-            const uint32_t kb = uint32_t(x0) + uint32_t(nx) * (uint32_t(yy) + uint32_t(ny) * uint32_t(zz));
-            const uint32_t j0 = start[kb], j1 = start[kb + uint32_t(x1 - x0) + 1u];
-            for (uint32_t j = j0; j < j1; ++j) {
-                if (j == uint32_t(s)) continue;
-                const double4 q = pos4[j];
-                const double dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
-                const double rj = 0.5 * q.w;
-                bool hit;
-                if (!f32) {
-                    hit = ((ri + rj) - __builtin_sqrt((dx * dx + dy * dy) + dz * dz)) > 0.0;
-                } else {
-                    const float dxf = float(dx), dyf = float(dy), dzf = float(dz);
-                    hit = ((rif + float(rj)) - __builtin_sqrtf((dxf * dxf + dyf * dyf) + dzf * dzf)) > 0.0f;
-                }
-                if (hit) {
-                    if (ids) ids[offsets[s] + c] = id_s[j];
-                    ++c;
-                }
+    for (int r = 0; r < 9; ++r) {
+        const uint2 run = s_run[r][t];
+        for (uint32_t j = run.x; j < run.y; ++j) {
+            if (j == uint32_t(s)) continue;
+            const double4 q = pos4[j];
+            const double dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+            const double rj = q.w;
+            bool hit;
+            if (!f32) {
+                hit = ((ri + rj) - __builtin_sqrt((dx * dx + dy * dy) + dz * dz)) > 0.0;
+            } else {
+                const float dxf = float(dx), dyf = float(dy), dzf = float(dz);
+                hit = ((rif + float(rj)) - __builtin_sqrtf((dxf * dxf + dyf * dyf) + dzf * dzf)) > 0.0f;
+            }
+            if (hit) {
+                if (ids) ids[offsets[s] + c] = id_s[j];
+                ++c;
             }
         }
     }
     counts[s] = c;
 }
 
-void launch_mech(const bdm_soa &s, const MechArgs &a, int force_bits, const Ws &w, hipStream_t st) {
-    int64_t nb = (s.capacity + kBlock - 1) / kBlock;
+void launch_mech(const bdm_soa &s, const Slots &sl, int64_t capacity, int precision, const Ws &w,
+                 hipStream_t st) {
+    int64_t nb = (capacity + kBlock - 1) / kBlock;
     if (nb < 1) nb = 1;
-    if (force_bits == 32)
-        hipLaunchKernelGGL(k_mech<true>, dim3(unsigned(nb)), dim3(kBlock), 0, st, w.grid, w.pos4, w.adh,
-                           w.ids, w.state, w.start, a, s);
+    const uint32_t *order = sl.table ? nullptr : w.flagid;  // plain: order built with the grid
+    if (precision == 32)
+        hipLaunchKernelGGL(k_mech<32>, dim3(unsigned(nb)), dim3(kBlock), 0, st, sl, order, w.pos4, w.adh, w.ids,
+                           w.state, w.start, s);
+    else if (precision == 64)
+        hipLaunchKernelGGL(k_mech<64>, dim3(unsigned(nb)), dim3(kBlock), 0, st, sl, order, w.pos4, w.adh, w.ids,
+                           w.state, w.start, s);
     else
-        hipLaunchKernelGGL(k_mech<false>, dim3(unsigned(nb)), dim3(kBlock), 0, st, w.grid, w.pos4, w.adh,
-                           w.ids, w.state, w.start, a, s);
+        hipLaunchKernelGGL(k_mech<0>, dim3(unsigned(nb)), dim3(kBlock), 0, st, sl, order, w.pos4, w.adh, w.ids,
+                           w.state, w.start, s);
 }
 
-void launch_contacts_mech(int f32, const Ws &w, uint32_t *counts, const int64_t *offsets, uint32_t *ids,
-                          hipStream_t st) {
+void launch_contacts_mech(int f32, const Slots &sl, const Ws &w, uint32_t *counts, const int64_t *offsets,
+                          uint32_t *ids, hipStream_t st) {
     int64_t nb = (w.lay.capacity + kBlock - 1) / kBlock;
     if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_contacts_mech, dim3(unsigned(nb)), dim3(kBlock), 0, st, w.grid, w.pos4, w.ids,
-                       w.start, f32, counts, offsets, ids);
+    hipLaunchKernelGGL(k_contacts_mech, dim3(unsigned(nb)), dim3(kBlock), 0, st, sl, w.pos4, w.ids, w.start, f32,
+                       counts, offsets, ids);
 }
 
 }  // namespace bdm

@@ -24,19 +24,25 @@ __device__ __forceinline__ double wrap(double v, double L) {
     return v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_sir(const GridDev *__restrict__ g,
-                                                const double4 *__restrict__ pos4,
+__global__ __launch_bounds__(kBlock) void k_sir(Slots sl, const double4 *__restrict__ pos4,
                                                 const uint8_t *__restrict__ state_s,
                                                 const uint32_t *__restrict__ id_s,
-                                                const uint32_t *__restrict__ start, SirArgs a,
-                                                bdm_soa out, unsigned long long *counts) {
-    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const bool live = g->valid && s < g->n && s < out.capacity;
+                                                const uint32_t *__restrict__ start_all, SirArgs a,
+                                                bdm_soa out) {
+    const int64_t tile = blockIdx.x;
+    const int slot = slot_of_tile(sl, tile);
+    if (slot < 0) return;
+    GridDev *g = &sl.grids[slot];
+    const SlotDev S = slot_record(sl, slot);
+    const uint32_t *start = start_all + S.box_off;
+    const int64_t l = tile * kBlock + threadIdx.x - S.agent_off;
+    const bool live = g->valid && l < g->n && l < S.capacity;
     uint8_t ns = 3;  // no agent
     if (live) {
-        const double4 p = pos4[s];
-        const uint8_t st = state_s[s];
-        const uint32_t me = id_s[s];
+        const uint32_t q = uint32_t(g->sorted_base + l);
+        const double4 p = pos4[q];
+        const uint8_t st = state_s[q];
+        const uint32_t me = id_s[q];
         ns = st;
         if (st == 0) {
             const int nb = g->dims[0];
@@ -54,11 +60,11 @@ __global__ __launch_bounds__(kBlock) void k_sir(const GridDev *__restrict__ g,
                         const uint32_t kb = uint32_t(xx) + uint32_t(nb) * (uint32_t(yy) + uint32_t(nb) * uint32_t(zz));
                         const uint32_t j1 = start[kb + 1];
                         for (uint32_t j = start[kb]; j < j1; ++j) {
-                            if (j == uint32_t(s) || state_s[j] != 1) continue;
-                            const double4 q = pos4[j];
-                            const double dx = min_image(p.x - q.x, a.L, a.half);
-                            const double dy = min_image(p.y - q.y, a.L, a.half);
-                            const double dz = min_image(p.z - q.z, a.L, a.half);
+                            if (j == q || state_s[j] != 1) continue;
+                            const double4 c = pos4[j];
+                            const double dx = min_image(p.x - c.x, a.L, a.half);
+                            const double dy = min_image(p.y - c.y, a.L, a.half);
+                            const double dz = min_image(p.z - c.z, a.L, a.half);
                             m += ((dx * dx + dy * dy) + dz * dz) <= a.r2;
                         }
                     }
@@ -74,29 +80,30 @@ __global__ __launch_bounds__(kBlock) void k_sir(const GridDev *__restrict__ g,
             if (bernoulli(draw(a.seed, a.salt, kRngRec, 0, me, a.step).w[0], a.trec)) ns = 2;
         }
         const Block4 w = draw(a.seed, a.salt, kRngMove, 0, me, a.step);
-        out.x[s] = wrap(p.x + a.walk * (2.0 * u01(w.w[0]) - 1.0), a.L);
-        out.y[s] = wrap(p.y + a.walk * (2.0 * u01(w.w[1]) - 1.0), a.L);
-        out.z[s] = wrap(p.z + a.walk * (2.0 * u01(w.w[2]) - 1.0), a.L);
-        out.state[s] = ns;
-        out.id[s] = me;
+        const int64_t o = S.agent_off + l;
+        out.x[o] = wrap(p.x + a.walk * (2.0 * u01(w.w[0]) - 1.0), a.L);
+        out.y[o] = wrap(p.y + a.walk * (2.0 * u01(w.w[1]) - 1.0), a.L);
+        out.z[o] = wrap(p.z + a.walk * (2.0 * u01(w.w[2]) - 1.0), a.L);
+        out.state[o] = ns;
+        out.id[o] = me;
     }
     // S/I/R totals: one atomic per wavefront and group
     const uint32_t cs = wave_sum(ns == 0), ci = wave_sum(ns == 1), cr = wave_sum(ns == 2);
     if ((threadIdx.x & 63) == 0) {
-        if (cs) atomicAdd(&counts[0], static_cast<unsigned long long>(cs));
-        if (ci) atomicAdd(&counts[1], static_cast<unsigned long long>(ci));
-        if (cr) atomicAdd(&counts[2], static_cast<unsigned long long>(cr));
+        if (cs) atomicAdd(&g->sir_counts[0], static_cast<unsigned long long>(cs));
+        if (ci) atomicAdd(&g->sir_counts[1], static_cast<unsigned long long>(ci));
+        if (cr) atomicAdd(&g->sir_counts[2], static_cast<unsigned long long>(cr));
     }
 }
 
 // Test hook: SIR contacts (any state) per sorted slot, boxes visited in (dz, dy, dx) order.
-__global__ __launch_bounds__(kBlock) void k_contacts_periodic(const GridDev *__restrict__ g,
-                                                              const double4 *__restrict__ pos4,
+__global__ __launch_bounds__(kBlock) void k_contacts_periodic(Slots sl, const double4 *__restrict__ pos4,
                                                               const uint32_t *__restrict__ id_s,
                                                               const uint32_t *__restrict__ start,
                                                               ContactArgs a, uint32_t *counts,
                                                               const int64_t *offsets, uint32_t *ids) {
     const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const GridDev *g = &sl.grids[0];
     if (!g->valid || s >= g->n) return;
     const double4 p = pos4[s];
     const int nb = g->dims[0];
@@ -129,23 +136,23 @@ __global__ __launch_bounds__(kBlock) void k_contacts_periodic(const GridDev *__r
     counts[s] = c;
 }
 
-void launch_sir(const bdm_soa &s, const SirArgs &a, const Ws &w, hipStream_t st) {
-    int64_t nb = (s.capacity + kBlock - 1) / kBlock;
+void launch_sir(const bdm_soa &s, const Slots &sl, int64_t capacity, const SirArgs &a, const Ws &w,
+                hipStream_t st) {
+    int64_t nb = (capacity + kBlock - 1) / kBlock;
     if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_sir, dim3(unsigned(nb)), dim3(kBlock), 0, st, w.grid, w.pos4, w.state, w.ids,
-                       w.start, a, s, w.grid->sir_counts);
+    hipLaunchKernelGGL(k_sir, dim3(unsigned(nb)), dim3(kBlock), 0, st, sl, w.pos4, w.state, w.ids, w.start, a, s);
 }
 
-void launch_contacts(const ContactArgs &a, const Ws &w, uint32_t *counts, const int64_t *offsets,
-                     uint32_t *ids, hipStream_t st) {
+void launch_contacts(const ContactArgs &a, const Slots &sl, const Ws &w, uint32_t *counts,
+                     const int64_t *offsets, uint32_t *ids, hipStream_t st) {
     if (a.mode != 2) {
-        launch_contacts_mech(a.mode == 1, w, counts, offsets, ids, st);
+        launch_contacts_mech(a.mode == 1, sl, w, counts, offsets, ids, st);
         return;
     }
     int64_t nb = (w.lay.capacity + kBlock - 1) / kBlock;
     if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_contacts_periodic, dim3(unsigned(nb)), dim3(kBlock), 0, st, w.grid, w.pos4,
-                       w.ids, w.start, a, counts, offsets, ids);
+    hipLaunchKernelGGL(k_contacts_periodic, dim3(unsigned(nb)), dim3(kBlock), 0, st, sl, w.pos4, w.ids,
+                       w.start, a, counts, offsets, ids);
 }
 
 }  // namespace bdm

@@ -1,5 +1,5 @@
 // k_spheroid.hip -- tumour-spheroid growth and division on gfx950 (paper Sec. 3.2: cell growth
-// and duplication; the cell growth & division benchmark of Sec. 3.4).
+// and duplication; the cell growth & division benchmark of Sec. 3.4).  Plain calls (one slot).
 //
 //   grow_flag  diam *= grow for every live agent; division flag by agent id (diam >= div_d);
 //              also clears the scan tiles for the rank scan that follows
@@ -20,7 +20,7 @@ __global__ __launch_bounds__(kBlock) void k_grow_flag(const int64_t *n_ptr, int6
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < max_tiles) tiles[i] = 0ull;
     if (i == 0) *ticket = 0u;
-    const int64_t n = live_count(n_ptr, capacity);
+    const int64_t n = live_count(n_ptr, 0, capacity);
     if (i >= n) return;
     const double d = diam[i] * a.grow;
     diam[i] = d;
@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kBlock) void k_divide(const int64_t *n_ptr, int64_t
                                                    const uint32_t *__restrict__ rankid, DivArgs a,
                                                    GridDev *g) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t n = live_count(n_ptr, capacity);
+    const int64_t n = live_count(n_ptr, 0, capacity);
     if (i >= n) return;
     const double d = s.diam[i];
     if (!(d >= a.div_d)) return;
@@ -80,24 +80,25 @@ __global__ __launch_bounds__(kBlock) void k_divide(const int64_t *n_ptr, int64_t
 
 __global__ void k_append(int64_t *n_ptr, int64_t capacity, const uint32_t *rankid) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int64_t n = live_count(n_ptr, capacity);
+    const int64_t n = live_count(n_ptr, 0, capacity);
     int64_t nn = n + int64_t(rankid[n]);
     if (nn > capacity) nn = capacity;
     *n_ptr = nn;
 }
 
-void launch_grow_divide(const bdm_soa &s, const DivArgs &a, const Ws &w, hipStream_t st) {
-    const int64_t cap = s.capacity;  // daughters must land inside the caller's arrays
+void launch_grow_divide(const bdm_soa &s, const Slots &sl, int64_t capacity, const DivArgs &a, const Ws &w,
+                        hipStream_t st) {
+    (void)sl;
+    const int64_t cap = capacity;  // daughters must land inside the caller's arrays
     int64_t nb = (cap + kBlock - 1) / kBlock;
     if (nb < 1) nb = 1;
     const int64_t need = w.lay.max_tiles;
     int64_t nb_flag = nb;
     if (nb_flag * kBlock < need) nb_flag = (need + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_grow_flag, dim3(unsigned(nb_flag)), dim3(kBlock), 0, st, s.n, cap, s.diam, s.id,
-                       a, w.flagid, w.tiles, w.lay.max_tiles, &w.grid->scan_ticket, w.grid);
-    launch_scan(w.flagid, w.rankid, s.n, nullptr, cap, w, 0, false, st);
-    hipLaunchKernelGGL(k_divide, dim3(unsigned(nb)), dim3(kBlock), 0, st, s.n, cap, s, w.rankid, a,
-                       w.grid);
+    hipLaunchKernelGGL(k_grow_flag, dim3(unsigned(nb_flag)), dim3(kBlock), 0, st, s.n, cap, s.diam, s.id, a,
+                       w.flagid, w.tiles, w.lay.max_tiles, &w.grid[0].scan_ticket, &w.grid[0]);
+    launch_scan(w.flagid, w.rankid, s.n, cap, w, 0, false, st);
+    hipLaunchKernelGGL(k_divide, dim3(unsigned(nb)), dim3(kBlock), 0, st, s.n, cap, s, w.rankid, a, &w.grid[0]);
     hipLaunchKernelGGL(k_append, dim3(1), dim3(64), 0, st, s.n, cap, w.rankid);
 }
 

@@ -1,18 +1,13 @@
 // kernels.hpp -- argument records and host launchers of the gfx950 kernels (internal).
+//
+// Every launcher takes a `Slots` record (common.hpp): one slot by value for a plain call, or
+// the batch's slot table and tile map.  Launch geometry covers `capacity` array entries in
+// tiles of kBlock agents; tiles outside any slot, or beyond a slot's live count, exit at once.
 #pragma once
 
 #include "common.hpp"
 
 namespace bdm {
-
-struct FinalizeArgs {
-    double box;         // requested box edge (<= 0: largest diameter; periodic: the request)
-    double L;           // periodic cube edge
-    int32_t nb;         // periodic boxes per axis
-    int32_t periodic;
-    int32_t has_d;      // diameters present (spheres) or not (points)
-    int64_t max_boxes;
-};
 
 struct SoaIn {
     const double *x, *y, *z, *d, *adh;
@@ -23,11 +18,6 @@ struct SoaIn {
 struct ReadOut {
     double *x, *y, *z, *d, *fx, *fy, *fz;
     uint8_t *state;
-};
-
-struct MechArgs {
-    double k, gamma, dt, max_disp;
-    float kf, gf;       // binary32 copies for the FP32 pair law
 };
 
 struct SirArgs {
@@ -54,17 +44,25 @@ struct ContactArgs {
     double L, half, r2;
 };
 
-void launch_grid_build(const bdm_soa &s, const FinalizeArgs &fa, const Ws &w, hipStream_t st);
-void launch_scan(uint32_t *in, uint32_t *out, const int64_t *len_ptr, const int32_t *gate,
-                 int64_t max_len, const Ws &w, int zero_in, bool prepare, hipStream_t st);
-void launch_contacts_mech(int f32, const Ws &w, uint32_t *counts, const int64_t *offsets,
+// Grid build (bounds, finalize, key/histogram, scan, scatter, canonical order) of every slot.
+void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, const Ws &w, hipStream_t st);
+// Exclusive scan of in[0, len) into out[0, len] (len read on the device).
+void launch_scan(uint32_t *in, uint32_t *out, const int64_t *len_ptr, int64_t max_len, const Ws &w,
+                 int zero_in, bool prepare, hipStream_t st);
+void launch_mech(const bdm_soa &s, const Slots &sl, int64_t capacity, int precision, const Ws &w,
+                 hipStream_t st);
+void launch_sir(const bdm_soa &s, const Slots &sl, int64_t capacity, const SirArgs &a, const Ws &w,
+                hipStream_t st);
+void launch_grow_divide(const bdm_soa &s, const Slots &sl, int64_t capacity, const DivArgs &a, const Ws &w,
+                        hipStream_t st);
+void launch_batch_advance(const Ws &w, hipStream_t st);
+void launch_set_slot(const Ws &w, int32_t slot, const SlotDev &rec, int64_t first_tile, int64_t ntile,
+                     int32_t value, hipStream_t st);
+void launch_contacts(const ContactArgs &a, const Slots &sl, const Ws &w, uint32_t *counts,
+                     const int64_t *offsets, uint32_t *ids, hipStream_t st);
+void launch_contacts_mech(int f32, const Slots &sl, const Ws &w, uint32_t *counts, const int64_t *offsets,
                           uint32_t *ids, hipStream_t st);
 void launch_read_agents(const bdm_soa &s, const ReadOut &o, hipStream_t st);
-void launch_mech(const bdm_soa &s, const MechArgs &a, int force_bits, const Ws &w, hipStream_t st);
-void launch_contacts(const ContactArgs &a, const Ws &w, uint32_t *counts, const int64_t *offsets,
-                     uint32_t *ids, hipStream_t st);
-void launch_sir(const bdm_soa &s, const SirArgs &a, const Ws &w, hipStream_t st);
-void launch_grow_divide(const bdm_soa &s, const DivArgs &a, const Ws &w, hipStream_t st);
 void launch_generate(const bdm_soa &s, const GenArgs &a, hipStream_t st);
 void launch_fp_probe(const double *a, const double *b, int64_t n, double *os, double *od, float *osf,
                      float *odf, hipStream_t st);
