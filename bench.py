@@ -40,6 +40,10 @@ def parse():
                     help="agents in the oracle's bounded sample (same density)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_mech_fp64_n16m.json"),
                     help="HBM bytes per mech_step launch from rocprofv3 counters (optional)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the batched/served stream")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-budget-gib", type=float, default=4.0,
+                    help="HBM the server may hold for resident simulations")
     return ap.parse_args()
 
 
@@ -120,6 +124,42 @@ def measured_traffic(path, n):
     return t.get("bytes_per_launch")
 
 
+def serving(args):
+    """Stream of independent simulations (n log-uniform in [1e3, 2e6], 10-100 steps, binary32
+    pair forces): continuous batching vs one-at-a-time plain launches."""
+    import torch
+
+    from paper_2006_06775_amd import serve
+    per_agent = 68 + 65 + 4
+    cap = int(args.serve_budget_gib * (1 << 30) / (per_agent + 8 * 1.6))
+    boxes = int(cap * 1.6)
+    slots = 64
+    # closed-system calibration: every request present at t = 0
+    calib = serve.make_trace(args.serve_requests, seed=0, rate=1e9)
+    srv = serve.Server(cap, boxes, slots)
+    c = srv.run(calib).summary()
+    del srv
+    torch.cuda.empty_cache()
+    rate = 0.8 * c["requests"] / c["wall_s"]
+    trace = serve.make_trace(args.serve_requests, seed=0, rate=rate)
+    srv = serve.Server(cap, boxes, slots)
+    b = srv.run(trace).summary()
+    del srv
+    torch.cuda.empty_cache()
+    p_stats, _ = serve.run_plain(trace)
+    p = p_stats.summary()
+    return {
+        "requests": args.serve_requests, "arrival_rate_per_s": rate, "slots": slots,
+        "hbm_budget_gib": args.serve_budget_gib, "force_precision": "fp32 pair law, fp64 positions",
+        "batched": {k: b[k] for k in ("agent_updates_per_s", "p50_latency_s", "p99_latency_s", "wall_s",
+                                      "batch_steps", "max_concurrent")},
+        "plain": {k: p[k] for k in ("agent_updates_per_s", "p50_latency_s", "p99_latency_s", "wall_s")},
+        "batched_over_plain": b["agent_updates_per_s"] / p["agent_updates_per_s"],
+        "calibration_closed_system": {k: c[k] for k in ("agent_updates_per_s", "wall_s")},
+        "agent_updates": b["agent_updates"],
+    }
+
+
 def cpu_baseline(n_sample):
     """Single-thread oracle: one mechanical step (grid + forces + move) of n_sample agents at
     the workload's density."""
@@ -181,6 +221,7 @@ def main():
     del r64["pop"]
     torch.cuda.empty_cache()
 
+    served = None if args.no_serve else serving(args)
     copy_gbps = copy_bandwidth(torch)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_sample)
     out = {
@@ -204,6 +245,7 @@ def main():
         "mech_step_only_agent_updates_per_s": n / (r64["mech_ms"] * 1e-3),
         "roofline": roofline,
         "fp32_forces": fp32,
+        "served_stream": served,
         "copy_kernel_GBps": round(copy_gbps, 1),
         "cpu_baseline": cpu,
     }

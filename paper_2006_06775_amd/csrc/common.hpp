@@ -1,8 +1,8 @@
 // common.hpp -- internals shared by the gfx950 kernels and the C-ABI layer of libbdm.so.
 //
 // Workspace layout, the per-population ("slot") parameter record and grid record,
-// Philox4x64-10 (Salmon et al., SC'11), the order-preserving integer encoding of binary64 used by
-// the min/max reductions, and the box coordinate rule of the uniform grid (paper Sec. 2.1).
+// Philox4x64-10 (Salmon et al., SC'11) and the box coordinate rule of the uniform grid (paper
+// Sec. 2.1).
 //
 // Every kernel works on "slots": independent populations packed into one set of arrays.  A
 // plain call is one slot whose record travels by value in the kernel arguments; the batched
@@ -35,11 +35,10 @@ struct GridDev {
     int64_t n;                      // agents binned by the last build
     int32_t valid;                  // 1 when the last build succeeded
     uint32_t flags;                 // sticky BDM_FLAG_* bits
-    unsigned long long red_min[3];  // order-encoded running minima of x, y, z
-    unsigned long long red_max[3];  // order-encoded running maxima
-    unsigned long long red_dmax;    // order-encoded running maximum diameter
-    uint32_t red_bad;               // a non-finite coordinate or diameter was seen
     uint32_t scan_ticket;           // dynamic tile index of the running scan (slot 0 only)
+    uint32_t pad0;
+    unsigned long long div_nx;      // fast-division multipliers of dims[0] and dims[1]
+    unsigned long long div_ny;
     unsigned long long sir_counts[3];
     int64_t sorted_base;            // first sorted position of this slot (start[box_off])
 };
@@ -65,8 +64,8 @@ struct SlotDev {
 // Byte offsets of every workspace region (256-byte aligned).  `slots` = 0 is a plain
 // workspace (one grid record, slot passed by value); > 0 is a batch of that many slots.
 struct WsLayout {
-    size_t grid, slots, tilemap, count, start, tiles, key, rank, tmpid, pos4, adh, ids, state, flagid,
-        rankid;
+    size_t grid, slots, tilemap, partials, count, start, tiles, key, rank, tmpid, pos4, adh, ids, state,
+        flagid, rankid;
     size_t total;
     int64_t capacity, max_boxes, max_tiles, nslots, ntiles;
 };
@@ -91,6 +90,7 @@ inline bool ws_layout(int64_t capacity, int64_t max_boxes, int64_t slots, WsLayo
     L->grid = take(256 * ngrid);
     L->slots = take(slots > 0 ? sizeof(SlotDev) * size_t(slots) : 0);
     L->tilemap = take(slots > 0 ? 4 * ntile : 0);
+    L->partials = take(64 * ((cap + kBoundsTile - 1) / kBoundsTile + 1));
     L->count = take(4 * (mb + 1));
     L->start = take(4 * (mb + 1));
     L->tiles = take(8 * tiles);
@@ -117,6 +117,7 @@ struct Ws {
     GridDev *grid;       // [max(1, nslots)]
     SlotDev *slots;      // batch only
     int32_t *tilemap;    // batch only: tile -> slot (-1 = none)
+    double *partials;    // bounds reduction: 8 values per kBoundsTile agents
     uint32_t *count, *start;
     unsigned long long *tiles;
     uint32_t *key, *rank, *tmpid;
@@ -134,6 +135,7 @@ inline Ws ws_view(void *base, const WsLayout &L) {
     w.grid = reinterpret_cast<GridDev *>(p + L.grid);
     w.slots = L.nslots > 0 ? reinterpret_cast<SlotDev *>(p + L.slots) : nullptr;
     w.tilemap = L.nslots > 0 ? reinterpret_cast<int32_t *>(p + L.tilemap) : nullptr;
+    w.partials = reinterpret_cast<double *>(p + L.partials);
     w.count = reinterpret_cast<uint32_t *>(p + L.count);
     w.start = reinterpret_cast<uint32_t *>(p + L.start);
     w.tiles = reinterpret_cast<unsigned long long *>(p + L.tiles);
@@ -223,16 +225,6 @@ __device__ __forceinline__ bool bernoulli(uint64_t w, Threshold th) {
     return th.mode == 2 || (th.mode == 1 && w < th.t);
 }
 
-// Order-preserving map from binary64 to unsigned 64-bit (for atomic min/max).
-__device__ __forceinline__ unsigned long long ord_enc(double v) {
-    unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
-    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
-}
-__device__ __forceinline__ double ord_dec(unsigned long long e) {
-    unsigned long long b = (e >> 63) ? (e & 0x7fffffffffffffffull) : ~e;
-    return __longlong_as_double(static_cast<long long>(b));
-}
-
 // Box coordinate along one axis: floor(v / b) relative to the grid origin (open space) or as
 // is (periodic cube), clamped into [0, nb - 1].  In open space the clamp never binds (the
 // origin and dims come from the min/max of the same positions) and only guards memory.
@@ -242,6 +234,16 @@ __device__ __forceinline__ int box_coord(double v, double b, int cmin, int nb, b
     if (f < 0.0) f = 0.0;
     if (f > double(nb - 1)) f = double(nb - 1);
     return int(f);
+}
+
+// Division of a 32-bit value by a 32-bit divisor d >= 1 through the multiplier M = (2^64 - 1)/d
+// + 1 (Lemire, Kaser and Kurz, "Faster remainder by direct computation", 2019): a / d is the
+// high 64 bits of M * a, exact for every 32-bit a; d = 1 (M wraps to 0) is handled apart.
+__host__ __device__ __forceinline__ unsigned long long fastdiv_magic(uint32_t d) {
+    return d <= 1 ? 0ull : ~0ull / d + 1ull;
+}
+__device__ __forceinline__ uint32_t fastdiv(uint32_t a, unsigned long long m) {
+    return m ? uint32_t(__umul64hi(m, a)) : a;
 }
 
 // Wavefront-wide inclusive prefix sum (64 lanes).

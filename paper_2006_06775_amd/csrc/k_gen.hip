@@ -63,16 +63,12 @@ __device__ void clear_grid(GridDev *g) {
     for (int a = 0; a < 3; ++a) {
         g->cmin[a] = 0;
         g->dims[a] = 0;
-        g->red_min[a] = ~0ull;
-        g->red_max[a] = 0ull;
         g->sir_counts[a] = 0ull;
     }
     g->nboxes = 0;
     g->n = 0;
     g->valid = 0;
     g->flags = 0u;
-    g->red_dmax = 0ull;
-    g->red_bad = 0u;
     g->scan_ticket = 0u;
     g->sorted_base = 0;
 }

@@ -2,15 +2,16 @@
 // centre, box edge from the largest agent, 27-box neighbourhood).
 //
 // Pipeline for every slot at once (one launch each, all device-resident, no host read-back):
-//   bounds     min/max of x, y, z and max diameter over each slot's live agents
-//              (order-encoded 64-bit atomics, one per workgroup and quantity)
-//   finalize   one lane per slot: box edge, lattice origin and dims, box count check
+//   bounds     min/max of x, y, z and max diameter per 1024 agents (one partial record each)
+//   finalize   one workgroup per slot: reduce its partials, box edge, lattice origin and dims,
+//              box count check
 //   key_count  box key per agent and its arrival rank in the box (integer atomics)
 //   scan       single-pass decoupled look-back exclusive scan of the packed histogram
 //   scatter    ids into their box range in arrival order
 //   canon      each agent counts the smaller ids in its box (ascending-id order inside a box)
 //              and copies itself into the sorted copy: (x, y, z, r = d/2) packed as double4
 //              (halving and doubling a binary64 are exact, so d = 2r is recovered bit for bit)
+//              plus its box key
 //   order      one workgroup: the processing order of the mechanics tiles (pencils of rows
 //              swept along z, so that the three z-planes a tile reads stay in one XCD's L2)
 #include "kernels.hpp"
@@ -20,27 +21,25 @@ namespace bdm {
 constexpr int kPencilRows = 16;       // y-rows per pencil of the processing order
 constexpr int kOrderBins = 8192;      // largest pencil x z-plane count the order kernel sorts
 
-__global__ __launch_bounds__(kBlock) void k_bounds(Slots sl, const int64_t *n_ptr,
-                                                   const double *__restrict__ x,
-                                                   const double *__restrict__ y,
-                                                   const double *__restrict__ z,
-                                                   const double *__restrict__ d,
-                                                   unsigned long long *tiles, int64_t max_tiles) {
-    const int64_t base = int64_t(blockIdx.x) * kBoundsTile;
-    if (blockIdx.x == 0) {  // reset the scan tiles of the coming histogram scan
-        for (int64_t t = threadIdx.x; t < max_tiles; t += blockDim.x) tiles[t] = 0ull;
-        if (threadIdx.x == 0) sl.grids[0].scan_ticket = 0u;
-    }
+// Per workgroup of kBoundsTile agents: min/max of x, y, z, max diameter and a non-finite flag,
+// written as one 8-value partial record (no atomics).
+__device__ __forceinline__ void bounds_tile(const Slots &sl, int64_t btile, const int64_t *n_ptr,
+                                            const double *__restrict__ x, const double *__restrict__ y,
+                                            const double *__restrict__ z, const double *__restrict__ d,
+                                            double *partials) {
+    const int64_t base = btile * kBoundsTile;
     const int slot = slot_of_tile(sl, base / kBlock);
     if (slot < 0) return;
     const SlotDev S = slot_record(sl, slot);
-    GridDev *g = &sl.grids[slot];
     const int64_t n = live_count(n_ptr, slot, S.capacity);
     const int64_t l0 = base - S.agent_off;  // local index of the workgroup's first agent
     if (l0 >= n) return;
-    double lo[3] = {__builtin_inf(), __builtin_inf(), __builtin_inf()};
-    double hi[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
-    double dmax = 0.0;
+    double v[8];
+    for (int a = 0; a < 3; ++a) {
+        v[a] = __builtin_inf();
+        v[3 + a] = -__builtin_inf();
+    }
+    v[6] = 0.0;
     bool bad = false;
     constexpr int kUnroll = kBoundsTile / kBlock;
     double px[kUnroll], py[kUnroll], pz[kUnroll], pd[kUnroll];
@@ -57,80 +56,100 @@ __global__ __launch_bounds__(kBlock) void k_bounds(Slots sl, const int64_t *n_pt
     for (int u = 0; u < kUnroll; ++u) {
         bad |= !__builtin_isfinite(px[u]) || !__builtin_isfinite(py[u]) || !__builtin_isfinite(pz[u]) ||
                !__builtin_isfinite(pd[u]);
-        lo[0] = fmin(lo[0], px[u]);
-        hi[0] = fmax(hi[0], px[u]);
-        lo[1] = fmin(lo[1], py[u]);
-        hi[1] = fmax(hi[1], py[u]);
-        lo[2] = fmin(lo[2], pz[u]);
-        hi[2] = fmax(hi[2], pz[u]);
-        dmax = fmax(dmax, pd[u]);
+        v[0] = fmin(v[0], px[u]);
+        v[3] = fmax(v[3], px[u]);
+        v[1] = fmin(v[1], py[u]);
+        v[4] = fmax(v[4], py[u]);
+        v[2] = fmin(v[2], pz[u]);
+        v[5] = fmax(v[5], pz[u]);
+        v[6] = fmax(v[6], pd[u]);
     }
-    uint32_t badw = bad ? 1u : 0u;
+    v[7] = bad ? 1.0 : 0.0;
+    __shared__ double s_red[kBlock / 64][8];
 #pragma unroll
     for (int s = 32; s >= 1; s >>= 1) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            lo[a] = fmin(lo[a], __shfl_xor(lo[a], s, 64));
-            hi[a] = fmax(hi[a], __shfl_xor(hi[a], s, 64));
+            v[a] = fmin(v[a], __shfl_xor(v[a], s, 64));
+            v[3 + a] = fmax(v[3 + a], __shfl_xor(v[3 + a], s, 64));
         }
-        dmax = fmax(dmax, __shfl_xor(dmax, s, 64));
-        badw |= __shfl_xor(badw, s, 64);
+        v[6] = fmax(v[6], __shfl_xor(v[6], s, 64));
+        v[7] = fmax(v[7], __shfl_xor(v[7], s, 64));
     }
-    __shared__ double s_red[kBlock / 64][8];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) {
-        for (int a = 0; a < 3; ++a) {
-            s_red[wave][a] = lo[a];
-            s_red[wave][3 + a] = hi[a];
-        }
-        s_red[wave][6] = dmax;
-        s_red[wave][7] = badw ? 1.0 : 0.0;
-    }
+    if (lane == 0)
+        for (int a = 0; a < 8; ++a) s_red[wave][a] = v[a];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < kBlock / 64; ++w) {
-            for (int a = 0; a < 3; ++a) {
-                lo[a] = fmin(lo[a], s_red[w][a]);
-                hi[a] = fmax(hi[a], s_red[w][3 + a]);
-            }
-            dmax = fmax(dmax, s_red[w][6]);
-            badw |= s_red[w][7] != 0.0;
-        }
-        if (badw) atomicOr(&g->red_bad, 1u);
-        for (int a = 0; a < 3; ++a) {
-            atomicMin(&g->red_min[a], ord_enc(lo[a]));
-            atomicMax(&g->red_max[a], ord_enc(hi[a]));
-        }
-        if (d) atomicMax(&g->red_dmax, ord_enc(dmax));
+    if (threadIdx.x < 8) {
+        const int a = threadIdx.x;
+        double r = s_red[0][a];
+        for (int w = 1; w < kBlock / 64; ++w) r = (a < 3) ? fmin(r, s_red[w][a]) : fmax(r, s_red[w][a]);
+        partials[btile * 8 + a] = r;
     }
+    __syncthreads();  // s_red is reused by the next tile of this workgroup
 }
 
-// One lane per slot: box edge, lattice, box count; resets the reductions for the next build.
-__global__ void k_finalize(Slots sl, const int64_t *n_ptr) {
-    const int slot = int(blockIdx.x) * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_bounds(Slots sl, int64_t nbtiles, const int64_t *n_ptr,
+                                                   const double *__restrict__ x,
+                                                   const double *__restrict__ y,
+                                                   const double *__restrict__ z,
+                                                   const double *__restrict__ d, double *partials,
+                                                   unsigned long long *tiles, int64_t max_tiles) {
+    if (blockIdx.x == 0) {  // reset the scan tiles of the coming histogram scan
+        for (int64_t t = threadIdx.x; t < max_tiles; t += blockDim.x) tiles[t] = 0ull;
+        if (threadIdx.x == 0) sl.grids[0].scan_ticket = 0u;
+    }
+    for (int64_t bt = blockIdx.x; bt < nbtiles; bt += gridDim.x) bounds_tile(sl, bt, n_ptr, x, y, z, d, partials);
+}
+
+// One workgroup per slot: reduce the slot's bounds partials, then box edge, lattice, box count.
+__global__ __launch_bounds__(kBlock) void k_finalize(Slots sl, const int64_t *n_ptr, const double *partials) {
+    const int slot = int(blockIdx.x);
     if (slot >= sl.nslots) return;
     const SlotDev a = slot_record(sl, slot);
     GridDev *g = &sl.grids[slot];
     const int64_t n_raw = n_ptr[slot];
     const int64_t n = live_count(n_ptr, slot, a.capacity);
-    const double dmax = a.has_d ? ord_dec(g->red_dmax) : 0.0;
-    double lo[3], hi[3];
+    const bool idle = a.steps_left <= 0 || a.capacity <= 0;
+    double v[8];
     for (int i = 0; i < 3; ++i) {
-        lo[i] = ord_dec(g->red_min[i]);
-        hi[i] = ord_dec(g->red_max[i]);
+        v[i] = __builtin_inf();
+        v[3 + i] = -__builtin_inf();
     }
-    const uint32_t bad = g->red_bad;
-    for (int i = 0; i < 3; ++i) {
-        g->red_min[i] = ~0ull;
-        g->red_max[i] = 0ull;
+    v[6] = 0.0;
+    v[7] = 0.0;
+    if (!idle) {
+        const int64_t b0 = a.agent_off / kBoundsTile, nb = (n + kBoundsTile - 1) / kBoundsTile;
+        for (int64_t k = threadIdx.x; k < nb; k += blockDim.x) {
+            const double *p = partials + (b0 + k) * 8;
+            for (int i = 0; i < 3; ++i) {
+                v[i] = fmin(v[i], p[i]);
+                v[3 + i] = fmax(v[3 + i], p[3 + i]);
+            }
+            v[6] = fmax(v[6], p[6]);
+            v[7] = fmax(v[7], p[7]);
+        }
     }
-    g->red_dmax = 0ull;
-    g->red_bad = 0u;
+    __shared__ double s_red[kBlock][8];
+    for (int i = 0; i < 8; ++i) s_red[threadIdx.x][i] = v[i];
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (int(threadIdx.x) < off)
+            for (int i = 0; i < 8; ++i)
+                s_red[threadIdx.x][i] = (i < 3) ? fmin(s_red[threadIdx.x][i], s_red[threadIdx.x + off][i])
+                                                : fmax(s_red[threadIdx.x][i], s_red[threadIdx.x + off][i]);
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double lo[3] = {s_red[0][0], s_red[0][1], s_red[0][2]};
+    const double hi[3] = {s_red[0][3], s_red[0][4], s_red[0][5]};
+    const double dmax = a.has_d ? s_red[0][6] : 0.0;
+    const bool bad = s_red[0][7] != 0.0;
     g->sir_counts[0] = g->sir_counts[1] = g->sir_counts[2] = 0ull;
     g->valid = 0;
     g->n = 0;
     g->nboxes = 0;
-    if (a.steps_left <= 0) return;  // idle batch slot
+    if (idle) return;  // idle batch slot
     if (n_raw != n) {
         g->flags |= BDM_FLAG_BADCOUNT;
         return;
@@ -195,16 +214,17 @@ __global__ void k_finalize(Slots sl, const int64_t *n_ptr) {
         return;
     }
     g->nboxes = int64_t(g->dims[0]) * g->dims[1] * g->dims[2];
+    g->div_nx = fastdiv_magic(uint32_t(g->dims[0]));
+    g->div_ny = fastdiv_magic(uint32_t(g->dims[1]));
     g->valid = 1;
 }
 
-__global__ __launch_bounds__(kBlock) void k_key_count(Slots sl, const double *__restrict__ x,
-                                                      const double *__restrict__ y,
-                                                      const double *__restrict__ z, uint32_t *count,
-                                                      uint32_t *__restrict__ key,
-                                                      uint32_t *__restrict__ rank) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int slot = slot_of_tile(sl, blockIdx.x);
+__device__ __forceinline__ void key_count_tile(const Slots &sl, int64_t tile, const double *__restrict__ x,
+                                               const double *__restrict__ y, const double *__restrict__ z,
+                                               uint32_t *count, uint32_t *__restrict__ key,
+                                               uint32_t *__restrict__ rank) {
+    const int64_t i = tile * kBlock + threadIdx.x;
+    const int slot = slot_of_tile(sl, tile);
     if (slot < 0) return;
     const GridDev *g = &sl.grids[slot];
     const SlotDev S = slot_record(sl, slot);
@@ -217,6 +237,15 @@ __global__ __launch_bounds__(kBlock) void k_key_count(Slots sl, const double *__
     const uint32_t k = uint32_t(cx) + uint32_t(g->dims[0]) * (uint32_t(cy) + uint32_t(g->dims[1]) * uint32_t(cz));
     key[i] = k;
     rank[i] = atomicAdd(&count[S.box_off + k], 1u);
+}
+
+__global__ __launch_bounds__(kBlock) void k_key_count(Slots sl, int64_t ntiles, const double *__restrict__ x,
+                                                      const double *__restrict__ y,
+                                                      const double *__restrict__ z, uint32_t *count,
+                                                      uint32_t *__restrict__ key,
+                                                      uint32_t *__restrict__ rank) {
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+        key_count_tile(sl, tile, x, y, z, count, key, rank);
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_prepare(unsigned long long *tiles, int64_t max_tiles,
@@ -344,13 +373,12 @@ __global__ __launch_bounds__(kBlock) void k_scan(uint32_t *in, uint32_t *out, co
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter_id(Slots sl, const uint32_t *__restrict__ key,
-                                                       const uint32_t *__restrict__ rank,
-                                                       const uint32_t *__restrict__ start,
-                                                       const uint32_t *__restrict__ id,
-                                                       uint32_t *__restrict__ tmpid) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int slot = slot_of_tile(sl, blockIdx.x);
+__device__ __forceinline__ void scatter_tile(const Slots &sl, int64_t tile, const uint32_t *__restrict__ key,
+                                             const uint32_t *__restrict__ rank,
+                                             const uint32_t *__restrict__ start,
+                                             const uint32_t *__restrict__ id, uint32_t *__restrict__ tmpid) {
+    const int64_t i = tile * kBlock + threadIdx.x;
+    const int slot = slot_of_tile(sl, tile);
     if (slot < 0) return;
     GridDev *g = &sl.grids[slot];
     const SlotDev S = slot_record(sl, slot);
@@ -365,14 +393,23 @@ __global__ __launch_bounds__(kBlock) void k_scatter_id(Slots sl, const uint32_t 
     tmpid[pos] = id[i];
 }
 
-__global__ __launch_bounds__(kBlock) void k_canon(Slots sl, SoaIn s, const uint32_t *__restrict__ key,
-                                                  const uint32_t *__restrict__ start,
-                                                  const uint32_t *__restrict__ tmpid,
-                                                  double4 *__restrict__ pos4, double *__restrict__ adh_s,
-                                                  uint32_t *__restrict__ id_s, uint8_t *__restrict__ state_s,
-                                                  uint32_t *__restrict__ tile_key) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int slot = slot_of_tile(sl, blockIdx.x);
+__global__ __launch_bounds__(kBlock) void k_scatter_id(Slots sl, int64_t ntiles, const uint32_t *__restrict__ key,
+                                                       const uint32_t *__restrict__ rank,
+                                                       const uint32_t *__restrict__ start,
+                                                       const uint32_t *__restrict__ id,
+                                                       uint32_t *__restrict__ tmpid) {
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+        scatter_tile(sl, tile, key, rank, start, id, tmpid);
+}
+
+__device__ __forceinline__ void canon_tile(const Slots &sl, int64_t tile, const SoaIn &s,
+                                           const uint32_t *__restrict__ key, const uint32_t *__restrict__ start,
+                                           const uint32_t *__restrict__ tmpid, double4 *__restrict__ pos4,
+                                           double *__restrict__ adh_s, uint32_t *__restrict__ id_s,
+                                           uint8_t *__restrict__ state_s, uint32_t *__restrict__ key_s,
+                                           uint32_t *__restrict__ tile_key) {
+    const int64_t i = tile * kBlock + threadIdx.x;
+    const int slot = slot_of_tile(sl, tile);
     if (slot < 0) return;
     const GridDev *g = &sl.grids[slot];
     const SlotDev S = slot_record(sl, slot);
@@ -389,10 +426,21 @@ __global__ __launch_bounds__(kBlock) void k_canon(Slots sl, SoaIn s, const uint3
     pos4[dst] = make_double4(s.x[i], s.y[i], s.z[i], s.d ? 0.5 * s.d[i] : 0.0);  // radius, exact
     if (s.adh) adh_s[dst] = s.adh[i];
     id_s[dst] = me;
+    key_s[dst] = k;
     if (s.state) state_s[dst] = s.state[i];
     if (tile_key) {  // key of every tile's first agent (plain calls only: one slot, base 0)
         if ((dst & (kBlock - 1)) == 0) tile_key[dst / kBlock] = k;
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_canon(Slots sl, int64_t ntiles, SoaIn s, const uint32_t *__restrict__ key,
+                                                  const uint32_t *__restrict__ start,
+                                                  const uint32_t *__restrict__ tmpid,
+                                                  double4 *__restrict__ pos4, double *__restrict__ adh_s,
+                                                  uint32_t *__restrict__ id_s, uint8_t *__restrict__ state_s,
+                                                  uint32_t *__restrict__ key_s, uint32_t *__restrict__ tile_key) {
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+        canon_tile(sl, tile, s, key, start, tmpid, pos4, adh_s, id_s, state_s, key_s, tile_key);
 }
 
 // Processing order of the mechanics tiles of a plain call: counting sort of the tiles (256
@@ -474,20 +522,31 @@ static inline unsigned blocks_for(int64_t n, int64_t per = kBlock) {
     return unsigned(b < 1 ? 1 : b);
 }
 
+// Workgroups of a per-tile launch: one per tile for a plain call; a batch strides over its
+// tiles with at most kBatchGrid workgroups, so empty capacity costs a table read, not a dispatch.
+unsigned tile_grid(const Slots &sl, int64_t ntiles) {
+    const int64_t cap = 8192;
+    if (ntiles < 1) return 1;
+    return unsigned(sl.table && ntiles > cap ? cap : ntiles);
+}
+
 void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, const Ws &w, hipStream_t st) {
     const bool has_d = sl.table ? true : sl.one.has_d != 0;
     const double *d = has_d ? s.diam : nullptr;
-    hipLaunchKernelGGL(k_bounds, dim3(blocks_for(capacity, kBoundsTile)), dim3(kBlock), 0, st, sl, s.n,
-                       s.x, s.y, s.z, d, w.tiles, w.lay.max_tiles);
-    hipLaunchKernelGGL(k_finalize, dim3(blocks_for(sl.nslots, 64)), dim3(64), 0, st, sl, s.n);
-    const unsigned nb = blocks_for(capacity);
-    hipLaunchKernelGGL(k_key_count, dim3(nb), dim3(kBlock), 0, st, sl, s.x, s.y, s.z, w.count, w.key, w.rank);
+    const int64_t nbt = (capacity + kBoundsTile - 1) / kBoundsTile;
+    hipLaunchKernelGGL(k_bounds, dim3(tile_grid(sl, nbt)), dim3(kBlock), 0, st, sl, nbt, s.n, s.x, s.y, s.z, d,
+                       w.partials, w.tiles, w.lay.max_tiles);
+    hipLaunchKernelGGL(k_finalize, dim3(unsigned(sl.nslots)), dim3(kBlock), 0, st, sl, s.n, w.partials);
+    const int64_t nt = (capacity + kBlock - 1) / kBlock;
+    const unsigned nb = tile_grid(sl, nt);
+    hipLaunchKernelGGL(k_key_count, dim3(nb), dim3(kBlock), 0, st, sl, nt, s.x, s.y, s.z, w.count, w.key, w.rank);
     launch_scan(w.count, w.start, nullptr, w.lay.max_boxes, w, 1, false, st);
-    hipLaunchKernelGGL(k_scatter_id, dim3(nb), dim3(kBlock), 0, st, sl, w.key, w.rank, w.start, s.id, w.tmpid);
+    hipLaunchKernelGGL(k_scatter_id, dim3(nb), dim3(kBlock), 0, st, sl, nt, w.key, w.rank, w.start, s.id, w.tmpid);
     SoaIn in{s.x, s.y, s.z, d, s.adh, s.id, s.state};
     uint32_t *tile_key = sl.table ? nullptr : w.rankid;  // plain calls reuse the rank-by-id area
-    hipLaunchKernelGGL(k_canon, dim3(nb), dim3(kBlock), 0, st, sl, in, w.key, w.start, w.tmpid, w.pos4, w.adh,
-                       w.ids, w.state, tile_key);
+    // the sorted agents' keys go to the rank array, which nothing reads after the scatter
+    hipLaunchKernelGGL(k_canon, dim3(nb), dim3(kBlock), 0, st, sl, nt, in, w.key, w.start, w.tmpid, w.pos4, w.adh,
+                       w.ids, w.state, w.rank, tile_key);
     if (!sl.table && !sl.one.periodic)
         hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, w.grid, tile_key, w.flagid,
                            int64_t(w.lay.ntiles));

@@ -8,10 +8,9 @@
 //
 // The work is split in two so that the wavefront does not pay the expensive exact law for
 // every candidate of every lane:
-//   1. candidate stream: each lane walks its 9 runs as one flattened stream (run table in LDS,
-//      the next 32-byte record prefetched while the current one is tested) and keeps the
-//      candidates that pass a cheap conservative squared-distance test in a small per-lane
-//      queue in LDS;
+//   1. candidate stream: each lane walks its 9 runs as one flattened stream (run table in LDS)
+//      and keeps the candidates that pass a cheap conservative squared-distance test in a small
+//      per-lane queue in LDS;
 //   2. exact pass: the queued candidates, still in canonical order, are re-read and evaluated
 //      exactly as the definition spells the law (binary64 or binary32) and summed.
 // The packed record holds (x, y, z, r) with r = d/2.
@@ -80,89 +79,78 @@ __device__ __forceinline__ void load_runs(const GridDev *__restrict__ g, const u
     }
 }
 
-// Summed force on the agent at sorted position q (canonical order), then gate/clamp/move.
-template <bool F32>
+// Packed-record loads: a raw buffer resource with 32-bit byte offsets when the sorted array
+// is below 4 GiB (one shift per address, out-of-range offsets read zero), else global loads.
+struct RecBuf {
+    void *base;
+    uint32_t bytes;
+    __device__ __forceinline__ double4 operator()(uint32_t j) const {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, 0, bytes, 0x00020000);
+        const uint32_t off = j * 32u;
+        const auto lo = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        const auto hi = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16u, 0, 0);
+        const double2 a = __builtin_bit_cast(double2, lo), c = __builtin_bit_cast(double2, hi);
+        return make_double4(a.x, a.y, c.x, c.y);
+    }
+};
+struct RecGlobal {
+    const double4 *__restrict__ p;
+    __device__ __forceinline__ double4 operator()(uint32_t j) const { return p[j]; }
+};
+
+// Summed force on the agent at sorted position q with box key `key` (canonical order).
+template <bool F32, class Rec>
 __device__ __forceinline__ void mech_agent(const GridDev *__restrict__ g, const SlotDev &S, uint32_t q,
-                                           const double4 *__restrict__ pos4, const uint32_t *__restrict__ start,
+                                           uint32_t key, const Rec &rec, const uint32_t *__restrict__ start,
                                            uint2 (*s_run)[kBlock], uint32_t (*s_q)[kBlock], int t,
                                            double &fx, double &fy, double &fz, double4 &p) {
-    const double b = g->b;
-    p = pos4[q];
-    const int cx = box_coord(p.x, b, g->cmin[0], g->dims[0], false);
-    const int cy = box_coord(p.y, b, g->cmin[1], g->dims[1], false);
-    const int cz = box_coord(p.z, b, g->cmin[2], g->dims[2], false);
-    load_runs(g, start, cx, cy, cz, s_run, t);
+    p = rec(q);
+    const uint32_t row = fastdiv(key, g->div_nx);
+    const int cx = int(key - row * uint32_t(g->dims[0]));
+    const uint32_t cz = fastdiv(row, g->div_ny);
+    const int cy = int(row - cz * uint32_t(g->dims[1]));
+    load_runs(g, start, cx, cy, int(cz), s_run, t);
     const float rif = float(p.w);
     fx = 0.0;
     fy = 0.0;
     fz = 0.0;
-    int qn = 0;
-    // flattened candidate stream over the 9 runs; (r, j, end) is the next slot to fetch
+    // flattened candidate stream over the 9 runs; the inner loop only fills the queue (so the
+    // force sums are not carried through it), the outer loop empties it in order
     int r = 0;
     uint2 run = s_run[0][t];
     uint32_t j = run.x, end = run.y;
-    while (j >= end && r < 8) {
-        run = s_run[++r][t];
-        j = run.x;
-        end = run.y;
-    }
-    bool have = j < end;
-    uint32_t jc = j;
-    double qx = 0.0, qy = 0.0, qz = 0.0, qr = 0.0;
-    if (have) {
-        const double4 c = pos4[jc];
-        qx = c.x; qy = c.y; qz = c.z; qr = c.w;
-    }
-    ++j;
-    while (have) {
-        while (j >= end && r < 8) {
-            run = s_run[++r][t];
-            j = run.x;
-            end = run.y;
-        }
-        const bool have_n = j < end;
-        const uint32_t jn = j;
-        double nx_ = 0.0, ny_ = 0.0, nz_ = 0.0, nr_ = 0.0;
-        if (have_n) {  // prefetch the next record while the current one is tested
-            const double4 c = pos4[jn];
-            nx_ = c.x; ny_ = c.y; nz_ = c.z; nr_ = c.w;
-        }
-        ++j;
-        const double dx = p.x - qx, dy = p.y - qy, dz = p.z - qz;
-        const double d2 = (dx * dx + dy * dy) + dz * dz;
-        if (maybe_touch(d2, p.w + qr) && jc != q) {
-            s_q[qn][t] = jc;
-            if (++qn == kQueue) {
-                for (int c = 0; c < kQueue; ++c) exact_pair<F32>(p, pos4[s_q[c][t]], rif, S, fx, fy, fz);
-                qn = 0;
+    bool done = false;
+    while (!done) {
+        int qn = 0;
+        for (;;) {
+            while (j >= end && r < 8) {
+                run = s_run[++r][t];
+                j = run.x;
+                end = run.y;
             }
+            if (j >= end) {
+                done = true;
+                break;
+            }
+            const double4 c = rec(j);
+            const double dx = p.x - c.x, dy = p.y - c.y, dz = p.z - c.z;
+            const double d2 = (dx * dx + dy * dy) + dz * dz;
+            if (maybe_touch(d2, p.w + c.w) && j != q) s_q[qn++][t] = j;
+            ++j;
+            if (qn == kQueue) break;
         }
-        jc = jn;
-        qx = nx_; qy = ny_; qz = nz_; qr = nr_;
-        have = have_n;
+        for (int k = 0; k < qn; ++k) exact_pair<F32>(p, rec(s_q[k][t]), rif, S, fx, fy, fz);
     }
-    for (int c = 0; c < qn; ++c) exact_pair<F32>(p, pos4[s_q[c][t]], rif, S, fx, fy, fz);
 }
 
-// precision: 64 or 32 for a plain call; 0 = per slot (batch)
-template <int kPrec>
-__global__ __launch_bounds__(kBlock) void k_mech(Slots sl, const uint32_t *__restrict__ order,
-                                                 const double4 *__restrict__ pos4,
-                                                 const double *__restrict__ adh_s,
-                                                 const uint32_t *__restrict__ id_s,
-                                                 const uint8_t *__restrict__ state_s,
-                                                 const uint32_t *__restrict__ start, bdm_soa out) {
-    __shared__ uint2 s_run[9][kBlock];
-    __shared__ uint32_t s_q[kQueue][kBlock];
+// One tile: 256 agents of one slot.  precision: 64 or 32 for a plain call; 0 = per slot.
+template <int kPrec, class Rec>
+__device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const Rec &rec,
+                                          const double *__restrict__ adh_s, const uint32_t *__restrict__ id_s,
+                                          const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
+                                          const uint32_t *__restrict__ start, const bdm_soa &out,
+                                          uint2 (*s_run)[kBlock], uint32_t (*s_q)[kBlock]) {
     const int t = threadIdx.x;
-    int64_t tile = blockIdx.x;
-    if (order) {  // plain call: pencil order, one contiguous part of it per XCD
-        const GridDev *g0 = &sl.grids[0];
-        if (!g0->valid) return;
-        const uint32_t live_tiles = uint32_t((g0->n + kBlock - 1) / kBlock);
-        if (blockIdx.x >= live_tiles) return;
-        tile = order[xcd_tile(blockIdx.x, live_tiles)];
-    }
     const int slot = slot_of_tile(sl, tile);
     if (slot < 0) return;
     const GridDev *g = &sl.grids[slot];
@@ -173,10 +161,11 @@ __global__ __launch_bounds__(kBlock) void k_mech(Slots sl, const uint32_t *__res
     double fx, fy, fz;
     double4 p;
     const bool f32 = kPrec == 32 || (kPrec == 0 && S.force_bits == 32);
+    const uint32_t key = key_s[q];
     if (f32)
-        mech_agent<true>(g, S, q, pos4, start + S.box_off, s_run, s_q, t, fx, fy, fz, p);
+        mech_agent<true>(g, S, q, key, rec, start + S.box_off, s_run, s_q, t, fx, fy, fz, p);
     else
-        mech_agent<false>(g, S, q, pos4, start + S.box_off, s_run, s_q, t, fx, fy, fz, p);
+        mech_agent<false>(g, S, q, key, rec, start + S.box_off, s_run, s_q, t, fx, fy, fz, p);
 
     // adherence gate, clamp, integrate (binary64)
     const double adh = adh_s[q];
@@ -206,6 +195,28 @@ __global__ __launch_bounds__(kBlock) void k_mech(Slots sl, const uint32_t *__res
     if (out.fx) __builtin_nontemporal_store(fx, &out.fx[o]);
     if (out.fy) __builtin_nontemporal_store(fy, &out.fy[o]);
     if (out.fz) __builtin_nontemporal_store(fz, &out.fz[o]);
+}
+
+template <int kPrec, class Rec>
+__global__ __launch_bounds__(kBlock) void k_mech(Slots sl, int64_t ntiles, const uint32_t *__restrict__ order, Rec rec,
+                                                 const double *__restrict__ adh_s,
+                                                 const uint32_t *__restrict__ id_s,
+                                                 const uint8_t *__restrict__ state_s,
+                                                 const uint32_t *__restrict__ key_s,
+                                                 const uint32_t *__restrict__ start, bdm_soa out) {
+    __shared__ uint2 s_run[9][kBlock];
+    __shared__ uint32_t s_q[kQueue][kBlock];
+    if (order) {  // plain call: pencil order, one contiguous part of it per XCD
+        const GridDev *g0 = &sl.grids[0];
+        if (!g0->valid) return;
+        const uint32_t live_tiles = uint32_t((g0->n + kBlock - 1) / kBlock);
+        if (blockIdx.x >= live_tiles) return;
+        mech_tile<kPrec>(sl, order[xcd_tile(blockIdx.x, live_tiles)], rec, adh_s, id_s, state_s, key_s, start, out,
+                         s_run, s_q);
+        return;
+    }
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)  // batch: stride over the tiles
+        mech_tile<kPrec>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q);
 }
 
 // Test hook: contact lists per sorted slot in force-sum order (mechanical contact, plain calls).
@@ -251,20 +262,32 @@ __global__ __launch_bounds__(kBlock) void k_contacts_mech(Slots sl, const double
     counts[s] = c;
 }
 
+template <class Rec>
+static void launch_mech_rec(const bdm_soa &s, const Slots &sl, int64_t ntiles, unsigned nb, int precision,
+                            const uint32_t *order, const Rec &rec, const Ws &w, hipStream_t st) {
+    if (precision == 32)
+        hipLaunchKernelGGL((k_mech<32, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, ntiles, order, rec, w.adh, w.ids,
+                           w.state, w.rank, w.start, s);
+    else if (precision == 64)
+        hipLaunchKernelGGL((k_mech<64, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, ntiles, order, rec, w.adh, w.ids,
+                           w.state, w.rank, w.start, s);
+    else
+        hipLaunchKernelGGL((k_mech<0, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, ntiles, order, rec, w.adh, w.ids,
+                           w.state, w.rank, w.start, s);
+}
+
 void launch_mech(const bdm_soa &s, const Slots &sl, int64_t capacity, int precision, const Ws &w,
                  hipStream_t st) {
-    int64_t nb = (capacity + kBlock - 1) / kBlock;
-    if (nb < 1) nb = 1;
+    const int64_t ntiles = (capacity + kBlock - 1) / kBlock;
+    const unsigned nb = tile_grid(sl, ntiles);
     const uint32_t *order = sl.table ? nullptr : w.flagid;  // plain: order built with the grid
-    if (precision == 32)
-        hipLaunchKernelGGL(k_mech<32>, dim3(unsigned(nb)), dim3(kBlock), 0, st, sl, order, w.pos4, w.adh, w.ids,
-                           w.state, w.start, s);
-    else if (precision == 64)
-        hipLaunchKernelGGL(k_mech<64>, dim3(unsigned(nb)), dim3(kBlock), 0, st, sl, order, w.pos4, w.adh, w.ids,
-                           w.state, w.start, s);
-    else
-        hipLaunchKernelGGL(k_mech<0>, dim3(unsigned(nb)), dim3(kBlock), 0, st, sl, order, w.pos4, w.adh, w.ids,
-                           w.state, w.start, s);
+    const uint64_t bytes = uint64_t(w.lay.capacity) * 32u;
+    if (bytes <= 0xFFFFFFE0ull) {
+        RecBuf rec{static_cast<void *>(w.pos4), uint32_t(bytes)};
+        launch_mech_rec(s, sl, ntiles, nb, precision, order, rec, w, st);
+    } else {
+        launch_mech_rec(s, sl, ntiles, nb, precision, order, RecGlobal{w.pos4}, w, st);
+    }
 }
 
 void launch_contacts_mech(int f32, const Slots &sl, const Ws &w, uint32_t *counts, const int64_t *offsets,

@@ -44,6 +44,8 @@ struct ContactArgs {
     double L, half, r2;
 };
 
+// Workgroups of a per-tile launch (one per tile for a plain call, capped for a batch).
+unsigned tile_grid(const Slots &sl, int64_t ntiles);
 // Grid build (bounds, finalize, key/histogram, scan, scatter, canonical order) of every slot.
 void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, const Ws &w, hipStream_t st);
 // Exclusive scan of in[0, len) into out[0, len] (len read on the device).

@@ -1,0 +1,61 @@
+"""Host logic of the serving loop: range allocation and the seeded request trace (CPU)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2006_06775_amd.serve import RangeAllocator, box_reserve, cube_edge, make_trace
+
+
+def test_allocator_first_fit_alignment_and_coalescing():
+    a = RangeAllocator(10 * 1024, align=1024)
+    r1 = a.alloc(1500)
+    r2 = a.alloc(1)
+    r3 = a.alloc(3000)
+    assert r1 == (0, 2048) and r2 == (2048, 1024) and r3 == (3072, 3072)
+    assert a.alloc(5000) is None  # only 4096 left
+    a.release(*r2)
+    assert a.alloc(1024) == (2048, 1024)  # first fit reuses the hole
+    a.release(2048, 1024)
+    a.release(*r1)
+    a.release(*r3)
+    assert a.free == [(0, 10 * 1024)] and a.free_total() == 10 * 1024
+
+
+def test_allocator_random_never_overlaps():
+    rng = np.random.default_rng(0)
+    a = RangeAllocator(1 << 20, align=1024)
+    live = []
+    for _ in range(3000):
+        if live and rng.random() < 0.45:
+            k = rng.integers(len(live))
+            a.release(*live.pop(k))
+        else:
+            r = a.alloc(int(rng.integers(1, 60000)))
+            if r is not None:
+                assert r[0] % 1024 == 0 and r[0] + r[1] <= 1 << 20
+                for s, l in live:
+                    assert r[0] + r[1] <= s or s + l <= r[0]
+                live.append(r)
+        assert a.free_total() + sum(l for _, l in live) == 1 << 20
+
+
+def test_trace_is_seeded_and_in_range():
+    t1 = make_trace(512, seed=0, rate=50.0)
+    t2 = make_trace(512, seed=0, rate=50.0)
+    assert [(r.arrival, r.n, r.steps) for r in t1] == [(r.arrival, r.n, r.steps) for r in t2]
+    ns = np.array([r.n for r in t1])
+    st = np.array([r.steps for r in t1])
+    assert ns.min() >= 1000 and ns.max() <= 2_000_000 and st.min() >= 10 and st.max() <= 100
+    # log-uniform: the log of n is roughly uniform
+    ln = np.log(ns)
+    assert abs(ln.mean() - 0.5 * (math.log(1e3) + math.log(2e6))) < 0.4
+    gaps = np.diff([r.arrival for r in t1])
+    assert abs(gaps.mean() - 1 / 50.0) < 0.2 / 50.0
+    assert t1[0].arrival == 0.0
+
+
+def test_box_reserve_covers_the_cube():
+    for n in (1000, 4096, 2_000_000):
+        per = round(box_reserve(n, 15.0) ** (1 / 3))
+        assert per * 15.0 >= cube_edge(n) + 3 * 15.0
