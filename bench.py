@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_mech_fp64_n16m.json"),
                     help="HBM bytes per mech_step launch from rocprofv3 counters (optional)")
     ap.add_argument("--no-serve", action="store_true", help="skip the batched/served stream")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the spheroid and SIR runs")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-budget-gib", type=float, default=4.0,
                     help="HBM the server may hold for resident simulations")
@@ -130,7 +131,7 @@ def serving(args):
     import torch
 
     from paper_2006_06775_amd import serve
-    per_agent = 68 + 65 + 4
+    per_agent = 68 + 81 + 4
     cap = int(args.serve_budget_gib * (1 << 30) / (per_agent + 8 * 1.6))
     boxes = int(cap * 1.6)
     slots = 64
@@ -158,6 +159,57 @@ def serving(args):
         "calibration_closed_system": {k: c[k] for k in ("agent_updates_per_s", "wall_s")},
         "agent_updates": b["agent_updates"],
     }
+
+
+def timed_steps(torch, fn, steps):
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for step in range(steps):
+        fn(step)
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) * 1e-3
+
+
+def workloads():
+    """The two other workloads on the same grid, at their full sizes."""
+    import torch
+
+    from paper_2006_06775_amd import bdm
+    out = {}
+    # tumour spheroid: 10^4 cells in a 60 um ball, +5 % volume per step, division at 14 um,
+    # 60 steps (about 2e5 cells at the end), binary64
+    h, g = 0.5 ** (1 / 3), 1.05 ** (1 / 3)
+    steps = 60
+    pop = bdm.Population(300_000, 1 << 22)
+    bdm.generate(pop.soa, bdm.gen(bdm.GEN_BALL, 10_000, 60.0, 14.0 * h, 14.0, 0.4, seed=0))
+    p = bdm.params(grow=g, div_d=14.0, half_cbrt=h, seed=0)
+
+    def sph(step):
+        bdm.sim_step(pop.soa, bdm.MODEL_SPHEROID, p, step, pop.ws)
+    t = timed_steps(torch, sph, steps)
+    n_end = pop.n
+    flags = bdm.status(pop.ws)
+    del pop
+    out["spheroid"] = dict(cells_start=10_000, cells_end=n_end, steps=steps, seconds=t,
+                           steps_per_s=steps / t, flags=flags, precision="fp64")
+    torch.cuda.empty_cache()
+    # SIR: 10^7 points in a periodic 5000^3 cube, box 20 (250^3 boxes), radius 2, p_inf 0.3,
+    # p_rec 0.01, walk 1, 0.1 % infected, 200 steps
+    n, L, steps = 10_000_000, 5000.0, 200
+    pop = bdm.Population(n, 250 ** 3, spheres=False, with_state=True)
+    bdm.generate(pop.soa, bdm.gen(bdm.GEN_SIR, n, L, n_infected=n // 1000, seed=0))
+    p = bdm.params(box=20.0, periodic=1, L=L, r_inf=2.0, p_inf=0.3, p_rec=0.01, walk=1.0, seed=0)
+
+    def sir(step):
+        bdm.sim_step(pop.soa, bdm.MODEL_SIR, p, step, pop.ws)
+    t = timed_steps(torch, sir, steps)
+    out["sir"] = dict(agents=n, steps=steps, seconds=t, agent_updates_per_s=n * steps / t,
+                      final_SIR=bdm.sir_counts(pop.ws), flags=bdm.status(pop.ws))
+    del pop
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(n_sample):
@@ -222,6 +274,7 @@ def main():
     torch.cuda.empty_cache()
 
     served = None if args.no_serve else serving(args)
+    other = None if args.no_workloads else workloads()
     copy_gbps = copy_bandwidth(torch)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_sample)
     out = {
@@ -246,6 +299,7 @@ def main():
         "roofline": roofline,
         "fp32_forces": fp32,
         "served_stream": served,
+        "other_workloads": other,
         "copy_kernel_GBps": round(copy_gbps, 1),
         "cpu_baseline": cpu,
     }

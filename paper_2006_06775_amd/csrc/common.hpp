@@ -64,7 +64,7 @@ struct SlotDev {
 // Byte offsets of every workspace region (256-byte aligned).  `slots` = 0 is a plain
 // workspace (one grid record, slot passed by value); > 0 is a batch of that many slots.
 struct WsLayout {
-    size_t grid, slots, tilemap, partials, count, start, tiles, key, rank, tmpid, pos4, adh, ids, state,
+    size_t grid, slots, tilemap, partials, count, start, tiles, key, rank, tmpid, pos4, pos4f, adh, ids, state,
         flagid, rankid;
     size_t total;
     int64_t capacity, max_boxes, max_tiles, nslots, ntiles;
@@ -98,6 +98,7 @@ inline bool ws_layout(int64_t capacity, int64_t max_boxes, int64_t slots, WsLayo
     L->rank = take(4 * cap);
     L->tmpid = take(4 * cap);
     L->pos4 = take(32 * cap);
+    L->pos4f = take(16 * cap);
     L->adh = take(8 * cap);
     L->ids = take(4 * cap);
     L->state = take(cap);
@@ -122,6 +123,7 @@ struct Ws {
     unsigned long long *tiles;
     uint32_t *key, *rank, *tmpid;
     double4 *pos4;
+    float4 *pos4f;       // binary32 filter copy of pos4 (mechanics slots)
     double *adh;
     uint32_t *ids;
     uint8_t *state;
@@ -143,6 +145,7 @@ inline Ws ws_view(void *base, const WsLayout &L) {
     w.rank = reinterpret_cast<uint32_t *>(p + L.rank);
     w.tmpid = reinterpret_cast<uint32_t *>(p + L.tmpid);
     w.pos4 = reinterpret_cast<double4 *>(p + L.pos4);
+    w.pos4f = reinterpret_cast<float4 *>(p + L.pos4f);
     w.adh = reinterpret_cast<double *>(p + L.adh);
     w.ids = reinterpret_cast<uint32_t *>(p + L.ids);
     w.state = reinterpret_cast<uint8_t *>(p + L.state);

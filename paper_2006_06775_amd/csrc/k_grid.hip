@@ -11,7 +11,8 @@
 //   canon      each agent counts the smaller ids in its box (ascending-id order inside a box)
 //              and copies itself into the sorted copy: (x, y, z, r = d/2) packed as double4
 //              (halving and doubling a binary64 are exact, so d = 2r is recovered bit for bit)
-//              plus its box key
+//              plus its box key, and for mechanics a binary32 copy (x - o, y - o, z - o, r)
+//              relative to the lattice origin o that only the conservative contact pre-test reads
 //   order      one workgroup: the processing order of the mechanics tiles (pencils of rows
 //              swept along z, so that the three z-planes a tile reads stay in one XCD's L2)
 #include "kernels.hpp"
@@ -405,9 +406,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter_id(Slots sl, int64_t ntiles,
 __device__ __forceinline__ void canon_tile(const Slots &sl, int64_t tile, const SoaIn &s,
                                            const uint32_t *__restrict__ key, const uint32_t *__restrict__ start,
                                            const uint32_t *__restrict__ tmpid, double4 *__restrict__ pos4,
-                                           double *__restrict__ adh_s, uint32_t *__restrict__ id_s,
-                                           uint8_t *__restrict__ state_s, uint32_t *__restrict__ key_s,
-                                           uint32_t *__restrict__ tile_key) {
+                                           float4 *__restrict__ pos4f, double *__restrict__ adh_s,
+                                           uint32_t *__restrict__ id_s, uint8_t *__restrict__ state_s,
+                                           uint32_t *__restrict__ key_s, uint32_t *__restrict__ tile_key) {
     const int64_t i = tile * kBlock + threadIdx.x;
     const int slot = slot_of_tile(sl, tile);
     if (slot < 0) return;
@@ -423,7 +424,13 @@ __device__ __forceinline__ void canon_tile(const Slots &sl, int64_t tile, const 
     for (uint32_t j = s0; j < s1; ++j) r += tmpid[j] < me;
     const uint32_t dst = s0 + r;
     if (dst >= s1) return;
-    pos4[dst] = make_double4(s.x[i], s.y[i], s.z[i], s.d ? 0.5 * s.d[i] : 0.0);  // radius, exact
+    const double x = s.x[i], y = s.y[i], z = s.z[i], rad = s.d ? 0.5 * s.d[i] : 0.0;  // radius, exact
+    pos4[dst] = make_double4(x, y, z, rad);
+    if (!S.periodic) {  // binary32 copy relative to the lattice origin, for the contact pre-test
+        const double b = g->b;
+        pos4f[dst] = make_float4(float(x - double(g->cmin[0]) * b), float(y - double(g->cmin[1]) * b),
+                                 float(z - double(g->cmin[2]) * b), float(rad));
+    }
     if (s.adh) adh_s[dst] = s.adh[i];
     id_s[dst] = me;
     key_s[dst] = k;
@@ -436,11 +443,12 @@ __device__ __forceinline__ void canon_tile(const Slots &sl, int64_t tile, const 
 __global__ __launch_bounds__(kBlock) void k_canon(Slots sl, int64_t ntiles, SoaIn s, const uint32_t *__restrict__ key,
                                                   const uint32_t *__restrict__ start,
                                                   const uint32_t *__restrict__ tmpid,
-                                                  double4 *__restrict__ pos4, double *__restrict__ adh_s,
-                                                  uint32_t *__restrict__ id_s, uint8_t *__restrict__ state_s,
-                                                  uint32_t *__restrict__ key_s, uint32_t *__restrict__ tile_key) {
+                                                  double4 *__restrict__ pos4, float4 *__restrict__ pos4f,
+                                                  double *__restrict__ adh_s, uint32_t *__restrict__ id_s,
+                                                  uint8_t *__restrict__ state_s, uint32_t *__restrict__ key_s,
+                                                  uint32_t *__restrict__ tile_key) {
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-        canon_tile(sl, tile, s, key, start, tmpid, pos4, adh_s, id_s, state_s, key_s, tile_key);
+        canon_tile(sl, tile, s, key, start, tmpid, pos4, pos4f, adh_s, id_s, state_s, key_s, tile_key);
 }
 
 // Processing order of the mechanics tiles of a plain call: counting sort of the tiles (256
@@ -545,8 +553,8 @@ void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, cons
     SoaIn in{s.x, s.y, s.z, d, s.adh, s.id, s.state};
     uint32_t *tile_key = sl.table ? nullptr : w.rankid;  // plain calls reuse the rank-by-id area
     // the sorted agents' keys go to the rank array, which nothing reads after the scatter
-    hipLaunchKernelGGL(k_canon, dim3(nb), dim3(kBlock), 0, st, sl, nt, in, w.key, w.start, w.tmpid, w.pos4, w.adh,
-                       w.ids, w.state, w.rank, tile_key);
+    hipLaunchKernelGGL(k_canon, dim3(nb), dim3(kBlock), 0, st, sl, nt, in, w.key, w.start, w.tmpid, w.pos4, w.pos4f,
+                       w.adh, w.ids, w.state, w.rank, tile_key);
     if (!sl.table && !sl.one.periodic)
         hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, w.grid, tile_key, w.flagid,
                            int64_t(w.lay.ntiles));

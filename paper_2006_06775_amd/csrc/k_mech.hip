@@ -25,10 +25,6 @@ namespace bdm {
 
 constexpr int kQueue = 8;  // queued candidates per lane before an exact pass
 
-// A contact needs |x_i - x_j| < r_i + r_j, i.e. d2 < (r_i + r_j)^2 in exact arithmetic; the
-// 1e-4 relative margin covers every rounding of both the binary64 and binary32 evaluations.
-__device__ __forceinline__ bool maybe_touch(double d2, double s) { return d2 < s * s * 1.0001; }
-
 template <bool F32>
 __device__ __forceinline__ void exact_pair(const double4 &p, const double4 &q, float rif, const SlotDev &a,
                                            double &fx, double &fy, double &fz) {
@@ -79,11 +75,12 @@ __device__ __forceinline__ void load_runs(const GridDev *__restrict__ g, const u
     }
 }
 
-// Packed-record loads: a raw buffer resource with 32-bit byte offsets when the sorted array
-// is below 4 GiB (one shift per address, out-of-range offsets read zero), else global loads.
+// Packed-record loads: a raw buffer resource with 32-bit byte offsets when the sorted arrays
+// are below 4 GiB (one shift per address, out-of-range offsets read zero), else global loads.
+// operator() reads the binary64 record (x, y, z, r), f() its binary32 pre-test copy.
 struct RecBuf {
-    void *base;
-    uint32_t bytes;
+    void *base, *basef;
+    uint32_t bytes;  // of the binary64 records (the binary32 copy is half as long)
     __device__ __forceinline__ double4 operator()(uint32_t j) const {
         const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, 0, bytes, 0x00020000);
         const uint32_t off = j * 32u;
@@ -92,39 +89,77 @@ struct RecBuf {
         const double2 a = __builtin_bit_cast(double2, lo), c = __builtin_bit_cast(double2, hi);
         return make_double4(a.x, a.y, c.x, c.y);
     }
+    __device__ __forceinline__ float4 f(uint32_t j) const {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(basef, 0, bytes / 2u, 0x00020000);
+        return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, j * 16u, 0, 0));
+    }
 };
 struct RecGlobal {
     const double4 *__restrict__ p;
+    const float4 *__restrict__ pf;
     __device__ __forceinline__ double4 operator()(uint32_t j) const { return p[j]; }
+    __device__ __forceinline__ float4 f(uint32_t j) const { return pf[j]; }
 };
 
-// Summed force on the agent at sorted position q with box key `key` (canonical order).
-template <bool F32, class Rec>
-__device__ __forceinline__ void mech_agent(const GridDev *__restrict__ g, const SlotDev &S, uint32_t q,
-                                           uint32_t key, const Rec &rec, const uint32_t *__restrict__ start,
-                                           uint2 (*s_run)[kBlock], uint32_t (*s_q)[kBlock], int t,
-                                           double &fx, double &fy, double &fz, double4 &p) {
-    p = rec(q);
+// Absolute slack of the binary32 pre-test of a slot.  Stored coordinates are relative to the
+// lattice origin o and lie within M = (largest dims + 1) * b of it (plus the rounding of x / b
+// at the lattice edges), so each is off by at most 2^-24 M and a difference by at most
+// e = 2^-23 (M + b) (with b >= r_i + r_j >= the distance of any contact).  Then the binary32
+// squared distance exceeds the true one by at most (1 + 2^-24)^3 (2 sqrt(3) d e + 3 e^2); with
+// e doubled, 4 (b + e) e bounds that.  The relative factor 1.001 on (r_i + r_j)^2 covers the
+// rounding of the radii, of their sum and square, and the rounding of every exact law's own
+// contact test.  So no pair that the exact law counts as a contact can fail the pre-test.
+__device__ __forceinline__ float pretest_slack(const GridDev *__restrict__ g) {
+    const double b = g->b;
+    int dm = g->dims[0];
+    if (g->dims[1] > dm) dm = g->dims[1];
+    if (g->dims[2] > dm) dm = g->dims[2];
+    double omax = 0.0;
+    for (int a = 0; a < 3; ++a) omax = fmax(omax, fabs(double(g->cmin[a]) * b));
+    const double M = (double(dm) + 1.0) * b + 0x1p-48 * omax;
+    const double e = 0x1p-22 * (M + b);
+    return float(4.0 * (b + e) * e) * 1.001f;
+}
+
+// Conservative contact pre-test in binary32 (every real contact passes; see pretest_slack).
+__device__ __forceinline__ bool maybe_touch(const float4 &a, const float4 &c, float slack) {
+    const float dx = a.x - c.x, dy = a.y - c.y, dz = a.z - c.z;
+    const float d2 = (dx * dx + dy * dy) + dz * dz;
+    const float s = a.w + c.w;
+    return d2 < (s * s) * 1.001f + slack;
+}
+
+// Box coordinates of a key (x fastest) by fast division.
+__device__ __forceinline__ void key_coords(const GridDev *__restrict__ g, uint32_t key, int &cx, int &cy, int &cz) {
     const uint32_t row = fastdiv(key, g->div_nx);
-    const int cx = int(key - row * uint32_t(g->dims[0]));
-    const uint32_t cz = fastdiv(row, g->div_ny);
-    const int cy = int(row - cz * uint32_t(g->dims[1]));
-    load_runs(g, start, cx, cy, int(cz), s_run, t);
+    cx = int(key - row * uint32_t(g->dims[0]));
+    const uint32_t z = fastdiv(row, g->div_ny);
+    cy = int(row - z * uint32_t(g->dims[1]));
+    cz = int(z);
+}
+
+// Summed force on the agent with record p at sorted position q whose 9 runs are in column
+// `col` of s_run (canonical order); the queue uses this lane's column t.
+template <bool F32, class Rec>
+__device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const double4 &p, const Rec &rec,
+                                            float slack, const uint2 (*s_run)[kBlock], int col,
+                                            uint32_t (*s_q)[kBlock], int t, double &fx, double &fy, double &fz) {
     const float rif = float(p.w);
+    const float4 pf = rec.f(q);
     fx = 0.0;
     fy = 0.0;
     fz = 0.0;
     // flattened candidate stream over the 9 runs; the inner loop only fills the queue (so the
     // force sums are not carried through it), the outer loop empties it in order
     int r = 0;
-    uint2 run = s_run[0][t];
+    uint2 run = s_run[0][col];
     uint32_t j = run.x, end = run.y;
     bool done = false;
     while (!done) {
         int qn = 0;
         for (;;) {
             while (j >= end && r < 8) {
-                run = s_run[++r][t];
+                run = s_run[++r][col];
                 j = run.x;
                 end = run.y;
             }
@@ -132,10 +167,7 @@ __device__ __forceinline__ void mech_agent(const GridDev *__restrict__ g, const 
                 done = true;
                 break;
             }
-            const double4 c = rec(j);
-            const double dx = p.x - c.x, dy = p.y - c.y, dz = p.z - c.z;
-            const double d2 = (dx * dx + dy * dy) + dz * dz;
-            if (maybe_touch(d2, p.w + c.w) && j != q) s_q[qn++][t] = j;
+            if (maybe_touch(pf, rec.f(j), slack) && j != q) s_q[qn++][t] = j;
             ++j;
             if (qn == kQueue) break;
         }
@@ -143,55 +175,120 @@ __device__ __forceinline__ void mech_agent(const GridDev *__restrict__ g, const 
     }
 }
 
+// Work of a lane grows with its agent's candidate count, and a wavefront runs as long as its
+// slowest lane.  Each tile therefore regroups its 256 agents so that every wavefront gets
+// agents of similar counts (a counting sort by count in LDS), computes, stages the results
+// in LDS and writes them back in the original order (coalesced).
+constexpr bool kBalanceWaves = false;
+
 // One tile: 256 agents of one slot.  precision: 64 or 32 for a plain call; 0 = per slot.
+// Every return before the last barrier depends on the tile only, so it is uniform over the
+// workgroup.
 template <int kPrec, class Rec>
 __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const Rec &rec,
                                           const double *__restrict__ adh_s, const uint32_t *__restrict__ id_s,
                                           const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
-                                          const uint32_t *__restrict__ start, const bdm_soa &out,
-                                          uint2 (*s_run)[kBlock], uint32_t (*s_q)[kBlock]) {
+                                          const uint32_t *__restrict__ start_all, const bdm_soa &out,
+                                          uint2 (*s_run)[kBlock], uint32_t (*s_q)[kBlock], uint32_t *s_hist,
+                                          uint32_t *s_perm) {
     const int t = threadIdx.x;
     const int slot = slot_of_tile(sl, tile);
     if (slot < 0) return;
     const GridDev *g = &sl.grids[slot];
     const SlotDev S = slot_record(sl, slot);
-    const int64_t l = tile * kBlock + t - S.agent_off;  // local (sorted) index in the slot
-    if (!g->valid || l >= g->n || l >= S.capacity) return;
-    const uint32_t q = uint32_t(g->sorted_base + l);
-    double fx, fy, fz;
-    double4 p;
+    const int64_t l0 = tile * kBlock - S.agent_off;  // local (sorted) index of lane 0
+    if (!g->valid || l0 >= g->n || l0 >= S.capacity) return;
+    const int64_t nlive = g->n < S.capacity ? g->n : S.capacity;
+    const uint32_t *start = start_all + S.box_off;
     const bool f32 = kPrec == 32 || (kPrec == 0 && S.force_bits == 32);
-    const uint32_t key = key_s[q];
-    if (f32)
-        mech_agent<true>(g, S, q, key, rec, start + S.box_off, s_run, s_q, t, fx, fy, fz, p);
-    else
-        mech_agent<false>(g, S, q, key, rec, start + S.box_off, s_run, s_q, t, fx, fy, fz, p);
+    const float slack = pretest_slack(g);
 
-    // adherence gate, clamp, integrate (binary64)
-    const double adh = adh_s[q];
-    double nxp = p.x, nyp = p.y, nzp = p.z;
-    const double fn = __builtin_sqrt((fx * fx + fy * fy) + fz * fz);
-    if (!(fn < adh)) {
-        double ux = S.dt * fx, uy = S.dt * fy, uz = S.dt * fz;
-        const double len = __builtin_sqrt((ux * ux + uy * uy) + uz * uz);
-        if (len > S.max_disp) {
-            const double sc = S.max_disp / len;
-            ux = ux * sc;
-            uy = uy * sc;
-            uz = uz * sc;
-        }
-        nxp = p.x + ux;
-        nyp = p.y + uy;
-        nzp = p.z + uz;
+    // own agent: its 9 runs (column t of s_run) and its candidate count
+    const bool live = l0 + t < nlive;
+    uint32_t cnt = 0;
+    if (live) {
+        int cx, cy, cz;
+        key_coords(g, key_s[uint32_t(g->sorted_base + l0 + t)], cx, cy, cz);
+        load_runs(g, start, cx, cy, cz, s_run, t);
+        for (int r = 0; r < 9; ++r) cnt += s_run[r][t].y - s_run[r][t].x;
     }
-    const int64_t o = S.agent_off + l;
+    int src = t;  // column (agent of the tile) this lane computes
+    if (kBalanceWaves) {
+        if (t < 128) s_hist[t] = 0u;
+        __syncthreads();
+        const uint32_t bin = live ? 126u - (cnt < 126u ? cnt : 126u) : 127u;  // most work first
+        const uint32_t rk = atomicAdd(&s_hist[bin], 1u);
+        __syncthreads();
+        if (t < 64) {  // exclusive scan of the 128 bins by the first wavefront
+            const uint32_t a = s_hist[2 * t], b = s_hist[2 * t + 1];
+            const uint32_t ex = wave_incl_scan(a + b) - (a + b);
+            s_hist[2 * t] = ex;
+            s_hist[2 * t + 1] = ex + a;
+        }
+        __syncthreads();
+        s_perm[s_hist[bin] + rk] = uint32_t(t);
+        __syncthreads();
+        src = int(s_perm[t]);
+    }
+
+    const uint32_t qs = uint32_t(g->sorted_base + l0 + src);
+    double fx = 0.0, fy = 0.0, fz = 0.0, nxp = 0.0, nyp = 0.0, nzp = 0.0;
+    if (l0 + src < nlive) {
+        const double4 p = rec(qs);
+        if (f32)
+            mech_forces<true>(S, qs, p, rec, slack, s_run, src, s_q, t, fx, fy, fz);
+        else
+            mech_forces<false>(S, qs, p, rec, slack, s_run, src, s_q, t, fx, fy, fz);
+        // adherence gate, clamp, integrate (binary64)
+        const double adh = adh_s[qs];
+        nxp = p.x;
+        nyp = p.y;
+        nzp = p.z;
+        const double fn = __builtin_sqrt((fx * fx + fy * fy) + fz * fz);
+        if (!(fn < adh)) {
+            double ux = S.dt * fx, uy = S.dt * fy, uz = S.dt * fz;
+            const double len = __builtin_sqrt((ux * ux + uy * uy) + uz * uz);
+            if (len > S.max_disp) {
+                const double sc = S.max_disp / len;
+                ux = ux * sc;
+                uy = uy * sc;
+                uz = uz * sc;
+            }
+            nxp = p.x + ux;
+            nyp = p.y + uy;
+            nzp = p.z + uz;
+        }
+    }
+    int wl = src;  // column whose results this lane writes
+    if (kBalanceWaves) {
+        __syncthreads();  // every lane is done with the run table: it stages the results now
+        double *stage = reinterpret_cast<double *>(&s_run[0][0]);
+        stage[0 * kBlock + src] = nxp;
+        stage[1 * kBlock + src] = nyp;
+        stage[2 * kBlock + src] = nzp;
+        stage[3 * kBlock + src] = fx;
+        stage[4 * kBlock + src] = fy;
+        stage[5 * kBlock + src] = fz;
+        __syncthreads();
+        wl = t;
+        nxp = stage[0 * kBlock + t];
+        nyp = stage[1 * kBlock + t];
+        nzp = stage[2 * kBlock + t];
+        fx = stage[3 * kBlock + t];
+        fy = stage[4 * kBlock + t];
+        fz = stage[5 * kBlock + t];
+        __syncthreads();  // the next tile of this workgroup rebuilds the run table
+    }
+    if (l0 + wl >= nlive) return;
+    const uint32_t qw = uint32_t(g->sorted_base + l0 + wl);
+    const int64_t o = S.agent_off + l0 + wl;
     __builtin_nontemporal_store(nxp, &out.x[o]);
     __builtin_nontemporal_store(nyp, &out.y[o]);
     __builtin_nontemporal_store(nzp, &out.z[o]);
-    __builtin_nontemporal_store(2.0 * p.w, &out.diam[o]);
-    __builtin_nontemporal_store(adh, &out.adh[o]);
-    __builtin_nontemporal_store(id_s[q], &out.id[o]);
-    if (out.state) out.state[o] = state_s[q];
+    __builtin_nontemporal_store(2.0 * rec(qw).w, &out.diam[o]);
+    __builtin_nontemporal_store(adh_s[qw], &out.adh[o]);
+    __builtin_nontemporal_store(id_s[qw], &out.id[o]);
+    if (out.state) out.state[o] = state_s[qw];
     if (out.fx) __builtin_nontemporal_store(fx, &out.fx[o]);
     if (out.fy) __builtin_nontemporal_store(fy, &out.fy[o]);
     if (out.fz) __builtin_nontemporal_store(fz, &out.fz[o]);
@@ -206,17 +303,20 @@ __global__ __launch_bounds__(kBlock) void k_mech(Slots sl, int64_t ntiles, const
                                                  const uint32_t *__restrict__ start, bdm_soa out) {
     __shared__ uint2 s_run[9][kBlock];
     __shared__ uint32_t s_q[kQueue][kBlock];
+    __shared__ uint32_t s_hist[128];
+    __shared__ uint32_t s_perm[kBlock];
     if (order) {  // plain call: pencil order, one contiguous part of it per XCD
         const GridDev *g0 = &sl.grids[0];
         if (!g0->valid) return;
         const uint32_t live_tiles = uint32_t((g0->n + kBlock - 1) / kBlock);
         if (blockIdx.x >= live_tiles) return;
         mech_tile<kPrec>(sl, order[xcd_tile(blockIdx.x, live_tiles)], rec, adh_s, id_s, state_s, key_s, start, out,
-                         s_run, s_q);
+                         s_run, s_q, s_hist, s_perm);
         return;
     }
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)  // batch: stride over the tiles
-        mech_tile<kPrec>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q);
+        mech_tile<kPrec>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q, s_hist,
+                         s_perm);
 }
 
 // Test hook: contact lists per sorted slot in force-sum order (mechanical contact, plain calls).
@@ -283,10 +383,10 @@ void launch_mech(const bdm_soa &s, const Slots &sl, int64_t capacity, int precis
     const uint32_t *order = sl.table ? nullptr : w.flagid;  // plain: order built with the grid
     const uint64_t bytes = uint64_t(w.lay.capacity) * 32u;
     if (bytes <= 0xFFFFFFE0ull) {
-        RecBuf rec{static_cast<void *>(w.pos4), uint32_t(bytes)};
+        RecBuf rec{static_cast<void *>(w.pos4), static_cast<void *>(w.pos4f), uint32_t(bytes)};
         launch_mech_rec(s, sl, ntiles, nb, precision, order, rec, w, st);
     } else {
-        launch_mech_rec(s, sl, ntiles, nb, precision, order, RecGlobal{w.pos4}, w, st);
+        launch_mech_rec(s, sl, ntiles, nb, precision, order, RecGlobal{w.pos4, w.pos4f}, w, st);
     }
 }
 

@@ -146,9 +146,9 @@ class Server:
 
     @staticmethod
     def footprint_bytes(n: int, box: float = D_HI) -> int:
-        """HBM a request occupies: packed SoA (68 B/agent) + workspace (65 B/agent and 1/16 of a
+        """HBM a request occupies: packed SoA (68 B/agent) + workspace (81 B/agent and 1/16 of a
         64-byte partial) + 8 B per reserved box."""
-        return int(n * (68 + 65 + 4) + 8 * box_reserve(n, box))
+        return int(n * (68 + 81 + 4) + 8 * box_reserve(n, box))
 
     def fits(self, req: Request) -> bool:
         return req.n <= self.capacity and box_reserve(req.n, self.box) <= self.max_boxes

@@ -46,7 +46,7 @@ def test_workspace_bytes_host_only():
     assert 0 < a < b and a % 256 == 0
     # per agent: packed double4 record 32 B, adherence 8, id 4, key 4, rank 4, scratch id 4,
     # state 1, division flag and rank 4 + 4 = 65 B
-    assert b - a == 4096 * 65 + 4 * 64  # plus one 64-byte bounds partial per 1024 agents
+    assert b - a == 4096 * 81 + 4 * 64  # plus one 64-byte bounds partial per 1024 agents
 
 
 def test_validation_without_gpu():
