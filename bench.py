@@ -101,18 +101,6 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def source_digest(paths):
-    import hashlib
-    h = hashlib.sha256()
-    for p in paths:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
-
-
-MECH_SOURCES = ("paper_2006_06775_amd/csrc/k_mech.hip", "paper_2006_06775_amd/csrc/common.hpp")
-
-
 def measured_traffic(path, n):
     """HBM bytes per mech_step launch from the rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None
     when there is none for this size or the kernel source changed since it was taken."""
@@ -120,7 +108,8 @@ def measured_traffic(path, n):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("n") != n or t.get("source_digest") != source_digest(MECH_SOURCES):
+    from paper_2006_06775_amd.rocprof_summary import source_digest
+    if t.get("n") != n or t.get("source_digest") != source_digest():
         return None
     return t.get("bytes_per_launch")
 
@@ -131,8 +120,8 @@ def serving(args):
     import torch
 
     from paper_2006_06775_amd import serve
-    per_agent = 68 + 81 + 4
-    cap = int(args.serve_budget_gib * (1 << 30) / (per_agent + 8 * 1.6))
+    per_agent = 68 + 85 + 4
+    cap = int(args.serve_budget_gib * (1 << 30) / (per_agent + (4 + 8 / 64) * 1.6))
     boxes = int(cap * 1.6)
     slots = 64
     # closed-system calibration: every request present at t = 0

@@ -57,6 +57,7 @@ extern "C" {
 /* ---- batched form ------------------------------------------------------------------------ */
 #define BDM_MAX_SLOTS 4096      /* slots of one batch */
 #define BDM_SLOT_ALIGN 1024     /* a slot's first agent index is a multiple of this */
+#define BDM_BOX_ALIGN 64        /* a slot's first histogram entry is a multiple of this */
 
 /* ---- generator kinds for bdm_generate ---------------------------------------------------- */
 #define BDM_GEN_CUBE 0  /* uniform in [0, L)^3, diameter uniform in [dlo, dhi) */
@@ -126,7 +127,8 @@ typedef struct bdm_grid_desc {
 
 /* A batch: many independent mechanical simulations packed into one population.  Slot s owns
  * the agent indices [agent_off, agent_off + capacity) of the packed arrays (agent_off a
- * multiple of BDM_SLOT_ALIGN) and the histogram entries [box_off, box_off + max_boxes); its live
+ * multiple of BDM_SLOT_ALIGN) and the histogram entries [box_off, box_off + max_boxes) (box_off a
+ * multiple of BDM_BOX_ALIGN: the grid build sorts boxes in buckets of 64); its live
  * count is soa->n[s] (soa->n points to `slots` int64 counts).  Each slot has its own grid, box
  * edge and parameters, so every agent's arithmetic is the same as in a plain call on that slot
  * alone.  The caller keeps slot ranges disjoint. */

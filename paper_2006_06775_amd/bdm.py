@@ -32,7 +32,7 @@ SYMBOLS = (
     "bdm_batch_init", "bdm_batch_set_slot", "bdm_batch_clear_slot", "bdm_batch_step",
     "bdm_batch_slot_status", "bdm_fp_probe", "bdm_strerror", "bdm_last_error",
 )
-MAX_SLOTS, SLOT_ALIGN = 4096, 1024
+MAX_SLOTS, SLOT_ALIGN, BOX_ALIGN = 4096, 1024, 64
 
 
 class BdmError(RuntimeError):

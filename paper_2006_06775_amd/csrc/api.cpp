@@ -454,6 +454,8 @@ int bdm_batch_set_slot(const bdm_batch *b, int32_t slot, int64_t agent_off, int6
     if (capacity < 1 || agent_off + capacity > b->capacity)
         return fail(BDM_EINVAL, "slot range [%lld, %lld) outside the batch", (long long)agent_off,
                     (long long)(agent_off + capacity));
+    if (box_off % BDM_BOX_ALIGN != 0)
+        return fail(BDM_EINVAL, "box_off must be a multiple of %d", BDM_BOX_ALIGN);
     if (box_off < 0 || max_boxes < 1 || box_off + max_boxes > b->max_boxes)
         return fail(BDM_EINVAL, "slot boxes [%lld, %lld) outside the batch", (long long)box_off,
                     (long long)(box_off + max_boxes));

@@ -21,6 +21,9 @@ constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts of 6
 constexpr int kBoundsTile = 1024;    // agents per workgroup of the bounds reduction
 constexpr int kScanItems = 8;        // items per thread in the decoupled look-back scan
 constexpr int kScanTile = kBlock * kScanItems;
+constexpr int kBucketShift = 6;       // 64 consecutive boxes per bucket of the two-level sort
+constexpr int kBucketBoxes = 1 << kBucketShift;
+constexpr int kOrderBins = 8192;      // largest (y-pencil x z-plane) count of the tile order
 constexpr uint32_t kScanSpinLimit = 1u << 22;  // polls before a look-back gives up
 
 // Philox draw purposes: counter word 0 = purpose + (attempt << 8).
@@ -64,10 +67,10 @@ struct SlotDev {
 // Byte offsets of every workspace region (256-byte aligned).  `slots` = 0 is a plain
 // workspace (one grid record, slot passed by value); > 0 is a batch of that many slots.
 struct WsLayout {
-    size_t grid, slots, tilemap, partials, count, start, tiles, key, rank, tmpid, pos4, pos4f, adh, ids, state,
-        flagid, rankid;
+    size_t grid, slots, tilemap, partials, count, bstart, start, tiles, key, rank, item, tmpid, pos4, pos4f, adh,
+        ids, state, flagid, rankid, order_bins;
     size_t total;
-    int64_t capacity, max_boxes, max_tiles, nslots, ntiles;
+    int64_t capacity, max_boxes, max_tiles, nslots, ntiles, nbuckets;
 };
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -77,7 +80,8 @@ inline bool ws_layout(int64_t capacity, int64_t max_boxes, int64_t slots, WsLayo
         capacity > (int64_t(1) << 32) - 2 - kBoundsTile || max_boxes > (int64_t(1) << 32) - 2)
         return false;
     size_t cap = size_t(capacity), mb = size_t(max_boxes);
-    size_t longest = cap > mb ? cap : mb;
+    const size_t nbk = (mb >> kBucketShift) + 1;  // buckets covering box indices 0..max_boxes
+    size_t longest = cap > nbk ? cap : nbk;       // longest scan: bucket counts or division flags
     size_t tiles = (longest + 1 + kScanTile - 1) / kScanTile + 1;
     size_t ngrid = slots > 0 ? size_t(slots) : 1;
     size_t ntile = (cap + kBlock - 1) / kBlock;
@@ -91,11 +95,13 @@ inline bool ws_layout(int64_t capacity, int64_t max_boxes, int64_t slots, WsLayo
     L->slots = take(slots > 0 ? sizeof(SlotDev) * size_t(slots) : 0);
     L->tilemap = take(slots > 0 ? 4 * ntile : 0);
     L->partials = take(64 * ((cap + kBoundsTile - 1) / kBoundsTile + 1));
-    L->count = take(4 * (mb + 1));
+    L->count = take(4 * (nbk + 1));
+    L->bstart = take(4 * (nbk + 1));
     L->start = take(4 * (mb + 1));
     L->tiles = take(8 * tiles);
     L->key = take(4 * cap);
     L->rank = take(4 * cap);
+    L->item = take(4 * cap);
     L->tmpid = take(4 * cap);
     L->pos4 = take(32 * cap);
     L->pos4f = take(16 * cap);
@@ -104,12 +110,14 @@ inline bool ws_layout(int64_t capacity, int64_t max_boxes, int64_t slots, WsLayo
     L->state = take(cap);
     L->flagid = take(4 * (cap + 1));
     L->rankid = take(4 * (cap + 1));
+    L->order_bins = take(3 * 4 * size_t(kOrderBins));
     L->total = off;
     L->capacity = capacity;
     L->max_boxes = max_boxes;
     L->max_tiles = int64_t(tiles);
     L->nslots = slots;
     L->ntiles = int64_t(ntile);
+    L->nbuckets = int64_t(nbk);
     return true;
 }
 
@@ -119,15 +127,18 @@ struct Ws {
     SlotDev *slots;      // batch only
     int32_t *tilemap;    // batch only: tile -> slot (-1 = none)
     double *partials;    // bounds reduction: 8 values per kBoundsTile agents
-    uint32_t *count, *start;
+    uint32_t *count;     // agents per bucket of 64 boxes (scan input, kept zero between builds)
+    uint32_t *bstart;    // first sorted position of each bucket
+    uint32_t *start;     // first sorted position of each box
     unsigned long long *tiles;
-    uint32_t *key, *rank, *tmpid;
+    uint32_t *key, *rank, *item, *tmpid;
     double4 *pos4;
     float4 *pos4f;       // binary32 filter copy of pos4 (mechanics slots)
     double *adh;
     uint32_t *ids;
     uint8_t *state;
     uint32_t *flagid, *rankid;
+    uint32_t *order_first, *order_last, *order_shift;  // tile-order runs per bin (plain calls)
     WsLayout lay;
 };
 
@@ -139,10 +150,12 @@ inline Ws ws_view(void *base, const WsLayout &L) {
     w.tilemap = L.nslots > 0 ? reinterpret_cast<int32_t *>(p + L.tilemap) : nullptr;
     w.partials = reinterpret_cast<double *>(p + L.partials);
     w.count = reinterpret_cast<uint32_t *>(p + L.count);
+    w.bstart = reinterpret_cast<uint32_t *>(p + L.bstart);
     w.start = reinterpret_cast<uint32_t *>(p + L.start);
     w.tiles = reinterpret_cast<unsigned long long *>(p + L.tiles);
     w.key = reinterpret_cast<uint32_t *>(p + L.key);
     w.rank = reinterpret_cast<uint32_t *>(p + L.rank);
+    w.item = reinterpret_cast<uint32_t *>(p + L.item);
     w.tmpid = reinterpret_cast<uint32_t *>(p + L.tmpid);
     w.pos4 = reinterpret_cast<double4 *>(p + L.pos4);
     w.pos4f = reinterpret_cast<float4 *>(p + L.pos4f);
@@ -151,6 +164,9 @@ inline Ws ws_view(void *base, const WsLayout &L) {
     w.state = reinterpret_cast<uint8_t *>(p + L.state);
     w.flagid = reinterpret_cast<uint32_t *>(p + L.flagid);
     w.rankid = reinterpret_cast<uint32_t *>(p + L.rankid);
+    w.order_first = reinterpret_cast<uint32_t *>(p + L.order_bins);
+    w.order_last = w.order_first + kOrderBins;
+    w.order_shift = w.order_last + kOrderBins;
     w.lay = L;
     return w;
 }
@@ -271,6 +287,17 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t nblocks) {
     const uint32_t per = nblocks / 8, rem = nblocks % 8, x = bid % 8, idx = bid / 8;
     return x * per + (x < rem ? x : rem) + idx;
+}
+
+// Tiles [t0, t1) of workgroup bid in a per-tile launch of nblocks workgroups over ntiles
+// tiles: one contiguous chunk per workgroup, and the chunks of one XCD's workgroups adjacent,
+// so each XCD streams one contiguous part of the box-sorted arrays and the histogram lines it
+// updates stay in its own L2.
+__device__ __forceinline__ void xcd_chunk(uint32_t bid, uint32_t nblocks, int64_t ntiles, int64_t &t0, int64_t &t1) {
+    const int64_t v = xcd_tile(bid, nblocks);
+    const int64_t per = ntiles / nblocks, rem = ntiles % nblocks;
+    t0 = v * per + (v < rem ? v : rem);
+    t1 = t0 + per + (v < rem ? 1 : 0);
 }
 
 }  // namespace bdm

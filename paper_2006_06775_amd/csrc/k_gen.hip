@@ -76,12 +76,14 @@ __device__ void clear_grid(GridDev *g) {
 // Zero the grid records, the histogram and the scan tiles; empty the batch slot table.
 __global__ __launch_bounds__(kBlock) void k_ws_init(GridDev *g, int64_t ngrid, uint32_t *count, int64_t ncount,
                                                     unsigned long long *tiles, int64_t ntiles, SlotDev *slots,
-                                                    int32_t *tilemap, int64_t ntilemap) {
+                                                    int32_t *tilemap, int64_t ntilemap, uint32_t *runs,
+                                                    int64_t nruns) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t k = i; k < ncount; k += stride) count[k] = 0u;
     for (int64_t k = i; k < ntiles; k += stride) tiles[k] = 0ull;
     for (int64_t k = i; k < ntilemap; k += stride) tilemap[k] = -1;
+    for (int64_t k = i; k < nruns; k += stride) runs[k] = 0xFFFFFFFFu;  // no run in any bin
     for (int64_t k = i; k < ngrid; k += stride) {
         clear_grid(&g[k]);
         if (slots) {
@@ -127,13 +129,14 @@ void launch_fp_probe(const double *a, const double *b, int64_t n, double *os, do
 }
 
 void launch_ws_init(const Ws &w, hipStream_t st) {
-    const int64_t ncount = w.lay.max_boxes + 1;
+    const int64_t ncount = w.lay.nbuckets + 1;
     const int64_t ngrid = w.lay.nslots > 0 ? w.lay.nslots : 1;
     const int64_t nmap = w.lay.nslots > 0 ? w.lay.ntiles : 0;
     int64_t most = ncount > w.lay.max_tiles ? ncount : w.lay.max_tiles;
     if (nmap > most) most = nmap;
+    if (2 * kOrderBins > most) most = 2 * kOrderBins;
     hipLaunchKernelGGL(k_ws_init, dim3(nblocks(most, 4096)), dim3(kBlock), 0, st, w.grid, ngrid, w.count, ncount,
-                       w.tiles, w.lay.max_tiles, w.slots, w.tilemap, nmap);
+                       w.tiles, w.lay.max_tiles, w.slots, w.tilemap, nmap, w.order_first, int64_t(2 * kOrderBins));
 }
 
 void launch_set_slot(const Ws &w, int32_t slot, const SlotDev &rec, int64_t first_tile, int64_t ntile,

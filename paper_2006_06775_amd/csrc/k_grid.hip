@@ -20,7 +20,7 @@
 namespace bdm {
 
 constexpr int kPencilRows = 16;       // y-rows per pencil of the processing order
-constexpr int kOrderBins = 8192;      // largest pencil x z-plane count the order kernel sorts
+constexpr int kBucketLds = 1024;      // agents of a bucket whose ids the sort keeps in LDS
 
 // Per workgroup of kBoundsTile agents: min/max of x, y, z, max diameter and a non-finite flag,
 // written as one 8-value partial record (no atomics).
@@ -121,14 +121,18 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Slots sl, const int64_t *n_
     v[7] = 0.0;
     if (!idle) {
         const int64_t b0 = a.agent_off / kBoundsTile, nb = (n + kBoundsTile - 1) / kBoundsTile;
-        for (int64_t k = threadIdx.x; k < nb; k += blockDim.x) {
-            const double *p = partials + (b0 + k) * 8;
-            for (int i = 0; i < 3; ++i) {
-                v[i] = fmin(v[i], p[i]);
-                v[3 + i] = fmax(v[3 + i], p[3 + i]);
-            }
-            v[6] = fmax(v[6], p[6]);
-            v[7] = fmax(v[7], p[7]);
+        const double4 *p4 = reinterpret_cast<const double4 *>(partials) + 2 * b0;
+#pragma unroll 8
+        for (int64_t k = threadIdx.x; k < nb; k += blockDim.x) {  // 64-byte records, loads in flight
+            const double4 lo = p4[2 * k], hi = p4[2 * k + 1];
+            v[0] = fmin(v[0], lo.x);
+            v[1] = fmin(v[1], lo.y);
+            v[2] = fmin(v[2], lo.z);
+            v[3] = fmax(v[3], lo.w);
+            v[4] = fmax(v[4], hi.x);
+            v[5] = fmax(v[5], hi.y);
+            v[6] = fmax(v[6], hi.z);
+            v[7] = fmax(v[7], hi.w);
         }
     }
     __shared__ double s_red[kBlock][8];
@@ -220,33 +224,78 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Slots sl, const int64_t *n_
     g->valid = 1;
 }
 
-__device__ __forceinline__ void key_count_tile(const Slots &sl, int64_t tile, const double *__restrict__ x,
-                                               const double *__restrict__ y, const double *__restrict__ z,
-                                               uint32_t *count, uint32_t *__restrict__ key,
-                                               uint32_t *__restrict__ rank) {
-    const int64_t i = tile * kBlock + threadIdx.x;
-    const int slot = slot_of_tile(sl, tile);
-    if (slot < 0) return;
-    const GridDev *g = &sl.grids[slot];
-    const SlotDev S = slot_record(sl, slot);
-    if (!g->valid || i - S.agent_off >= g->n) return;
-    const double b = g->b;
-    const bool per = S.periodic != 0;
-    const int cx = box_coord(x[i], b, g->cmin[0], g->dims[0], per);
-    const int cy = box_coord(y[i], b, g->cmin[1], g->dims[1], per);
-    const int cz = box_coord(z[i], b, g->cmin[2], g->dims[2], per);
-    const uint32_t k = uint32_t(cx) + uint32_t(g->dims[0]) * (uint32_t(cy) + uint32_t(g->dims[1]) * uint32_t(cz));
-    key[i] = k;
-    rank[i] = atomicAdd(&count[S.box_off + k], 1u);
+// Box key of every agent and its arrival rank in its bucket (64 consecutive boxes of the packed
+// box range).  Lanes of a wavefront with equal buckets in consecutive lanes (the usual case:
+// the agents arrive in the box order of the previous step) share one atomic: the first lane
+// of each run adds the run length and the others take their offsets from it.  A workgroup
+// handles kKeyTiles tiles at once so that their atomics are in flight together.
+constexpr int kKeyTiles = 4;
+
+struct KeyLane {
+    int64_t i;
+    bool live;
+    uint32_t k, bk, base;
+    int head;
+};
+
+__device__ __forceinline__ KeyLane key_bucket_issue(const Slots &sl, int64_t tile, int64_t ntiles,
+                                                    const double *__restrict__ x, const double *__restrict__ y,
+                                                    const double *__restrict__ z, uint32_t *count) {
+    KeyLane r{};
+    r.i = tile * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    r.head = lane;
+    if (tile < ntiles) {
+        const int slot = slot_of_tile(sl, tile);
+        if (slot >= 0) {
+            const GridDev *g = &sl.grids[slot];
+            const SlotDev S = slot_record(sl, slot);
+            r.live = g->valid && r.i - S.agent_off < g->n;
+            if (r.live) {
+                const double b = g->b;
+                const bool per = S.periodic != 0;
+                const int cx = box_coord(x[r.i], b, g->cmin[0], g->dims[0], per);
+                const int cy = box_coord(y[r.i], b, g->cmin[1], g->dims[1], per);
+                const int cz = box_coord(z[r.i], b, g->cmin[2], g->dims[2], per);
+                r.k = uint32_t(cx) + uint32_t(g->dims[0]) * (uint32_t(cy) + uint32_t(g->dims[1]) * uint32_t(cz));
+                r.bk = uint32_t((uint64_t(S.box_off) + r.k) >> kBucketShift);
+            }
+        }
+    }
+    if (!r.live) r.bk = 0xFFFFFFFFu;
+    const uint32_t prev = __shfl_up(r.bk, 1, 64);
+    const unsigned long long heads = __ballot(r.live && (lane == 0 || prev != r.bk));
+    // this lane's run head: highest head at or below the lane; the run ends at the next head
+    // or at the first dead lane after the head (live lanes of a tile form a prefix)
+    const unsigned long long upto = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+    if (upto) r.head = 63 - __clzll(static_cast<long long>(upto));
+    const unsigned long long after = ~((2ull << r.head) - 1ull);
+    const unsigned long long stop = (heads | ~__ballot(r.live)) & after;
+    const int end = stop ? __ffsll(static_cast<long long>(stop)) - 1 : 64;
+    if (r.live && lane == r.head) r.base = atomicAdd(&count[r.bk], uint32_t(end - r.head));
+    return r;
 }
 
-__global__ __launch_bounds__(kBlock) void k_key_count(Slots sl, int64_t ntiles, const double *__restrict__ x,
-                                                      const double *__restrict__ y,
-                                                      const double *__restrict__ z, uint32_t *count,
-                                                      uint32_t *__restrict__ key,
-                                                      uint32_t *__restrict__ rank) {
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-        key_count_tile(sl, tile, x, y, z, count, key, rank);
+__global__ __launch_bounds__(kBlock) void k_key_bucket(Slots sl, int64_t ntiles, const double *__restrict__ x,
+                                                       const double *__restrict__ y,
+                                                       const double *__restrict__ z, uint32_t *count,
+                                                       uint32_t *__restrict__ key,
+                                                       uint32_t *__restrict__ brank) {
+    int64_t t0, t1;
+    xcd_chunk(blockIdx.x, gridDim.x, ntiles, t0, t1);
+    const int lane = threadIdx.x & 63;
+    for (int64_t tile = t0; tile < t1; tile += kKeyTiles) {
+        KeyLane r[kKeyTiles];
+#pragma unroll
+        for (int u = 0; u < kKeyTiles; ++u) r[u] = key_bucket_issue(sl, tile + u, t1, x, y, z, count);
+#pragma unroll
+        for (int u = 0; u < kKeyTiles; ++u) {
+            const uint32_t base = __shfl(r[u].base, r[u].head, 64);
+            if (!r[u].live) continue;
+            key[r[u].i] = r[u].k;
+            brank[r[u].i] = base + uint32_t(lane - r[u].head);
+        }
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_prepare(unsigned long long *tiles, int64_t max_tiles,
@@ -374,135 +423,289 @@ __global__ __launch_bounds__(kBlock) void k_scan(uint32_t *in, uint32_t *out, co
     }
 }
 
-__device__ __forceinline__ void scatter_tile(const Slots &sl, int64_t tile, const uint32_t *__restrict__ key,
-                                             const uint32_t *__restrict__ rank,
-                                             const uint32_t *__restrict__ start,
-                                             const uint32_t *__restrict__ id, uint32_t *__restrict__ tmpid) {
-    const int64_t i = tile * kBlock + threadIdx.x;
-    const int slot = slot_of_tile(sl, tile);
-    if (slot < 0) return;
-    GridDev *g = &sl.grids[slot];
-    const SlotDev S = slot_record(sl, slot);
-    if (!g->valid || i - S.agent_off >= g->n) return;
-    const uint32_t base = start[S.box_off];
-    if (i == S.agent_off) g->sorted_base = base;
-    const uint32_t pos = start[S.box_off + key[i]] + rank[i];
-    if (pos - base >= uint32_t(g->n)) {  // cannot happen with a zeroed histogram; guards memory
-        atomicOr(&g->flags, BDM_FLAG_SCAN);
-        return;
-    }
-    tmpid[pos] = id[i];
-}
-
-__global__ __launch_bounds__(kBlock) void k_scatter_id(Slots sl, int64_t ntiles, const uint32_t *__restrict__ key,
-                                                       const uint32_t *__restrict__ rank,
-                                                       const uint32_t *__restrict__ start,
-                                                       const uint32_t *__restrict__ id,
-                                                       uint32_t *__restrict__ tmpid) {
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-        scatter_tile(sl, tile, key, rank, start, id, tmpid);
-}
-
-__device__ __forceinline__ void canon_tile(const Slots &sl, int64_t tile, const SoaIn &s,
-                                           const uint32_t *__restrict__ key, const uint32_t *__restrict__ start,
-                                           const uint32_t *__restrict__ tmpid, double4 *__restrict__ pos4,
-                                           float4 *__restrict__ pos4f, double *__restrict__ adh_s,
-                                           uint32_t *__restrict__ id_s, uint8_t *__restrict__ state_s,
-                                           uint32_t *__restrict__ key_s, uint32_t *__restrict__ tile_key) {
-    const int64_t i = tile * kBlock + threadIdx.x;
-    const int slot = slot_of_tile(sl, tile);
-    if (slot < 0) return;
-    const GridDev *g = &sl.grids[slot];
-    const SlotDev S = slot_record(sl, slot);
-    if (!g->valid || i - S.agent_off >= g->n) return;
-    const uint32_t k = key[i];
-    const uint32_t end = start[S.box_off] + uint32_t(g->n);
-    const uint32_t s0 = start[S.box_off + k];
-    const uint32_t s1 = min(start[S.box_off + k + 1], end);
-    const uint32_t me = s.id[i];
-    uint32_t r = 0;
-    for (uint32_t j = s0; j < s1; ++j) r += tmpid[j] < me;
-    const uint32_t dst = s0 + r;
-    if (dst >= s1) return;
-    const double x = s.x[i], y = s.y[i], z = s.z[i], rad = s.d ? 0.5 * s.d[i] : 0.0;  // radius, exact
-    pos4[dst] = make_double4(x, y, z, rad);
-    if (!S.periodic) {  // binary32 copy relative to the lattice origin, for the contact pre-test
-        const double b = g->b;
-        pos4f[dst] = make_float4(float(x - double(g->cmin[0]) * b), float(y - double(g->cmin[1]) * b),
-                                 float(z - double(g->cmin[2]) * b), float(rad));
-    }
-    if (s.adh) adh_s[dst] = s.adh[i];
-    id_s[dst] = me;
-    key_s[dst] = k;
-    if (s.state) state_s[dst] = s.state[i];
-    if (tile_key) {  // key of every tile's first agent (plain calls only: one slot, base 0)
-        if ((dst & (kBlock - 1)) == 0) tile_key[dst / kBlock] = k;
+// Agent indices into their bucket's range of sorted positions, in arrival order (kKeyTiles
+// tiles per workgroup at once, so that their dependent loads overlap).
+__global__ __launch_bounds__(kBlock) void k_bucket_scatter(Slots sl, int64_t ntiles,
+                                                           const uint32_t *__restrict__ key,
+                                                           const uint32_t *__restrict__ brank,
+                                                           const uint32_t *__restrict__ bstart,
+                                                           uint32_t *__restrict__ item, int64_t capacity) {
+    int64_t t0, t1;
+    xcd_chunk(blockIdx.x, gridDim.x, ntiles, t0, t1);
+    for (int64_t tile = t0; tile < t1; tile += kKeyTiles) {
+        int64_t iu[kKeyTiles];
+        uint32_t bk[kKeyTiles], rk[kKeyTiles], pos[kKeyTiles], lim[kKeyTiles];
+        GridDev *gu[kKeyTiles];
+#pragma unroll
+        for (int u = 0; u < kKeyTiles; ++u) {
+            iu[u] = -1;
+            const int64_t t = tile + u;
+            if (t >= t1) continue;
+            const int slot = slot_of_tile(sl, t);
+            if (slot < 0) continue;
+            GridDev *g = &sl.grids[slot];
+            const SlotDev S = slot_record(sl, slot);
+            const int64_t i = t * kBlock + threadIdx.x;
+            if (!g->valid || i - S.agent_off >= g->n) continue;
+            if (i == S.agent_off) g->sorted_base = bstart[S.box_off >> kBucketShift];
+            iu[u] = i;
+            gu[u] = g;
+            bk[u] = uint32_t((uint64_t(S.box_off) + key[i]) >> kBucketShift);
+            rk[u] = brank[i];
+        }
+#pragma unroll
+        for (int u = 0; u < kKeyTiles; ++u)
+            if (iu[u] >= 0) {
+                pos[u] = bstart[bk[u]] + rk[u];
+                lim[u] = bstart[bk[u] + 1];
+            }
+#pragma unroll
+        for (int u = 0; u < kKeyTiles; ++u) {
+            if (iu[u] < 0) continue;
+            if (pos[u] >= uint64_t(capacity) || pos[u] >= lim[u]) {  // cannot happen with zeroed counts
+                atomicOr(&gu[u]->flags, BDM_FLAG_SCAN);
+                continue;
+            }
+            item[pos[u]] = uint32_t(iu[u]);
+        }
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_canon(Slots sl, int64_t ntiles, SoaIn s, const uint32_t *__restrict__ key,
-                                                  const uint32_t *__restrict__ start,
-                                                  const uint32_t *__restrict__ tmpid,
-                                                  double4 *__restrict__ pos4, float4 *__restrict__ pos4f,
-                                                  double *__restrict__ adh_s, uint32_t *__restrict__ id_s,
-                                                  uint8_t *__restrict__ state_s, uint32_t *__restrict__ key_s,
-                                                  uint32_t *__restrict__ tile_key) {
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-        canon_tile(sl, tile, s, key, start, tmpid, pos4, pos4f, adh_s, id_s, state_s, key_s, tile_key);
-}
+// One wavefront per bucket: order the bucket's agents by (box, id) and copy them into the sorted
+// arrays; write the box starts of the bucket's 64 boxes.
+//   1. histogram of the agents' boxes within the bucket (LDS);
+//   2. exclusive scan over the 64 boxes (one box per lane): box starts;
+//   3. each agent's id into its box's range (LDS cursor, arrival order; the ids themselves in
+//      LDS up to kBucketLds agents, else in the scratch id array);
+//   4. each agent counts the smaller ids of its box, which gives its final position, and copies
+//      (x, y, z, r = d/2) packed as a double4 (halving and doubling a binary64 are exact, so d =
+//      2r is recovered bit for bit), its binary32 copy relative to the lattice origin (for the
+//      mechanics pre-test), adh, id, state and its box key there.
+// A bucket holds any number of agents (the wavefront walks them 64 at a time).
+struct SortOut {
+    double4 *pos4;
+    float4 *pos4f;
+    double *adh;
+    uint32_t *id;
+    uint8_t *state;
+    uint32_t *key;       // box key of each sorted agent
+    uint32_t *tile_key;  // key of every tile's first agent (plain calls only)
+};
 
-// Processing order of the mechanics tiles of a plain call: counting sort of the tiles (256
-// consecutive sorted agents) by (pencil of kPencilRows y-rows, z-plane) of their first agent.
-// Every order is correct (each tile is independent); this one keeps the three z-planes a tile
-// reads within a small window.  Falls back to the identity when the grid has too many pencils.
-__global__ __launch_bounds__(1024) void k_tile_order(const GridDev *__restrict__ g,
-                                                     const uint32_t *__restrict__ tile_key,
-                                                     uint32_t *__restrict__ order, int64_t max_tiles) {
-    __shared__ uint32_t s_bin[kOrderBins];
-    __shared__ uint32_t s_part[1024];
-    const int t = threadIdx.x;
-    const int64_t ntile = g->valid ? (g->n + kBlock - 1) / kBlock : 0;
-    const int ny = g->dims[1], nz = g->dims[2], nx = g->dims[0];
-    const int64_t pencils = (int64_t(ny) + kPencilRows - 1) / kPencilRows;
-    const int64_t nbins = pencils * int64_t(nz);
-    if (ntile == 0) return;
-    if (nbins > kOrderBins || nbins <= 0) {
-        for (int64_t c = t; c < ntile && c < max_tiles; c += blockDim.x) order[c] = uint32_t(c);
-        return;
-    }
-    for (int b = t; b < nbins; b += blockDim.x) s_bin[b] = 0u;
-    __syncthreads();
-    auto bin_of = [&](uint32_t k) -> uint32_t {
-        const uint32_t row = k / uint32_t(nx);
-        const uint32_t yy = row % uint32_t(ny), zz = row / uint32_t(ny);
-        return (yy / kPencilRows) * uint32_t(nz) + zz;
+// One sorted agent as the bucket sort carries it.
+struct BucketAgent {
+    int64_t i;      // index in the input arrays
+    int slot;       // its slot (-1: not a valid entry)
+    uint32_t k;     // box key within its slot
+    uint32_t kl;    // box within the bucket (>= 64: skip)
+    uint32_t id;
+    double x, y, z, rad, adh;
+    uint8_t st;
+};
+
+__global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbuckets, int64_t max_boxes,
+                                                        SoaIn s, const uint32_t *__restrict__ key,
+                                                        const uint32_t *__restrict__ bstart,
+                                                        const uint32_t *__restrict__ item,
+                                                        uint32_t *__restrict__ grouped, uint32_t *__restrict__ start,
+                                                        SortOut o, int periodic, int64_t capacity) {
+    __shared__ uint32_t s_hist[kBlock / 64][kBucketBoxes];
+    __shared__ uint32_t s_ls[kBlock / 64][kBucketBoxes];
+    __shared__ uint32_t s_cur[kBlock / 64][kBucketBoxes];
+    __shared__ uint32_t s_grp[kBlock / 64][kBucketLds];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t bk = int64_t(xcd_tile(blockIdx.x, gridDim.x)) * (kBlock / 64) + wave;
+    if (bk >= nbuckets) return;  // (the whole wavefront; no workgroup barrier below)
+    uint32_t *hist = s_hist[wave], *lst = s_ls[wave], *cur = s_cur[wave], *grp = s_grp[wave];
+    const uint32_t b0 = bstart[bk];
+    uint32_t b1 = bstart[bk + 1];
+    if (b1 > uint64_t(capacity)) b1 = uint32_t(capacity);  // (only after a failed scan)
+    const uint32_t m = b1 > b0 ? b1 - b0 : 0u;
+    const bool in_lds = m <= uint32_t(kBucketLds);  // else the grouped ids go through memory
+    const int64_t box0 = bk << kBucketShift;
+    hist[lane] = 0u;
+
+    // the agent of item slot c (kl >= 64 marks an entry to skip: an index or key that cannot
+    // come from a valid build); `full` also loads what the copy needs
+    auto fetch = [&](uint32_t c, bool full) {
+        BucketAgent a{};
+        a.kl = 0xFFFFFFFFu;
+        a.slot = -1;
+        if (c >= m) return a;
+        a.i = item[b0 + c];
+        if (a.i >= capacity) return a;
+        a.slot = slot_of_tile(sl, a.i / kBlock);
+        if (a.slot < 0) return a;
+        const SlotDev S = slot_record(sl, a.slot);
+        a.k = key[a.i];
+        a.kl = uint32_t(int64_t(S.box_off) + int64_t(a.k) - box0);
+        a.id = s.id[a.i];
+        if (full) {
+            a.x = s.x[a.i];
+            a.y = s.y[a.i];
+            a.z = s.z[a.i];
+            a.rad = s.d ? 0.5 * s.d[a.i] : 0.0;  // radius, exact
+            a.adh = s.adh ? s.adh[a.i] : 0.0;
+            a.st = s.state ? s.state[a.i] : 0;
+        }
+        return a;
     };
-    for (int64_t c = t; c < ntile; c += blockDim.x) atomicAdd(&s_bin[bin_of(tile_key[c])], 1u);
-    __syncthreads();
-    // exclusive scan of the bins: each thread owns a contiguous chunk
-    const int per = int((nbins + blockDim.x - 1) / blockDim.x);
-    const int b0 = t * per, b1 = min(int(nbins), b0 + per);
-    uint32_t sum = 0;
-    for (int b = b0; b < b1; ++b) sum += s_bin[b];
+    auto count = [&](const BucketAgent &a) {
+        if (a.kl < uint32_t(kBucketBoxes)) atomicAdd(&hist[a.kl], 1u);
+    };
+    auto group = [&](const BucketAgent &a) {
+        if (a.kl >= uint32_t(kBucketBoxes)) return;
+        const uint32_t p = atomicAdd(&cur[a.kl], 1u);
+        if (in_lds)
+            grp[p] = a.id;
+        else  // through L2 (bypassing L1), read back below by other lanes of this wavefront
+            __hip_atomic_store(&grouped[b0 + p], a.id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    auto emit = [&](const BucketAgent &a) {
+        if (a.kl >= uint32_t(kBucketBoxes)) return;
+        const uint32_t l0 = lst[a.kl], gn = hist[a.kl];
+        uint32_t r = 0;
+        if (in_lds)
+            for (uint32_t j = 0; j < gn; ++j) r += grp[l0 + j] < a.id;
+        else
+            for (uint32_t j = 0; j < gn; ++j)
+                r += __hip_atomic_load(&grouped[b0 + l0 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < a.id;
+        if (r >= gn) return;  // duplicate ids (not a valid population)
+        const uint32_t dst = b0 + l0 + r;
+        o.pos4[dst] = make_double4(a.x, a.y, a.z, a.rad);
+        if (!periodic) {
+            const GridDev *g = &sl.grids[a.slot];
+            const double b = g->b;
+            o.pos4f[dst] = make_float4(float(a.x - double(g->cmin[0]) * b), float(a.y - double(g->cmin[1]) * b),
+                                       float(a.z - double(g->cmin[2]) * b), float(a.rad));
+        }
+        if (s.adh) o.adh[dst] = a.adh;
+        o.id[dst] = a.id;
+        o.key[dst] = a.k;
+        if (s.state) o.state[dst] = a.st;
+        if (o.tile_key && (dst & (kBlock - 1)) == 0) o.tile_key[dst / kBlock] = a.k;
+    };
+    auto starts = [&]() {  // exclusive scan over the bucket's 64 boxes (one per lane)
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t h = hist[lane];
+        const uint32_t ls = wave_incl_scan(h) - h;
+        if (box0 + lane <= max_boxes) start[box0 + lane] = b0 + ls;
+        lst[lane] = ls;
+        cur[lane] = ls;
+        __builtin_amdgcn_wave_barrier();
+    };
+    auto settle = [&]() {  // grouped ids written above complete before they are read below
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    };
+
+    if (m <= 128) {  // the usual bucket: two agents per lane, every load issued up front
+        const BucketAgent a0 = fetch(uint32_t(lane), true), a1 = fetch(uint32_t(lane) + 64u, true);
+        __builtin_amdgcn_wave_barrier();
+        count(a0);
+        count(a1);
+        starts();
+        group(a0);
+        group(a1);
+        settle();
+        emit(a0);
+        emit(a1);
+        return;
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t c = lane; c < m; c += 64) count(fetch(c, false));
+    starts();
+    for (uint32_t c = lane; c < m; c += 64) group(fetch(c, false));
+    settle();
+    for (uint32_t c = lane; c < m; c += 64) emit(fetch(c, true));
+}
+
+// Processing order of the mechanics tiles of a plain call: the tiles (256 consecutive sorted
+// agents) sorted stably by (pencil of kPencilRows y-rows, z-plane) of their first agent.  Every
+// order is correct (each tile is independent); this one keeps the three z-planes a tile reads
+// within a small window.  The tiles' first keys are non-decreasing, so the tiles of one bin
+// form one contiguous run, and the runs come in (z, pencil) order: the order is a permutation
+// of runs, found from each run's ends, a scan over the bins and one write per tile.  Falls
+// back to the identity when the grid has more than kOrderBins bins.
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
+
+struct OrderGeom {
+    int64_t ntile;
+    uint32_t nx, ny, nz, nbins;
+    bool ok;
+    __device__ explicit OrderGeom(const GridDev *g) {
+        ntile = g->valid ? (g->n + kBlock - 1) / kBlock : 0;
+        nx = uint32_t(g->dims[0]);
+        ny = uint32_t(g->dims[1]);
+        nz = uint32_t(g->dims[2]);
+        const int64_t bins = (int64_t(ny) + kPencilRows - 1) / kPencilRows * int64_t(nz);
+        ok = ntile > 0 && nx > 0 && ny > 0 && bins > 0 && bins <= kOrderBins;
+        nbins = ok ? uint32_t(bins) : 0u;
+    }
+    __device__ uint32_t bin(uint32_t k) const {
+        const uint32_t row = k / nx, yy = row % ny, zz = row / ny;
+        const uint32_t b = (yy / kPencilRows) * nz + zz;
+        return b < nbins ? b : nbins - 1u;
+    }
+};
+
+// First and last tile of every bin's run.
+__global__ __launch_bounds__(kBlock) void k_order_runs(const GridDev *__restrict__ g,
+                                                       const uint32_t *__restrict__ tile_key, uint32_t *first,
+                                                       uint32_t *last) {
+    const OrderGeom o(g);
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (!o.ok || c >= o.ntile) return;
+    const uint32_t b = o.bin(tile_key[c]);
+    if (c == 0 || o.bin(tile_key[c - 1]) != b) first[b] = uint32_t(c);
+    if (c == o.ntile - 1 || o.bin(tile_key[c + 1]) != b) last[b] = uint32_t(c);
+}
+
+// One workgroup: exclusive scan of the runs' lengths in (pencil, z) order; shift[b] is set so
+// that tile c of bin b goes to position c + shift[b] (mod 2^32).  Clears the run ends for the
+// next build.
+__global__ __launch_bounds__(1024) void k_order_scan(const GridDev *__restrict__ g, uint32_t *first,
+                                                     uint32_t *last, uint32_t *shift) {
+    __shared__ uint32_t s_part[1024];
+    const OrderGeom o(g);
+    const int t = threadIdx.x;
+    const int per = (kOrderBins + 1023) / 1024;
+    const int b0 = t * per;
+    uint32_t len[per], sum = 0;
+    for (int j = 0; j < per; ++j) {
+        const int b = b0 + j;
+        len[j] = 0;
+        if (o.ok && b < int(o.nbins) && first[b] != kNoTile) len[j] = last[b] - first[b] + 1u;
+        sum += len[j];
+    }
     s_part[t] = sum;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan of the chunk sums
+    for (int off = 1; off < 1024; off <<= 1) {
         const uint32_t v = t >= off ? s_part[t - off] : 0u;
         __syncthreads();
         s_part[t] += v;
         __syncthreads();
     }
     uint32_t run = s_part[t] - sum;
-    for (int b = b0; b < b1; ++b) {
-        const uint32_t c = s_bin[b];
-        s_bin[b] = run;
-        run += c;
+    for (int j = 0; j < per; ++j) {
+        const int b = b0 + j;
+        if (len[j]) shift[b] = run - first[b];
+        run += len[j];
+        first[b] = kNoTile;
+        last[b] = kNoTile;
     }
-    __syncthreads();
-    for (int64_t c = t; c < ntile; c += blockDim.x) {
-        const uint32_t pos = atomicAdd(&s_bin[bin_of(tile_key[c])], 1u);
-        if (pos < max_tiles) order[pos] = uint32_t(c);
-    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_order_write(const GridDev *__restrict__ g,
+                                                        const uint32_t *__restrict__ tile_key,
+                                                        const uint32_t *__restrict__ shift,
+                                                        uint32_t *__restrict__ order, int64_t max_tiles) {
+    const OrderGeom o(g);
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= o.ntile || c >= max_tiles) return;
+    const uint32_t pos = o.ok ? uint32_t(c) + shift[o.bin(tile_key[c])] : uint32_t(c);
+    if (pos < max_tiles) order[pos] = uint32_t(c);
 }
 
 __global__ __launch_bounds__(kBlock) void k_read_agents(const int64_t *n_ptr, const bdm_soa s,
@@ -547,17 +750,30 @@ void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, cons
     hipLaunchKernelGGL(k_finalize, dim3(unsigned(sl.nslots)), dim3(kBlock), 0, st, sl, s.n, w.partials);
     const int64_t nt = (capacity + kBlock - 1) / kBlock;
     const unsigned nb = tile_grid(sl, nt);
-    hipLaunchKernelGGL(k_key_count, dim3(nb), dim3(kBlock), 0, st, sl, nt, s.x, s.y, s.z, w.count, w.key, w.rank);
-    launch_scan(w.count, w.start, nullptr, w.lay.max_boxes, w, 1, false, st);
-    hipLaunchKernelGGL(k_scatter_id, dim3(nb), dim3(kBlock), 0, st, sl, nt, w.key, w.rank, w.start, s.id, w.tmpid);
+    // keys and bucket ranks (rank array), bucket starts, agent indices by bucket
+    const unsigned nbk = tile_grid(sl, (nt + kKeyTiles - 1) / kKeyTiles);
+    hipLaunchKernelGGL(k_key_bucket, dim3(nbk), dim3(kBlock), 0, st, sl, nt, s.x, s.y, s.z, w.count, w.key, w.rank);
+    launch_scan(w.count, w.bstart, nullptr, w.lay.nbuckets, w, 1, false, st);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(nbk), dim3(kBlock), 0, st, sl, nt, w.key, w.rank, w.bstart, w.item,
+                       capacity);
+    // per-bucket order; the sorted agents' keys go to the rank array, which nothing reads after
+    // the scatter; plain calls keep each tile's first key in the rank-by-id area
+    uint32_t *tile_key = sl.table ? nullptr : w.rankid;
+    const int periodic = sl.table ? 0 : sl.one.periodic;
     SoaIn in{s.x, s.y, s.z, d, s.adh, s.id, s.state};
-    uint32_t *tile_key = sl.table ? nullptr : w.rankid;  // plain calls reuse the rank-by-id area
-    // the sorted agents' keys go to the rank array, which nothing reads after the scatter
-    hipLaunchKernelGGL(k_canon, dim3(nb), dim3(kBlock), 0, st, sl, nt, in, w.key, w.start, w.tmpid, w.pos4, w.pos4f,
-                       w.adh, w.ids, w.state, w.rank, tile_key);
-    if (!sl.table && !sl.one.periodic)
-        hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, w.grid, tile_key, w.flagid,
-                           int64_t(w.lay.ntiles));
+    SortOut o{w.pos4, w.pos4f, w.adh, w.ids, w.state, w.rank, tile_key};
+    const int64_t nwg = (w.lay.nbuckets + kBlock / 64 - 1) / (kBlock / 64);
+    hipLaunchKernelGGL(k_bucket_sort, dim3(unsigned(nwg)), dim3(kBlock), 0, st, sl, w.lay.nbuckets,
+                       w.lay.max_boxes, in, w.key, w.bstart, w.item, w.tmpid, w.start, o, periodic, capacity);
+    if (!sl.table && !sl.one.periodic) {
+        const unsigned nto = blocks_for(w.lay.ntiles);
+        hipLaunchKernelGGL(k_order_runs, dim3(nto), dim3(kBlock), 0, st, w.grid, tile_key, w.order_first,
+                           w.order_last);
+        hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, st, w.grid, w.order_first, w.order_last,
+                           w.order_shift);
+        hipLaunchKernelGGL(k_order_write, dim3(nto), dim3(kBlock), 0, st, w.grid, tile_key, w.order_shift,
+                           w.flagid, int64_t(w.lay.ntiles));
+    }
 }
 
 void launch_scan(uint32_t *in, uint32_t *out, const int64_t *len_ptr, int64_t max_len, const Ws &w,

@@ -154,21 +154,51 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
     int r = 0;
     uint2 run = s_run[0][col];
     uint32_t j = run.x, end = run.y;
+    // next candidate position after j (j itself when the stream is exhausted)
+    auto step = [&](uint32_t &jj, uint32_t &ee, int &rr) {
+        ++jj;
+        while (jj >= ee && rr < 8) {
+            const uint2 u = s_run[++rr][col];
+            jj = u.x;
+            ee = u.y;
+        }
+    };
+    while (j >= end && r < 8) {
+        run = s_run[++r][col];
+        j = run.x;
+        end = run.y;
+    }
     bool done = false;
     while (!done) {
         int qn = 0;
+        float4 ca = rec.f(j < end ? j : q), cb;
         for (;;) {
-            while (j >= end && r < 8) {
-                run = s_run[++r][col];
-                j = run.x;
-                end = run.y;
-            }
             if (j >= end) {
                 done = true;
                 break;
             }
-            if (maybe_touch(pf, rec.f(j), slack) && j != q) s_q[qn++][t] = j;
-            ++j;
+            uint32_t jn = j, en = end;
+            int rn = r;
+            step(jn, en, rn);
+            cb = rec.f(jn < en ? jn : q);
+            if (maybe_touch(pf, ca, slack) && j != q) s_q[qn++][t] = j;
+            j = jn;
+            end = en;
+            r = rn;
+            if (qn == kQueue) break;
+            if (j >= end) {
+                done = true;
+                break;
+            }
+            jn = j;
+            en = end;
+            rn = r;
+            step(jn, en, rn);
+            ca = rec.f(jn < en ? jn : q);
+            if (maybe_touch(pf, cb, slack) && j != q) s_q[qn++][t] = j;
+            j = jn;
+            end = en;
+            r = rn;
             if (qn == kQueue) break;
         }
         for (int k = 0; k < qn; ++k) exact_pair<F32>(p, rec(s_q[k][t]), rif, S, fx, fy, fz);
@@ -314,7 +344,9 @@ __global__ __launch_bounds__(kBlock) void k_mech(Slots sl, int64_t ntiles, const
                          s_run, s_q, s_hist, s_perm);
         return;
     }
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)  // batch: stride over the tiles
+    int64_t t0, t1;  // batch: a contiguous chunk of tiles per workgroup, XCD by XCD
+    xcd_chunk(blockIdx.x, gridDim.x, ntiles, t0, t1);
+    for (int64_t tile = t0; tile < t1; ++tile)
         mech_tile<kPrec>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q, s_hist,
                          s_perm);
 }

@@ -134,7 +134,7 @@ class Server:
         self.max_boxes, self.slots, self.box = int(max_boxes), int(slots), float(box)
         self.batch = bdm.Batch(self.capacity, self.max_boxes, self.slots)
         self.agents = RangeAllocator(self.capacity, ALIGN)
-        self.boxes = RangeAllocator(self.max_boxes, 1)
+        self.boxes = RangeAllocator(self.max_boxes, bdm.BOX_ALIGN)
         self.free_slots = list(range(self.slots))[::-1]
         self.running: dict[int, Running] = {}
         self.params = bdm.params(k=2.0, gamma=1.0, dt=0.01, max_disp=3.0, box=self.box, force_bits=32)
@@ -146,9 +146,9 @@ class Server:
 
     @staticmethod
     def footprint_bytes(n: int, box: float = D_HI) -> int:
-        """HBM a request occupies: packed SoA (68 B/agent) + workspace (81 B/agent and 1/16 of a
-        64-byte partial) + 8 B per reserved box."""
-        return int(n * (68 + 81 + 4) + 8 * box_reserve(n, box))
+        """HBM a request occupies: packed SoA (68 B/agent) + workspace (85 B/agent and 1/16 of a
+        64-byte partial) + per reserved box 4 B of box start and 8 B per bucket of 64 boxes."""
+        return int(n * (68 + 85 + 4) + (4 + 8 / 64) * box_reserve(n, box))
 
     def fits(self, req: Request) -> bool:
         return req.n <= self.capacity and box_reserve(req.n, self.box) <= self.max_boxes

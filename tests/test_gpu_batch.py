@@ -47,7 +47,7 @@ def layout(mix):
         nb = bdm.box_count_hint(edge(n), 10.0, 4)
         out.append((off, n, boff, nb))
         off += (n + bdm.SLOT_ALIGN - 1) // bdm.SLOT_ALIGN * bdm.SLOT_ALIGN
-        boff += nb
+        boff += (nb + bdm.BOX_ALIGN - 1) // bdm.BOX_ALIGN * bdm.BOX_ALIGN
     return out, off, boff
 
 
