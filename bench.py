@@ -116,7 +116,9 @@ def measured_traffic(path, n):
 
 def serving(args):
     """Stream of independent simulations (n log-uniform in [1e3, 2e6], 10-100 steps, binary32
-    pair forces): continuous batching vs one-at-a-time plain launches."""
+    pair forces): continuous batching vs one-at-a-time plain launches, as a closed system
+    (every request present at t = 0: capacity) and as a Poisson stream at 0.8 x the batched
+    capacity (latency at the same offered load)."""
     import torch
 
     from paper_2006_06775_amd import serve
@@ -138,6 +140,8 @@ def serving(args):
     torch.cuda.empty_cache()
     p_stats, _ = serve.run_plain(trace)
     p = p_stats.summary()
+    pc_stats, _ = serve.run_plain(calib)  # plain capacity: the same closed system
+    pc = pc_stats.summary()
     return {
         "requests": args.serve_requests, "arrival_rate_per_s": rate, "slots": slots,
         "hbm_budget_gib": args.serve_budget_gib, "force_precision": "fp32 pair law, fp64 positions",
@@ -145,7 +149,11 @@ def serving(args):
                                       "batch_steps", "max_concurrent")},
         "plain": {k: p[k] for k in ("agent_updates_per_s", "p50_latency_s", "p99_latency_s", "wall_s")},
         "batched_over_plain": b["agent_updates_per_s"] / p["agent_updates_per_s"],
-        "calibration_closed_system": {k: c[k] for k in ("agent_updates_per_s", "wall_s")},
+        "closed_system": {
+            "batched": {k: c[k] for k in ("agent_updates_per_s", "wall_s", "p50_latency_s", "p99_latency_s")},
+            "plain": {k: pc[k] for k in ("agent_updates_per_s", "wall_s", "p50_latency_s", "p99_latency_s")},
+            "batched_over_plain": c["agent_updates_per_s"] / pc["agent_updates_per_s"],
+        },
         "agent_updates": b["agent_updates"],
     }
 

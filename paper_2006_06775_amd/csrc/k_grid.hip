@@ -503,6 +503,24 @@ struct BucketAgent {
     uint8_t st;
 };
 
+// A bucket of at most 64 * K agents: K agents per lane held in registers through all phases.
+template <int K, class Fetch, class Count, class Starts, class Group, class Settle, class Emit>
+__device__ __forceinline__ void run_small(int lane, Fetch &fetch, Count &count, Starts &starts, Group &group,
+                                          Settle &settle, Emit &emit) {
+    BucketAgent a[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) a[u] = fetch(uint32_t(lane) + 64u * uint32_t(u), true);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int u = 0; u < K; ++u) count(a[u]);
+    starts();
+#pragma unroll
+    for (int u = 0; u < K; ++u) group(a[u]);
+    settle();
+#pragma unroll
+    for (int u = 0; u < K; ++u) emit(a[u]);
+}
+
 __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbuckets, int64_t max_boxes,
                                                         SoaIn s, const uint32_t *__restrict__ key,
                                                         const uint32_t *__restrict__ bstart,
@@ -600,17 +618,12 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbucke
         __builtin_amdgcn_wave_barrier();
     };
 
-    if (m <= 128) {  // the usual bucket: two agents per lane, every load issued up front
-        const BucketAgent a0 = fetch(uint32_t(lane), true), a1 = fetch(uint32_t(lane) + 64u, true);
-        __builtin_amdgcn_wave_barrier();
-        count(a0);
-        count(a1);
-        starts();
-        group(a0);
-        group(a1);
-        settle();
-        emit(a0);
-        emit(a1);
+    if (m <= 128) {  // the usual bucket: up to two agents per lane, every load issued up front
+        run_small<2>(lane, fetch, count, starts, group, settle, emit);
+        return;
+    }
+    if (m <= 256) {
+        run_small<4>(lane, fetch, count, starts, group, settle, emit);
         return;
     }
     __builtin_amdgcn_wave_barrier();

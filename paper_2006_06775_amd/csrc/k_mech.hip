@@ -57,22 +57,34 @@ __device__ __forceinline__ void exact_pair(const double4 &p, const double4 &q, f
     }
 }
 
-// The 9 key runs of the box (cx, cy, cz) as [lo, hi) ranges of sorted positions.
-__device__ __forceinline__ void load_runs(const GridDev *__restrict__ g, const uint32_t *__restrict__ start,
-                                          int cx, int cy, int cz, uint2 (*s_run)[kBlock], int t) {
+// The 9 key runs of the box (cx, cy, cz) as [lo, hi) ranges of sorted positions, the non-empty
+// ones first in canonical order, then the empty ones, in column t; returns the candidate count.
+__device__ __forceinline__ uint32_t load_runs(const GridDev *__restrict__ g, const uint32_t *__restrict__ start,
+                                              int cx, int cy, int cz, uint2 (*s_run)[kBlock], int t) {
     const int nx = g->dims[0], ny = g->dims[1], nz = g->dims[2];
     const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < nx - 1 ? cx + 1 : nx - 1;
+    uint32_t lo[9], hi[9];
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
         const int zz = cz + r / 3 - 1, yy = cy + r % 3 - 1;
-        uint32_t lo = 0, hi = 0;
+        lo[r] = 0;
+        hi[r] = 0;
         if (zz >= 0 && zz < nz && yy >= 0 && yy < ny) {
             const uint32_t kb = uint32_t(x0) + uint32_t(nx) * (uint32_t(yy) + uint32_t(ny) * uint32_t(zz));
-            lo = start[kb];
-            hi = start[kb + uint32_t(x1 - x0) + 1u];
+            lo[r] = start[kb];
+            hi[r] = start[kb + uint32_t(x1 - x0) + 1u];
         }
-        s_run[r][t] = make_uint2(lo, hi);
     }
+    uint32_t cnt = 0;
+    int k = 0;
+#pragma unroll
+    for (int r = 0; r < 9; ++r)
+        if (hi[r] > lo[r]) {
+            s_run[k++][t] = make_uint2(lo[r], hi[r]);
+            cnt += hi[r] - lo[r];
+        }
+    for (int r = k; r < 9; ++r) s_run[r][t] = make_uint2(0u, 0u);  // empty runs after them
+    return cnt;
 }
 
 // Packed-record loads: a raw buffer resource with 32-bit byte offsets when the sorted arrays
@@ -138,187 +150,117 @@ __device__ __forceinline__ void key_coords(const GridDev *__restrict__ g, uint32
     cz = int(z);
 }
 
-// Summed force on the agent with record p at sorted position q whose 9 runs are in column
-// `col` of s_run (canonical order); the queue uses this lane's column t.
+// Summed force on the agent with record p at sorted position q whose `cnt` candidates are the
+// runs in column `col` of s_run (canonical order); the queue uses this lane's column t.
+// The candidates are walked as one counted stream, two per iteration with the next record
+// loaded one ahead.  Survivors of the pre-test go to the queue (written unconditionally,
+// kept when they pass), which the exact law empties in order when full and at the end.
 template <bool F32, class Rec>
 __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const double4 &p, const Rec &rec,
-                                            float slack, const uint2 (*s_run)[kBlock], int col,
+                                            float slack, const uint2 (*s_run)[kBlock], int col, uint32_t cnt,
                                             uint32_t (*s_q)[kBlock], int t, double &fx, double &fy, double &fz) {
     const float rif = float(p.w);
     const float4 pf = rec.f(q);
     fx = 0.0;
     fy = 0.0;
     fz = 0.0;
-    // flattened candidate stream over the 9 runs; the inner loop only fills the queue (so the
-    // force sums are not carried through it), the outer loop empties it in order
+    int qn = 0;
+    auto flush = [&]() {
+        for (int k = 0; k < qn; ++k) exact_pair<F32>(p, rec(s_q[k][t]), rif, S, fx, fy, fz);
+        qn = 0;
+    };
     int r = 0;
     uint2 run = s_run[0][col];
-    uint32_t j = run.x, end = run.y;
-    // next candidate position after j (j itself when the stream is exhausted)
-    auto step = [&](uint32_t &jj, uint32_t &ee, int &rr) {
+    uint32_t j = run.x, left = run.y - run.x;  // current candidate, candidates left in its run
+    // position after j (a run switch reads the next packed run)
+    auto advance = [&](uint32_t &jj, uint32_t &ll, int &rr) {
         ++jj;
-        while (jj >= ee && rr < 8) {
+        if (--ll == 0 && rr < 8) {
             const uint2 u = s_run[++rr][col];
             jj = u.x;
-            ee = u.y;
+            ll = u.y - u.x;
         }
     };
-    while (j >= end && r < 8) {
-        run = s_run[++r][col];
-        j = run.x;
-        end = run.y;
+    auto visit = [&](uint32_t jj, const float4 &c) {
+        s_q[qn][t] = jj;
+        qn += (maybe_touch(pf, c, slack) && jj != q) ? 1 : 0;
+        if (qn == kQueue) flush();
+    };
+    float4 ca = rec.f(cnt ? j : q), cb;
+    uint32_t c = 0;
+    while (c < cnt) {
+        uint32_t jn = j, ln = left;
+        int rn = r;
+        advance(jn, ln, rn);
+        cb = rec.f(c + 1 < cnt ? jn : q);
+        visit(j, ca);
+        j = jn;
+        left = ln;
+        r = rn;
+        if (++c == cnt) break;
+        advance(jn, ln, rn);
+        ca = rec.f(c + 1 < cnt ? jn : q);
+        visit(j, cb);
+        j = jn;
+        left = ln;
+        r = rn;
+        ++c;
     }
-    bool done = false;
-    while (!done) {
-        int qn = 0;
-        float4 ca = rec.f(j < end ? j : q), cb;
-        for (;;) {
-            if (j >= end) {
-                done = true;
-                break;
-            }
-            uint32_t jn = j, en = end;
-            int rn = r;
-            step(jn, en, rn);
-            cb = rec.f(jn < en ? jn : q);
-            if (maybe_touch(pf, ca, slack) && j != q) s_q[qn++][t] = j;
-            j = jn;
-            end = en;
-            r = rn;
-            if (qn == kQueue) break;
-            if (j >= end) {
-                done = true;
-                break;
-            }
-            jn = j;
-            en = end;
-            rn = r;
-            step(jn, en, rn);
-            ca = rec.f(jn < en ? jn : q);
-            if (maybe_touch(pf, cb, slack) && j != q) s_q[qn++][t] = j;
-            j = jn;
-            end = en;
-            r = rn;
-            if (qn == kQueue) break;
-        }
-        for (int k = 0; k < qn; ++k) exact_pair<F32>(p, rec(s_q[k][t]), rif, S, fx, fy, fz);
-    }
+    flush();
 }
 
-// Work of a lane grows with its agent's candidate count, and a wavefront runs as long as its
-// slowest lane.  Each tile therefore regroups its 256 agents so that every wavefront gets
-// agents of similar counts (a counting sort by count in LDS), computes, stages the results
-// in LDS and writes them back in the original order (coalesced).
-constexpr bool kBalanceWaves = false;
-
-// One tile: 256 agents of one slot.  precision: 64 or 32 for a plain call; 0 = per slot.
-// Every return before the last barrier depends on the tile only, so it is uniform over the
-// workgroup.
+// One tile: 256 agents of one slot, one lane per agent.  precision: 64 or 32 for a plain call;
+// 0 = per slot.
 template <int kPrec, class Rec>
 __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const Rec &rec,
                                           const double *__restrict__ adh_s, const uint32_t *__restrict__ id_s,
                                           const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
                                           const uint32_t *__restrict__ start_all, const bdm_soa &out,
-                                          uint2 (*s_run)[kBlock], uint32_t (*s_q)[kBlock], uint32_t *s_hist,
-                                          uint32_t *s_perm) {
+                                          uint2 (*s_run)[kBlock], uint32_t (*s_q)[kBlock]) {
     const int t = threadIdx.x;
     const int slot = slot_of_tile(sl, tile);
     if (slot < 0) return;
     const GridDev *g = &sl.grids[slot];
     const SlotDev S = slot_record(sl, slot);
-    const int64_t l0 = tile * kBlock - S.agent_off;  // local (sorted) index of lane 0
-    if (!g->valid || l0 >= g->n || l0 >= S.capacity) return;
-    const int64_t nlive = g->n < S.capacity ? g->n : S.capacity;
-    const uint32_t *start = start_all + S.box_off;
+    const int64_t l = tile * kBlock + t - S.agent_off;  // local (sorted) index in the slot
+    if (!g->valid || l >= g->n || l >= S.capacity) return;
     const bool f32 = kPrec == 32 || (kPrec == 0 && S.force_bits == 32);
-    const float slack = pretest_slack(g);
+    const uint32_t q = uint32_t(g->sorted_base + l);
+    int cx, cy, cz;
+    key_coords(g, key_s[q], cx, cy, cz);
+    const uint32_t cnt = load_runs(g, start_all + S.box_off, cx, cy, cz, s_run, t);
+    const double4 p = rec(q);
+    double fx, fy, fz;
+    if (f32)
+        mech_forces<true>(S, q, p, rec, pretest_slack(g), s_run, t, cnt, s_q, t, fx, fy, fz);
+    else
+        mech_forces<false>(S, q, p, rec, pretest_slack(g), s_run, t, cnt, s_q, t, fx, fy, fz);
 
-    // own agent: its 9 runs (column t of s_run) and its candidate count
-    const bool live = l0 + t < nlive;
-    uint32_t cnt = 0;
-    if (live) {
-        int cx, cy, cz;
-        key_coords(g, key_s[uint32_t(g->sorted_base + l0 + t)], cx, cy, cz);
-        load_runs(g, start, cx, cy, cz, s_run, t);
-        for (int r = 0; r < 9; ++r) cnt += s_run[r][t].y - s_run[r][t].x;
-    }
-    int src = t;  // column (agent of the tile) this lane computes
-    if (kBalanceWaves) {
-        if (t < 128) s_hist[t] = 0u;
-        __syncthreads();
-        const uint32_t bin = live ? 126u - (cnt < 126u ? cnt : 126u) : 127u;  // most work first
-        const uint32_t rk = atomicAdd(&s_hist[bin], 1u);
-        __syncthreads();
-        if (t < 64) {  // exclusive scan of the 128 bins by the first wavefront
-            const uint32_t a = s_hist[2 * t], b = s_hist[2 * t + 1];
-            const uint32_t ex = wave_incl_scan(a + b) - (a + b);
-            s_hist[2 * t] = ex;
-            s_hist[2 * t + 1] = ex + a;
+    // adherence gate, clamp, integrate (binary64)
+    const double adh = adh_s[q];
+    double nxp = p.x, nyp = p.y, nzp = p.z;
+    const double fn = __builtin_sqrt((fx * fx + fy * fy) + fz * fz);
+    if (!(fn < adh)) {
+        double ux = S.dt * fx, uy = S.dt * fy, uz = S.dt * fz;
+        const double len = __builtin_sqrt((ux * ux + uy * uy) + uz * uz);
+        if (len > S.max_disp) {
+            const double sc = S.max_disp / len;
+            ux = ux * sc;
+            uy = uy * sc;
+            uz = uz * sc;
         }
-        __syncthreads();
-        s_perm[s_hist[bin] + rk] = uint32_t(t);
-        __syncthreads();
-        src = int(s_perm[t]);
+        nxp = p.x + ux;
+        nyp = p.y + uy;
+        nzp = p.z + uz;
     }
-
-    const uint32_t qs = uint32_t(g->sorted_base + l0 + src);
-    double fx = 0.0, fy = 0.0, fz = 0.0, nxp = 0.0, nyp = 0.0, nzp = 0.0;
-    if (l0 + src < nlive) {
-        const double4 p = rec(qs);
-        if (f32)
-            mech_forces<true>(S, qs, p, rec, slack, s_run, src, s_q, t, fx, fy, fz);
-        else
-            mech_forces<false>(S, qs, p, rec, slack, s_run, src, s_q, t, fx, fy, fz);
-        // adherence gate, clamp, integrate (binary64)
-        const double adh = adh_s[qs];
-        nxp = p.x;
-        nyp = p.y;
-        nzp = p.z;
-        const double fn = __builtin_sqrt((fx * fx + fy * fy) + fz * fz);
-        if (!(fn < adh)) {
-            double ux = S.dt * fx, uy = S.dt * fy, uz = S.dt * fz;
-            const double len = __builtin_sqrt((ux * ux + uy * uy) + uz * uz);
-            if (len > S.max_disp) {
-                const double sc = S.max_disp / len;
-                ux = ux * sc;
-                uy = uy * sc;
-                uz = uz * sc;
-            }
-            nxp = p.x + ux;
-            nyp = p.y + uy;
-            nzp = p.z + uz;
-        }
-    }
-    int wl = src;  // column whose results this lane writes
-    if (kBalanceWaves) {
-        __syncthreads();  // every lane is done with the run table: it stages the results now
-        double *stage = reinterpret_cast<double *>(&s_run[0][0]);
-        stage[0 * kBlock + src] = nxp;
-        stage[1 * kBlock + src] = nyp;
-        stage[2 * kBlock + src] = nzp;
-        stage[3 * kBlock + src] = fx;
-        stage[4 * kBlock + src] = fy;
-        stage[5 * kBlock + src] = fz;
-        __syncthreads();
-        wl = t;
-        nxp = stage[0 * kBlock + t];
-        nyp = stage[1 * kBlock + t];
-        nzp = stage[2 * kBlock + t];
-        fx = stage[3 * kBlock + t];
-        fy = stage[4 * kBlock + t];
-        fz = stage[5 * kBlock + t];
-        __syncthreads();  // the next tile of this workgroup rebuilds the run table
-    }
-    if (l0 + wl >= nlive) return;
-    const uint32_t qw = uint32_t(g->sorted_base + l0 + wl);
-    const int64_t o = S.agent_off + l0 + wl;
+    const int64_t o = S.agent_off + l;
     __builtin_nontemporal_store(nxp, &out.x[o]);
     __builtin_nontemporal_store(nyp, &out.y[o]);
     __builtin_nontemporal_store(nzp, &out.z[o]);
-    __builtin_nontemporal_store(2.0 * rec(qw).w, &out.diam[o]);
-    __builtin_nontemporal_store(adh_s[qw], &out.adh[o]);
-    __builtin_nontemporal_store(id_s[qw], &out.id[o]);
-    if (out.state) out.state[o] = state_s[qw];
+    __builtin_nontemporal_store(2.0 * p.w, &out.diam[o]);
+    __builtin_nontemporal_store(adh, &out.adh[o]);
+    __builtin_nontemporal_store(id_s[q], &out.id[o]);
+    if (out.state) out.state[o] = state_s[q];
     if (out.fx) __builtin_nontemporal_store(fx, &out.fx[o]);
     if (out.fy) __builtin_nontemporal_store(fy, &out.fy[o]);
     if (out.fz) __builtin_nontemporal_store(fz, &out.fz[o]);
@@ -333,22 +275,19 @@ __global__ __launch_bounds__(kBlock) void k_mech(Slots sl, int64_t ntiles, const
                                                  const uint32_t *__restrict__ start, bdm_soa out) {
     __shared__ uint2 s_run[9][kBlock];
     __shared__ uint32_t s_q[kQueue][kBlock];
-    __shared__ uint32_t s_hist[128];
-    __shared__ uint32_t s_perm[kBlock];
     if (order) {  // plain call: pencil order, one contiguous part of it per XCD
         const GridDev *g0 = &sl.grids[0];
         if (!g0->valid) return;
         const uint32_t live_tiles = uint32_t((g0->n + kBlock - 1) / kBlock);
         if (blockIdx.x >= live_tiles) return;
         mech_tile<kPrec>(sl, order[xcd_tile(blockIdx.x, live_tiles)], rec, adh_s, id_s, state_s, key_s, start, out,
-                         s_run, s_q, s_hist, s_perm);
+                         s_run, s_q);
         return;
     }
     int64_t t0, t1;  // batch: a contiguous chunk of tiles per workgroup, XCD by XCD
     xcd_chunk(blockIdx.x, gridDim.x, ntiles, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile)
-        mech_tile<kPrec>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q, s_hist,
-                         s_perm);
+        mech_tile<kPrec>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q);
 }
 
 // Test hook: contact lists per sorted slot in force-sum order (mechanical contact, plain calls).
