@@ -366,41 +366,50 @@ typedef struct {
     int64_t max_boxes;
 } orc_mech_params;
 
-/* Summed force on every agent: for agent i, the 27 boxes around its own are visited in
- * ascending key order and the agents of each box in ascending id, skipping i itself.
- * ncontact (optional) receives each agent's contact count. */
+/* Summed force on agent i: the 27 boxes around its own are visited in ascending key order and
+ * the agents of each box in ascending id, skipping i itself.  Returns the contact count. */
+static uint32_t agent_force(int64_t i, const double *x, const double *y, const double *z,
+                            const double *d, const orc_mech_params *p, const orc_grid *g,
+                            const uint32_t *order, const uint32_t *start, double f_out[3])
+{
+    int64_t cx = box_coord(g, x[i], 0), cy = box_coord(g, y[i], 1), cz = box_coord(g, z[i], 2);
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    uint32_t contacts = 0;
+    for (int oz = -1; oz <= 1; ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                int64_t nk = neighbour_key(g, cx, cy, cz, ox, oy, oz);
+                if (nk < 0) continue;
+                for (uint32_t s = start[nk]; s < start[nk + 1]; ++s) {
+                    uint32_t j = order[s];
+                    if ((int64_t)j == i) continue;
+                    double f[3];
+                    int hit = (p->force_bits == 32)
+                                  ? orc_pair_force_f32(x[i], y[i], z[i], d[i], x[j], y[j], z[j], d[j],
+                                                       p->k, p->gamma, f)
+                                  : orc_pair_force_f64(x[i], y[i], z[i], d[i], x[j], y[j], z[j], d[j],
+                                                       p->k, p->gamma, f);
+                    if (hit) {
+                        contacts += 1;
+                        sx = sx + f[0]; sy = sy + f[1]; sz = sz + f[2];
+                    }
+                }
+            }
+    f_out[0] = sx; f_out[1] = sy; f_out[2] = sz;
+    return contacts;
+}
+
+/* Summed force on every agent.  ncontact (optional) receives each agent's contact count. */
 static int mech_forces(int64_t n, const double *x, const double *y, const double *z,
                        const double *d, const orc_mech_params *p, const orc_grid *g,
-                       const uint32_t *key, const uint32_t *order, const uint32_t *start,
+                       const uint32_t *order, const uint32_t *start,
                        double *fx, double *fy, double *fz, uint32_t *ncontact)
 {
     for (int64_t i = 0; i < n; ++i) {
-        int64_t cx = box_coord(g, x[i], 0), cy = box_coord(g, y[i], 1), cz = box_coord(g, z[i], 2);
-        (void)key;
-        double sx = 0.0, sy = 0.0, sz = 0.0;
-        uint32_t contacts = 0;
-        for (int oz = -1; oz <= 1; ++oz)
-            for (int oy = -1; oy <= 1; ++oy)
-                for (int ox = -1; ox <= 1; ++ox) {
-                    int64_t nk = neighbour_key(g, cx, cy, cz, ox, oy, oz);
-                    if (nk < 0) continue;
-                    for (uint32_t s = start[nk]; s < start[nk + 1]; ++s) {
-                        uint32_t j = order[s];
-                        if ((int64_t)j == i) continue;
-                        double f[3];
-                        int hit = (p->force_bits == 32)
-                                      ? orc_pair_force_f32(x[i], y[i], z[i], d[i], x[j], y[j], z[j],
-                                                           d[j], p->k, p->gamma, f)
-                                      : orc_pair_force_f64(x[i], y[i], z[i], d[i], x[j], y[j], z[j],
-                                                           d[j], p->k, p->gamma, f);
-                        if (hit) {
-                            contacts += 1;
-                            sx = sx + f[0]; sy = sy + f[1]; sz = sz + f[2];
-                        }
-                    }
-                }
-        fx[i] = sx; fy[i] = sy; fz[i] = sz;
-        if (ncontact) ncontact[i] = contacts;
+        double f[3];
+        uint32_t c = agent_force(i, x, y, z, d, p, g, order, start, f);
+        fx[i] = f[0]; fy[i] = f[1]; fz[i] = f[2];
+        if (ncontact) ncontact[i] = c;
     }
     return ORC_OK;
 }
@@ -431,7 +440,7 @@ int orc_mech_step(int64_t n, double *x, double *y, double *z, const double *d, c
     uint32_t *start = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(g.nboxes + 1));
     if (!key || !order || !start) { free(key); free(order); free(start); return ORC_ENOMEM; }
     rc = orc_grid_sort(n, x, y, z, &g, key, order, start);
-    if (!rc) rc = mech_forces(n, x, y, z, d, p, &g, key, order, start, fx, fy, fz, ncontact);
+    if (!rc) rc = mech_forces(n, x, y, z, d, p, &g, order, start, fx, fy, fz, ncontact);
     if (!rc) {
         for (int64_t i = 0; i < n; ++i) {
             double disp[3];
@@ -442,6 +451,36 @@ int orc_mech_step(int64_t n, double *x, double *y, double *z, const double *d, c
             y[i] = y[i] + disp[1];
             z[i] = z[i] + disp[2];
         }
+    }
+    free(key); free(order); free(start);
+    return rc;
+}
+
+/* The summed (pre-gate) forces of the m agents ids[0..m) of one mechanical step on positions
+ * at t, each exactly as orc_mech_step computes it (same grid, same candidate order): for
+ * checking sampled agents of populations too large to step whole on one core. */
+int orc_mech_sample(int64_t n, const double *x, const double *y, const double *z, const double *d,
+                    const orc_mech_params *p, int64_t m, const int64_t *ids, double *fx, double *fy,
+                    double *fz, uint32_t *ncontact)
+{
+    int rc = check_mech_params(p);
+    if (rc) return rc;
+    if (n == 0 || m == 0) return ORC_OK;
+    for (int64_t k = 0; k < m; ++k)
+        if (ids[k] < 0 || ids[k] >= n) return ORC_EINVAL;
+    orc_grid g;
+    rc = orc_grid_setup(n, x, y, z, d, p->box, 0, 0.0, p->max_boxes, &g);
+    if (rc) return rc;
+    uint32_t *key = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+    uint32_t *order = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+    uint32_t *start = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(g.nboxes + 1));
+    if (!key || !order || !start) { free(key); free(order); free(start); return ORC_ENOMEM; }
+    rc = orc_grid_sort(n, x, y, z, &g, key, order, start);
+    for (int64_t k = 0; !rc && k < m; ++k) {
+        double f[3];
+        uint32_t c = agent_force(ids[k], x, y, z, d, p, &g, order, start, f);
+        fx[k] = f[0]; fy[k] = f[1]; fz[k] = f[2];
+        if (ncontact) ncontact[k] = c;
     }
     free(key); free(order); free(start);
     return rc;

@@ -98,6 +98,8 @@ def _declare(L):
     L.orc_displacement.argtypes = [C.c_double] * 6 + [_D]
     L.orc_mech_step.argtypes = [C.c_int64, _D, _D, _D, _D, _D, C.POINTER(_MechParams), _D, _D,
                                 _D, _U32, _U8]
+    L.orc_mech_sample.argtypes = [C.c_int64, _D, _D, _D, _D, C.POINTER(_MechParams), C.c_int64, _I64,
+                                  _D, _D, _D, _U32]
     L.orc_contacts.argtypes = [C.c_int64, _D, _D, _D, _D, C.c_double, C.c_int32, C.c_double,
                                C.c_double, C.c_int32, C.c_int64, _U32, _I64, _U32]
     L.orc_division_axis.argtypes = [C.c_uint64] * 4 + [_D]
@@ -109,7 +111,7 @@ def _declare(L):
     L.orc_sir_step.argtypes = [C.c_int64, _D, _D, _D, _U8, C.POINTER(_SirParams), C.c_int64, _I64]
     for name in ("orc_generate_cube", "orc_generate_ball", "orc_generate_sir", "orc_grid_setup",
                  "orc_grid_sort", "orc_pair_force_f64", "orc_pair_force_f32", "orc_displacement",
-                 "orc_mech_step", "orc_contacts", "orc_grow_divide", "orc_spheroid_step",
+                 "orc_mech_step", "orc_mech_sample", "orc_contacts", "orc_grow_divide", "orc_spheroid_step",
                  "orc_sir_step"):
         getattr(L, name).restype = C.c_int
 
@@ -241,6 +243,23 @@ def mech_step(state, k=2.0, gamma=1.0, dt=0.01, max_disp=3.0, box=0.0, force_bit
                                _p(fy, C.c_double), _p(fz, C.c_double), _p(nc, C.c_uint32),
                                _p(fl, C.c_uint8)), "mech_step")
     return fx, fy, fz, nc, fl
+
+
+def mech_sample(state, ids, k=2.0, gamma=1.0, dt=0.01, max_disp=3.0, box=0.0, force_bits=64,
+                max_boxes=1 << 31):
+    """Summed (pre-gate) forces and contact counts of the agents `ids` in one mechanical step on
+    `state` (not modified), each computed exactly as mech_step does."""
+    x, y, z, d = (_f64(state[k_]) for k_ in ("x", "y", "z", "d"))
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    m = len(ids)
+    p = mech_params(k, gamma, dt, max_disp, box, force_bits, max_boxes)
+    fx, fy, fz = _zeros(m), _zeros(m), _zeros(m)
+    nc = _zeros(m, np.uint32)
+    _check(lib().orc_mech_sample(len(x), _p(x, C.c_double), _p(y, C.c_double), _p(z, C.c_double),
+                                 _p(d, C.c_double), C.byref(p), m, _p(ids, C.c_int64),
+                                 _p(fx, C.c_double), _p(fy, C.c_double), _p(fz, C.c_double),
+                                 _p(nc, C.c_uint32)), "mech_sample")
+    return fx, fy, fz, nc
 
 
 def contacts(x, y, z, d=None, box=0.0, periodic=False, L=0.0, radius=0.0, force_bits=64,

@@ -209,3 +209,16 @@ def test_empty_and_single(orc):
              adh=np.array([0.4]))
     fx, fy, fz, nc, fl = orc.mech_step(s)
     assert fx[0] == 0.0 and nc[0] == 0 and fl[0] == 1 and s["x"][0] == 1.0
+
+
+def test_mech_sample_matches_full_step(orc):
+    """The sampled-agent entry used at full size computes each agent's force exactly as the
+    full step does (same grid, same candidate order)."""
+    st = orc.generate_cube(3000, 7, 180.0, 10.0, 15.0, 0.4)
+    ids = np.array([0, 1, 17, 1500, 2999])
+    for bits in (64, 32):
+        s2 = {k: v.copy() for k, v in st.items()}
+        fx, fy, fz, nc, _ = orc.mech_step(s2, force_bits=bits)
+        sx, sy, sz, snc = orc.mech_sample(st, ids, force_bits=bits)
+        assert np.array_equal(sx, fx[ids]) and np.array_equal(sy, fy[ids]) and np.array_equal(sz, fz[ids])
+        assert np.array_equal(snc, nc[ids])
