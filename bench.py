@@ -170,7 +170,8 @@ def timed_steps(torch, fn, steps):
 
 
 def workloads():
-    """The two other workloads on the same grid, at their full sizes."""
+    """The other workloads on the same grid, at their full sizes: the tumour spheroid (60
+    steps, and on to about 4e6 cells) and the SIR epidemic."""
     import torch
 
     from paper_2006_06775_amd import bdm
@@ -191,6 +192,23 @@ def workloads():
     del pop
     out["spheroid"] = dict(cells_start=10_000, cells_end=n_end, steps=steps, seconds=t,
                            steps_per_s=steps / t, flags=flags, precision="fp64")
+    torch.cuda.empty_cache()
+    # the same growth run on to about 4e6 cells (122 steps); the live count of every step is
+    # copied on the device, so the run never waits for the host
+    steps = 122
+    pop = bdm.Population(5_000_000, 1 << 24)
+    bdm.generate(pop.soa, bdm.gen(bdm.GEN_BALL, 10_000, 60.0, 14.0 * h, 14.0, 0.4, seed=0))
+    counts = torch.zeros(steps, dtype=torch.int64, device="cuda")
+
+    def sph4m(step):
+        bdm.sim_step(pop.soa, bdm.MODEL_SPHEROID, p, step, pop.ws)
+        counts[step:step + 1].copy_(pop.t["n"])
+    t = timed_steps(torch, sph4m, steps)
+    updates = int(counts.sum().item())
+    out["spheroid_4m"] = dict(cells_start=10_000, cells_end=pop.n, steps=steps, seconds=t,
+                              steps_per_s=steps / t, agent_updates_per_s=updates / t,
+                              flags=bdm.status(pop.ws), precision="fp64")
+    del pop, counts
     torch.cuda.empty_cache()
     # SIR: 10^7 points in a periodic 5000^3 cube, box 20 (250^3 boxes), radius 2, p_inf 0.3,
     # p_rec 0.01, walk 1, 0.1 % infected, 200 steps

@@ -525,8 +525,9 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbucke
                                                         SoaIn s, const uint32_t *__restrict__ key,
                                                         const uint32_t *__restrict__ bstart,
                                                         const uint32_t *__restrict__ item,
-                                                        uint32_t *__restrict__ grouped, uint32_t *__restrict__ start,
-                                                        SortOut o, int periodic, int64_t capacity) {
+                                                        uint32_t *__restrict__ grouped, uint32_t *__restrict__ grouped_i,
+                                                        uint32_t *__restrict__ start, SortOut o, int periodic,
+                                                        int64_t capacity) {
     __shared__ uint32_t s_hist[kBlock / 64][kBucketBoxes];
     __shared__ uint32_t s_ls[kBlock / 64][kBucketBoxes];
     __shared__ uint32_t s_cur[kBlock / 64][kBucketBoxes];
@@ -543,30 +544,39 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbucke
     const int64_t box0 = bk << kBucketShift;
     hist[lane] = 0u;
 
-    // the agent of item slot c (kl >= 64 marks an entry to skip: an index or key that cannot
+    // the agent at input index i (kl >= 64 marks an entry to skip: an index or key that cannot
     // come from a valid build); `full` also loads what the copy needs
-    auto fetch = [&](uint32_t c, bool full) {
+    auto from_index = [&](int64_t i, bool full) {
         BucketAgent a{};
         a.kl = 0xFFFFFFFFu;
         a.slot = -1;
-        if (c >= m) return a;
-        a.i = item[b0 + c];
-        if (a.i >= capacity) return a;
-        a.slot = slot_of_tile(sl, a.i / kBlock);
+        a.i = i;
+        if (i < 0 || i >= capacity) return a;
+        a.slot = slot_of_tile(sl, i / kBlock);
         if (a.slot < 0) return a;
         const SlotDev S = slot_record(sl, a.slot);
-        a.k = key[a.i];
+        a.k = key[i];
         a.kl = uint32_t(int64_t(S.box_off) + int64_t(a.k) - box0);
-        a.id = s.id[a.i];
+        a.id = s.id[i];
         if (full) {
-            a.x = s.x[a.i];
-            a.y = s.y[a.i];
-            a.z = s.z[a.i];
-            a.rad = s.d ? 0.5 * s.d[a.i] : 0.0;  // radius, exact
-            a.adh = s.adh ? s.adh[a.i] : 0.0;
-            a.st = s.state ? s.state[a.i] : 0;
+            a.x = s.x[i];
+            a.y = s.y[i];
+            a.z = s.z[i];
+            a.rad = s.d ? 0.5 * s.d[i] : 0.0;  // radius, exact
+            a.adh = s.adh ? s.adh[i] : 0.0;
+            a.st = s.state ? s.state[i] : 0;
         }
         return a;
+    };
+    // the agent of item slot c
+    auto fetch = [&](uint32_t c, bool full) {
+        if (c >= m) {
+            BucketAgent a{};
+            a.kl = 0xFFFFFFFFu;
+            a.slot = -1;
+            return a;
+        }
+        return from_index(int64_t(item[b0 + c]), full);
     };
     auto count = [&](const BucketAgent &a) {
         if (a.kl < uint32_t(kBucketBoxes)) atomicAdd(&hist[a.kl], 1u);
@@ -574,22 +584,14 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbucke
     auto group = [&](const BucketAgent &a) {
         if (a.kl >= uint32_t(kBucketBoxes)) return;
         const uint32_t p = atomicAdd(&cur[a.kl], 1u);
-        if (in_lds)
+        if (in_lds) {
             grp[p] = a.id;
-        else  // through L2 (bypassing L1), read back below by other lanes of this wavefront
+        } else {  // through L2 (bypassing L1), read back below by other lanes of this wavefront
             __hip_atomic_store(&grouped[b0 + p], a.id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&grouped_i[b0 + p], uint32_t(a.i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     };
-    auto emit = [&](const BucketAgent &a) {
-        if (a.kl >= uint32_t(kBucketBoxes)) return;
-        const uint32_t l0 = lst[a.kl], gn = hist[a.kl];
-        uint32_t r = 0;
-        if (in_lds)
-            for (uint32_t j = 0; j < gn; ++j) r += grp[l0 + j] < a.id;
-        else
-            for (uint32_t j = 0; j < gn; ++j)
-                r += __hip_atomic_load(&grouped[b0 + l0 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < a.id;
-        if (r >= gn) return;  // duplicate ids (not a valid population)
-        const uint32_t dst = b0 + l0 + r;
+    auto write_out = [&](const BucketAgent &a, uint32_t dst) {
         o.pos4[dst] = make_double4(a.x, a.y, a.z, a.rad);
         if (!periodic) {
             const GridDev *g = &sl.grids[a.slot];
@@ -602,6 +604,14 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbucke
         o.key[dst] = a.k;
         if (s.state) o.state[dst] = a.st;
         if (o.tile_key && (dst & (kBlock - 1)) == 0) o.tile_key[dst / kBlock] = a.k;
+    };
+    auto emit = [&](const BucketAgent &a) {  // rank among the ids of its box, kept in LDS
+        if (a.kl >= uint32_t(kBucketBoxes)) return;
+        const uint32_t l0 = lst[a.kl], gn = hist[a.kl];
+        uint32_t r = 0;
+        for (uint32_t j = 0; j < gn; ++j) r += grp[l0 + j] < a.id;
+        if (r >= gn) return;  // duplicate ids (not a valid population)
+        write_out(a, b0 + l0 + r);
     };
     auto starts = [&]() {  // exclusive scan over the bucket's 64 boxes (one per lane)
         __builtin_amdgcn_wave_barrier();
@@ -631,7 +641,37 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbucke
     starts();
     for (uint32_t c = lane; c < m; c += 64) group(fetch(c, false));
     settle();
-    for (uint32_t c = lane; c < m; c += 64) emit(fetch(c, true));
+    if (in_lds) {
+        for (uint32_t c = lane; c < m; c += 64) emit(fetch(c, true));
+        return;
+    }
+    // a crowded bucket: box by box, 64 members at a time; the box's ids are staged in LDS,
+    // kBucketLds at a time, and each member counts the smaller ones
+    for (int kl = 0; kl < kBucketBoxes; ++kl) {
+        const uint32_t l0 = lst[kl], gn = hist[kl];
+        for (uint32_t m0 = 0; m0 < gn; m0 += 64) {
+            const uint32_t pm = m0 + uint32_t(lane);
+            const bool mine = pm < gn;
+            const uint32_t me =
+                mine ? __hip_atomic_load(&grouped[b0 + l0 + pm], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+            uint32_t r = 0;
+            for (uint32_t w0 = 0; w0 < gn; w0 += uint32_t(kBucketLds)) {
+                const uint32_t wn = gn - w0 < uint32_t(kBucketLds) ? gn - w0 : uint32_t(kBucketLds);
+                __builtin_amdgcn_wave_barrier();
+                for (uint32_t e = uint32_t(lane); e < wn; e += 64)
+                    grp[e] = __hip_atomic_load(&grouped[b0 + l0 + w0 + e], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_wave_barrier();
+                if (mine)
+                    for (uint32_t e = 0; e < wn; ++e) r += grp[e] < me;
+            }
+            if (!mine || r >= gn) continue;  // (r >= gn: duplicate ids, not a valid population)
+            const uint32_t i =
+                __hip_atomic_load(&grouped_i[b0 + l0 + pm], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const BucketAgent a = from_index(int64_t(i), true);
+            if (a.kl == uint32_t(kl)) write_out(a, b0 + l0 + r);
+        }
+    }
 }
 
 // Processing order of the mechanics tiles of a plain call: the tiles (256 consecutive sorted
@@ -770,14 +810,17 @@ void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, cons
     hipLaunchKernelGGL(k_bucket_scatter, dim3(nbk), dim3(kBlock), 0, st, sl, nt, w.key, w.rank, w.bstart, w.item,
                        capacity);
     // per-bucket order; the sorted agents' keys go to the rank array, which nothing reads after
-    // the scatter; plain calls keep each tile's first key in the rank-by-id area
+    // the scatter; plain calls keep each tile's first key in the rank-by-id area; crowded
+    // buckets group ids in the scratch id array and agent indices in the division-flag array
+    // (free during the build: the tile order is written there afterwards)
     uint32_t *tile_key = sl.table ? nullptr : w.rankid;
     const int periodic = sl.table ? 0 : sl.one.periodic;
     SoaIn in{s.x, s.y, s.z, d, s.adh, s.id, s.state};
     SortOut o{w.pos4, w.pos4f, w.adh, w.ids, w.state, w.rank, tile_key};
     const int64_t nwg = (w.lay.nbuckets + kBlock / 64 - 1) / (kBlock / 64);
     hipLaunchKernelGGL(k_bucket_sort, dim3(unsigned(nwg)), dim3(kBlock), 0, st, sl, w.lay.nbuckets,
-                       w.lay.max_boxes, in, w.key, w.bstart, w.item, w.tmpid, w.start, o, periodic, capacity);
+                       w.lay.max_boxes, in, w.key, w.bstart, w.item, w.tmpid, w.flagid, w.start, o, periodic,
+                       capacity);
     if (!sl.table && !sl.one.periodic) {
         const unsigned nto = blocks_for(w.lay.ntiles);
         hipLaunchKernelGGL(k_order_runs, dim3(nto), dim3(kBlock), 0, st, w.grid, tile_key, w.order_first,

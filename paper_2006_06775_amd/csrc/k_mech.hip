@@ -184,29 +184,36 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
     auto visit = [&](uint32_t jj, const float4 &c) {
         s_q[qn][t] = jj;
         qn += (maybe_touch(pf, c, slack) && jj != q) ? 1 : 0;
-        if (qn == kQueue) flush();
     };
+    // the inner loop fills the queue and stops at a full queue or the end of the stream; the
+    // exact law then empties it with every lane of the wavefront together (a lane whose queue
+    // fills early waits for the others instead of running its own exact pass alone)
     float4 ca = rec.f(cnt ? j : q), cb;
     uint32_t c = 0;
     while (c < cnt) {
-        uint32_t jn = j, ln = left;
-        int rn = r;
-        advance(jn, ln, rn);
-        cb = rec.f(c + 1 < cnt ? jn : q);
-        visit(j, ca);
-        j = jn;
-        left = ln;
-        r = rn;
-        if (++c == cnt) break;
-        advance(jn, ln, rn);
-        ca = rec.f(c + 1 < cnt ? jn : q);
-        visit(j, cb);
-        j = jn;
-        left = ln;
-        r = rn;
-        ++c;
+        for (;;) {
+            uint32_t jn = j, ln = left;
+            int rn = r;
+            advance(jn, ln, rn);
+            cb = rec.f(c + 1 < cnt ? jn : q);
+            visit(j, ca);
+            j = jn;
+            left = ln;
+            r = rn;
+            if (++c == cnt || qn == kQueue) {
+                ca = cb;
+                break;
+            }
+            advance(jn, ln, rn);
+            ca = rec.f(c + 1 < cnt ? jn : q);
+            visit(j, cb);
+            j = jn;
+            left = ln;
+            r = rn;
+            if (++c == cnt || qn == kQueue) break;
+        }
+        flush();
     }
-    flush();
 }
 
 // One tile: 256 agents of one slot, one lane per agent.  precision: 64 or 32 for a plain call;
