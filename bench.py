@@ -121,29 +121,31 @@ def serving(args):
     capacity (latency at the same offered load)."""
     import torch
 
-    from paper_2006_06775_amd import serve
+    from paper_2006_06775_amd import serve, tune
+    plan = tune.plan()  # box edge per request size, measured on this device
     per_agent = 68 + 85 + 4
     cap = int(args.serve_budget_gib * (1 << 30) / (per_agent + (4 + 8 / 64) * 1.6))
     boxes = int(cap * 1.6)
     slots = 64
     # closed-system calibration: every request present at t = 0
     calib = serve.make_trace(args.serve_requests, seed=0, rate=1e9)
-    srv = serve.Server(cap, boxes, slots)
+    srv = serve.Server(cap, boxes, slots, box=plan)
     c = srv.run(calib).summary()
     del srv
     torch.cuda.empty_cache()
     rate = 0.8 * c["requests"] / c["wall_s"]
     trace = serve.make_trace(args.serve_requests, seed=0, rate=rate)
-    srv = serve.Server(cap, boxes, slots)
+    srv = serve.Server(cap, boxes, slots, box=plan)
     b = srv.run(trace).summary()
     del srv
     torch.cuda.empty_cache()
-    p_stats, _ = serve.run_plain(trace)
+    p_stats, _ = serve.run_plain(trace, box=plan)
     p = p_stats.summary()
-    pc_stats, _ = serve.run_plain(calib)  # plain capacity: the same closed system
+    pc_stats, _ = serve.run_plain(calib, box=plan)  # plain capacity: the same closed system
     pc = pc_stats.summary()
     return {
         "requests": args.serve_requests, "arrival_rate_per_s": rate, "slots": slots,
+        "box_plan": plan.summary(),
         "hbm_budget_gib": args.serve_budget_gib, "force_precision": "fp32 pair law, fp64 positions",
         "batched": {k: b[k] for k in ("agent_updates_per_s", "p50_latency_s", "p99_latency_s", "wall_s",
                                       "batch_steps", "max_concurrent")},

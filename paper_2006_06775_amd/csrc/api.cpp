@@ -133,6 +133,7 @@ bdm::Slots plain_slots(const bdm::Ws &w, const bdm::SlotDev &rec) {
     bdm::Slots sl{};
     sl.table = nullptr;
     sl.tilemap = nullptr;
+    sl.bucketmap = nullptr;
     sl.grids = w.grid;
     sl.nslots = 1;
     sl.one = rec;
@@ -496,6 +497,7 @@ int bdm_batch_step(const bdm_soa *packed, const bdm_batch *b, void *stream) {
     bdm::Slots sl{};
     sl.table = w.slots;
     sl.tilemap = w.tilemap;
+    sl.bucketmap = w.bucketmap;
     sl.grids = w.grid;
     sl.nslots = b->slots;
     bdm::launch_grid_build(*packed, sl, b->capacity, w, st);

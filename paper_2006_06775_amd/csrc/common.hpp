@@ -67,7 +67,7 @@ struct SlotDev {
 // Byte offsets of every workspace region (256-byte aligned).  `slots` = 0 is a plain
 // workspace (one grid record, slot passed by value); > 0 is a batch of that many slots.
 struct WsLayout {
-    size_t grid, slots, tilemap, partials, count, bstart, start, tiles, key, rank, item, tmpid, pos4, pos4f, adh,
+    size_t grid, slots, tilemap, bucketmap, partials, count, bstart, start, tiles, key, rank, item, tmpid, pos4, pos4f, adh,
         ids, state, flagid, rankid, order_bins;
     size_t total;
     int64_t capacity, max_boxes, max_tiles, nslots, ntiles, nbuckets;
@@ -94,6 +94,7 @@ inline bool ws_layout(int64_t capacity, int64_t max_boxes, int64_t slots, WsLayo
     L->grid = take(256 * ngrid);
     L->slots = take(slots > 0 ? sizeof(SlotDev) * size_t(slots) : 0);
     L->tilemap = take(slots > 0 ? 4 * ntile : 0);
+    L->bucketmap = take(slots > 0 ? 4 * nbk : 0);
     L->partials = take(64 * ((cap + kBoundsTile - 1) / kBoundsTile + 1));
     L->count = take(4 * (nbk + 1));
     L->bstart = take(4 * (nbk + 1));
@@ -126,6 +127,7 @@ struct Ws {
     GridDev *grid;       // [max(1, nslots)]
     SlotDev *slots;      // batch only
     int32_t *tilemap;    // batch only: tile -> slot (-1 = none)
+    int32_t *bucketmap;  // batch only: bucket of 64 boxes -> slot owning it (-1 = none)
     double *partials;    // bounds reduction: 8 values per kBoundsTile agents
     uint32_t *count;     // agents per bucket of 64 boxes (scan input, kept zero between builds)
     uint32_t *bstart;    // first sorted position of each bucket
@@ -148,6 +150,7 @@ inline Ws ws_view(void *base, const WsLayout &L) {
     w.grid = reinterpret_cast<GridDev *>(p + L.grid);
     w.slots = L.nslots > 0 ? reinterpret_cast<SlotDev *>(p + L.slots) : nullptr;
     w.tilemap = L.nslots > 0 ? reinterpret_cast<int32_t *>(p + L.tilemap) : nullptr;
+    w.bucketmap = L.nslots > 0 ? reinterpret_cast<int32_t *>(p + L.bucketmap) : nullptr;
     w.partials = reinterpret_cast<double *>(p + L.partials);
     w.count = reinterpret_cast<uint32_t *>(p + L.count);
     w.bstart = reinterpret_cast<uint32_t *>(p + L.bstart);
@@ -175,6 +178,7 @@ inline Ws ws_view(void *base, const WsLayout &L) {
 struct Slots {
     const SlotDev *table;      // batch: slot records; plain: nullptr (use `one`)
     const int32_t *tilemap;    // batch: tile -> slot; plain: nullptr (every tile is slot 0)
+    const int32_t *bucketmap;  // batch: bucket -> owning slot or -1; plain: nullptr (all owned)
     GridDev *grids;            // grid record per slot
     int64_t nslots;            // 1 for a plain call
     SlotDev one;               // the plain call's slot record
@@ -289,15 +293,5 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t nblocks) {
     return x * per + (x < rem ? x : rem) + idx;
 }
 
-// Tiles [t0, t1) of workgroup bid in a per-tile launch of nblocks workgroups over ntiles
-// tiles: one contiguous chunk per workgroup, and the chunks of one XCD's workgroups adjacent,
-// so each XCD streams one contiguous part of the box-sorted arrays and the histogram lines it
-// updates stay in its own L2.
-__device__ __forceinline__ void xcd_chunk(uint32_t bid, uint32_t nblocks, int64_t ntiles, int64_t &t0, int64_t &t1) {
-    const int64_t v = xcd_tile(bid, nblocks);
-    const int64_t per = ntiles / nblocks, rem = ntiles % nblocks;
-    t0 = v * per + (v < rem ? v : rem);
-    t1 = t0 + per + (v < rem ? 1 : 0);
-}
 
 }  // namespace bdm

@@ -76,13 +76,14 @@ __device__ void clear_grid(GridDev *g) {
 // Zero the grid records, the histogram and the scan tiles; empty the batch slot table.
 __global__ __launch_bounds__(kBlock) void k_ws_init(GridDev *g, int64_t ngrid, uint32_t *count, int64_t ncount,
                                                     unsigned long long *tiles, int64_t ntiles, SlotDev *slots,
-                                                    int32_t *tilemap, int64_t ntilemap, uint32_t *runs,
-                                                    int64_t nruns) {
+                                                    int32_t *tilemap, int64_t ntilemap, int32_t *bucketmap,
+                                                    int64_t nbucketmap, uint32_t *runs, int64_t nruns) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t k = i; k < ncount; k += stride) count[k] = 0u;
     for (int64_t k = i; k < ntiles; k += stride) tiles[k] = 0ull;
     for (int64_t k = i; k < ntilemap; k += stride) tilemap[k] = -1;
+    for (int64_t k = i; k < nbucketmap; k += stride) bucketmap[k] = -1;
     for (int64_t k = i; k < nruns; k += stride) runs[k] = 0xFFFFFFFFu;  // no run in any bin
     for (int64_t k = i; k < ngrid; k += stride) {
         clear_grid(&g[k]);
@@ -93,17 +94,31 @@ __global__ __launch_bounds__(kBlock) void k_ws_init(GridDev *g, int64_t ngrid, u
     }
 }
 
-// Write one slot record and point its tiles at it (rec.capacity < 0 clears the slot: its tiles
-// point nowhere and its record is zeroed).  Runs on the stream, so replays see it in order.
-__global__ __launch_bounds__(kBlock) void k_set_slot(SlotDev *slots, int32_t *tilemap, GridDev *grids,
-                                                     int32_t slot, SlotDev rec, int64_t first_tile,
-                                                     int64_t ntile, int32_t value) {
+// Write one slot record and point its tiles and buckets at it (rec.capacity < 0 clears the
+// slot: its tiles point nowhere and its record is zeroed).  Runs on the stream, so replays see
+// it in order.
+__global__ __launch_bounds__(kBlock) void k_set_slot(SlotDev *slots, int32_t *tilemap, int32_t *bucketmap,
+                                                     GridDev *grids, int32_t slot, SlotDev rec, int64_t first_tile,
+                                                     int64_t ntile, int64_t first_bucket, int64_t nbucket,
+                                                     int32_t value) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < ntile) tilemap[first_tile + i] = value;
+    if (i < nbucket) bucketmap[first_bucket + i] = value;
     if (i == 0) {
         slots[slot] = rec;
         clear_grid(&grids[slot]);
     }
+}
+
+// Release the buckets the slot's current record owns (before the record is rewritten).
+__global__ __launch_bounds__(kBlock) void k_unmap_buckets(const SlotDev *slots, int32_t *bucketmap, int64_t nbuckets,
+                                                          int32_t slot) {
+    const SlotDev r = slots[slot];
+    if (r.capacity <= 0 || r.max_boxes <= 0) return;
+    const int64_t b0 = r.box_off >> kBucketShift, b1 = (r.box_off + r.max_boxes - 1) >> kBucketShift;
+    for (int64_t b = b0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; b <= b1 && b < nbuckets;
+         b += int64_t(gridDim.x) * blockDim.x)
+        if (bucketmap[b] == slot) bucketmap[b] = -1;
 }
 
 // One step done for every slot that was running.
@@ -132,17 +147,28 @@ void launch_ws_init(const Ws &w, hipStream_t st) {
     const int64_t ncount = w.lay.nbuckets + 1;
     const int64_t ngrid = w.lay.nslots > 0 ? w.lay.nslots : 1;
     const int64_t nmap = w.lay.nslots > 0 ? w.lay.ntiles : 0;
+    const int64_t nbmap = w.lay.nslots > 0 ? w.lay.nbuckets : 0;
     int64_t most = ncount > w.lay.max_tiles ? ncount : w.lay.max_tiles;
     if (nmap > most) most = nmap;
+    if (nbmap > most) most = nbmap;
     if (2 * kOrderBins > most) most = 2 * kOrderBins;
     hipLaunchKernelGGL(k_ws_init, dim3(nblocks(most, 4096)), dim3(kBlock), 0, st, w.grid, ngrid, w.count, ncount,
-                       w.tiles, w.lay.max_tiles, w.slots, w.tilemap, nmap, w.order_first, int64_t(2 * kOrderBins));
+                       w.tiles, w.lay.max_tiles, w.slots, w.tilemap, nmap, w.bucketmap, nbmap, w.order_first,
+                       int64_t(2 * kOrderBins));
 }
 
 void launch_set_slot(const Ws &w, int32_t slot, const SlotDev &rec, int64_t first_tile, int64_t ntile,
                      int32_t value, hipStream_t st) {
-    hipLaunchKernelGGL(k_set_slot, dim3(nblocks(ntile, 0)), dim3(kBlock), 0, st, w.slots, w.tilemap, w.grid, slot,
-                       rec, first_tile, ntile, value);
+    // release the buckets of the record being replaced, then map the new record's buckets
+    hipLaunchKernelGGL(k_unmap_buckets, dim3(64), dim3(kBlock), 0, st, w.slots, w.bucketmap, w.lay.nbuckets, slot);
+    int64_t first_bucket = 0, nbucket = 0;
+    if (value >= 0 && rec.max_boxes > 0) {
+        first_bucket = rec.box_off >> kBucketShift;
+        nbucket = ((rec.box_off + rec.max_boxes - 1) >> kBucketShift) - first_bucket + 1;
+    }
+    const int64_t most = ntile > nbucket ? ntile : nbucket;
+    hipLaunchKernelGGL(k_set_slot, dim3(nblocks(most, 0)), dim3(kBlock), 0, st, w.slots, w.tilemap, w.bucketmap,
+                       w.grid, slot, rec, first_tile, ntile, first_bucket, nbucket, value);
 }
 
 void launch_batch_advance(const Ws &w, hipStream_t st) {

@@ -281,13 +281,13 @@ __global__ __launch_bounds__(kBlock) void k_key_bucket(Slots sl, int64_t ntiles,
                                                        const double *__restrict__ z, uint32_t *count,
                                                        uint32_t *__restrict__ key,
                                                        uint32_t *__restrict__ brank) {
-    int64_t t0, t1;
-    xcd_chunk(blockIdx.x, gridDim.x, ntiles, t0, t1);
     const int lane = threadIdx.x & 63;
-    for (int64_t tile = t0; tile < t1; tile += kKeyTiles) {
+    const int64_t ngroups = (ntiles + kKeyTiles - 1) / kKeyTiles;
+    for (int64_t grp = xcd_tile(blockIdx.x, gridDim.x); grp < ngroups; grp += gridDim.x) {
+        const int64_t tile = grp * kKeyTiles;
         KeyLane r[kKeyTiles];
 #pragma unroll
-        for (int u = 0; u < kKeyTiles; ++u) r[u] = key_bucket_issue(sl, tile + u, t1, x, y, z, count);
+        for (int u = 0; u < kKeyTiles; ++u) r[u] = key_bucket_issue(sl, tile + u, ntiles, x, y, z, count);
 #pragma unroll
         for (int u = 0; u < kKeyTiles; ++u) {
             const uint32_t base = __shfl(r[u].base, r[u].head, 64);
@@ -424,15 +424,16 @@ __global__ __launch_bounds__(kBlock) void k_scan(uint32_t *in, uint32_t *out, co
 }
 
 // Agent indices into their bucket's range of sorted positions, in arrival order (kKeyTiles
-// tiles per workgroup at once, so that their dependent loads overlap).
+// tiles per workgroup at once, so that their dependent loads overlap; the workgroups stride
+// over groups of tiles, so a simulation's tiles spread over all of them).
 __global__ __launch_bounds__(kBlock) void k_bucket_scatter(Slots sl, int64_t ntiles,
                                                            const uint32_t *__restrict__ key,
                                                            const uint32_t *__restrict__ brank,
                                                            const uint32_t *__restrict__ bstart,
                                                            uint32_t *__restrict__ item, int64_t capacity) {
-    int64_t t0, t1;
-    xcd_chunk(blockIdx.x, gridDim.x, ntiles, t0, t1);
-    for (int64_t tile = t0; tile < t1; tile += kKeyTiles) {
+    const int64_t ngroups = (ntiles + kKeyTiles - 1) / kKeyTiles;
+    for (int64_t grp = xcd_tile(blockIdx.x, gridDim.x); grp < ngroups; grp += gridDim.x) {
+        const int64_t tile = grp * kKeyTiles, t1 = ntiles;
         int64_t iu[kKeyTiles];
         uint32_t bk[kKeyTiles], rk[kKeyTiles], pos[kKeyTiles], lim[kKeyTiles];
         GridDev *gu[kKeyTiles];
@@ -535,6 +536,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbucke
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t bk = int64_t(xcd_tile(blockIdx.x, gridDim.x)) * (kBlock / 64) + wave;
     if (bk >= nbuckets) return;  // (the whole wavefront; no workgroup barrier below)
+    if (sl.bucketmap && sl.bucketmap[bk] < 0) return;  // a batch bucket no simulation owns
     uint32_t *hist = s_hist[wave], *lst = s_ls[wave], *cur = s_cur[wave], *grp = s_grp[wave];
     const uint32_t b0 = bstart[bk];
     uint32_t b1 = bstart[bk + 1];
@@ -618,6 +620,10 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbucke
         const uint32_t h = hist[lane];
         const uint32_t ls = wave_incl_scan(h) - h;
         if (box0 + lane <= max_boxes) start[box0 + lane] = b0 + ls;
+    // the first box start of the next bucket is this bucket's end: written here too, so that a
+    // simulation whose box range ends at this bucket's end finds it even when no simulation
+    // owns the next bucket (both writers write the same value)
+    if (lane == 0 && box0 + kBucketBoxes <= max_boxes) start[box0 + kBucketBoxes] = b1;
         lst[lane] = ls;
         cur[lane] = ls;
         __builtin_amdgcn_wave_barrier();

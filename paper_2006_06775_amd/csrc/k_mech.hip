@@ -291,9 +291,9 @@ __global__ __launch_bounds__(kBlock) void k_mech(Slots sl, int64_t ntiles, const
                          s_run, s_q);
         return;
     }
-    int64_t t0, t1;  // batch: a contiguous chunk of tiles per workgroup, XCD by XCD
-    xcd_chunk(blockIdx.x, gridDim.x, ntiles, t0, t1);
-    for (int64_t tile = t0; tile < t1; ++tile)
+    // batch: the workgroups stride over the tiles (a simulation's tiles spread over all of them),
+    // neighbouring tiles of a round going to workgroups of one XCD
+    for (int64_t tile = xcd_tile(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x)
         mech_tile<kPrec>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q);
 }
 

@@ -37,6 +37,17 @@ def box_reserve(n: int, box: float) -> int:
     return per ** 3
 
 
+def box_edge(box, n: int) -> float:
+    """The box edge of a request of n agents: a fixed edge, or a tune.BoxPlan's choice."""
+    return float(box.box_for(n)) if hasattr(box, "box_for") else float(box)
+
+
+def mech_params(box: float):
+    """The served simulations' parameters (C0's mechanics, binary32 pair law) with box edge `box`."""
+    from . import bdm
+    return bdm.params(k=2.0, gamma=1.0, dt=0.01, max_disp=3.0, box=box, force_bits=32)
+
+
 @dataclass
 class Request:
     rid: int
@@ -124,20 +135,20 @@ class ServeStats:
 class Server:
     """Packed population of `slots` simulation slots with `capacity` agents in total."""
 
-    def __init__(self, capacity: int, max_boxes: int, slots: int = 64, box: float = D_HI,
+    def __init__(self, capacity: int, max_boxes: int, slots: int = 64, box=D_HI,
                  use_graph: bool = True, keep_results: bool = False):
         import torch
 
         from . import bdm
         self.torch, self.bdm = torch, bdm
         self.capacity = (int(capacity) + ALIGN - 1) // ALIGN * ALIGN
-        self.max_boxes, self.slots, self.box = int(max_boxes), int(slots), float(box)
+        self.max_boxes, self.slots = int(max_boxes), int(slots)
+        self.box = box  # one edge for every request, or a tune.BoxPlan (edge per request size)
         self.batch = bdm.Batch(self.capacity, self.max_boxes, self.slots)
         self.agents = RangeAllocator(self.capacity, ALIGN)
         self.boxes = RangeAllocator(self.max_boxes, bdm.BOX_ALIGN)
         self.free_slots = list(range(self.slots))[::-1]
         self.running: dict[int, Running] = {}
-        self.params = bdm.params(k=2.0, gamma=1.0, dt=0.01, max_disp=3.0, box=self.box, force_bits=32)
         self.stream = torch.cuda.Stream()
         self.graph = None
         self.use_graph = use_graph
@@ -150,8 +161,11 @@ class Server:
         64-byte partial) + per reserved box 4 B of box start and 8 B per bucket of 64 boxes."""
         return int(n * (68 + 85 + 4) + (4 + 8 / 64) * box_reserve(n, box))
 
+    def box_of(self, req: Request) -> float:
+        return box_edge(self.box, req.n)
+
     def fits(self, req: Request) -> bool:
-        return req.n <= self.capacity and box_reserve(req.n, self.box) <= self.max_boxes
+        return req.n <= self.capacity and box_reserve(req.n, self.box_of(req)) <= self.max_boxes
 
     def try_admit(self, req: Request) -> bool:
         if not self.free_slots:
@@ -159,7 +173,8 @@ class Server:
         a = self.agents.alloc(req.n)
         if a is None:
             return False
-        nb = box_reserve(req.n, self.box)
+        box = self.box_of(req)
+        nb = box_reserve(req.n, box)
         bx = self.boxes.alloc(nb)
         if bx is None:
             self.agents.release(*a)
@@ -170,7 +185,7 @@ class Server:
             view = self.batch.view(slot, a[0], req.n)
             bdm.generate(view, bdm.gen(bdm.GEN_CUBE, req.n, cube_edge(req.n), D_LO, D_HI, 0.4, seed=req.seed),
                          stream=self.stream)
-            self.batch.set_slot(slot, a[0], req.n, bx[0], bx[1], req.steps, self.params, stream=self.stream)
+            self.batch.set_slot(slot, a[0], req.n, bx[0], bx[1], req.steps, mech_params(box), stream=self.stream)
         self.running[slot] = Running(req, slot, a[0], a[1], bx[0], bx[1], req.steps)
         return True
 
@@ -241,17 +256,17 @@ class Server:
         return stats
 
 
-def run_plain(trace, time_scale: float = 1.0, box: float = D_HI, keep_results: bool = False):
-    """Serve the trace one request at a time with plain launches (FIFO, no batching)."""
+def run_plain(trace, time_scale: float = 1.0, box=D_HI, keep_results: bool = False):
+    """Serve the trace one request at a time with plain launches (FIFO, no batching); `box` as
+    for Server."""
     import torch
 
     from . import bdm
     stats = ServeStats()
     results = {}
     pending = sorted(trace, key=lambda r: r.arrival)
-    p = bdm.params(k=2.0, gamma=1.0, dt=0.01, max_disp=3.0, box=box, force_bits=32)
     cap = max(r.n for r in pending)
-    pop = bdm.Population(cap, max(box_reserve(r.n, box) for r in pending))
+    pop = bdm.Population(cap, max(box_reserve(r.n, box_edge(box, r.n)) for r in pending))
     t0 = time.perf_counter()
     for r in pending:
         wait = r.arrival * time_scale - (time.perf_counter() - t0)
@@ -260,6 +275,7 @@ def run_plain(trace, time_scale: float = 1.0, box: float = D_HI, keep_results: b
         view = bdm.Soa(r.n, pop.soa.n, pop.soa.x, pop.soa.y, pop.soa.z, pop.soa.diam, pop.soa.adh,
                        pop.soa.fx, pop.soa.fy, pop.soa.fz, pop.soa.id, None)
         bdm.generate(view, bdm.gen(bdm.GEN_CUBE, r.n, cube_edge(r.n), D_LO, D_HI, 0.4, seed=r.seed))
+        p = mech_params(box_edge(box, r.n))
         for step in range(r.steps):
             bdm.sim_step(view, bdm.MODEL_MECH, p, step, pop.ws)
         out = {}

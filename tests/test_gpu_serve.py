@@ -36,3 +36,27 @@ def test_server_without_graph_matches():
     b.run(trace)
     for r in trace:
         assert np.array_equal(a.results[r.rid]["x"], b.results[r.rid]["x"])
+
+
+def test_served_mixed_box_edges_equal_alone():
+    """Requests of different sizes get different box edges from a plan; each served result still
+    equals the same request served alone with its edge."""
+    print("case: serve mixed box edges", flush=True)
+    from paper_2006_06775_amd import tune
+    plan = tune.BoxPlan(serve.D_HI, {1000: 1.0, 30000: 1.3})
+    trace = serve.make_trace(8, seed=5, rate=5000.0, n_min=1000, n_max=40000, s_min=2, s_max=6)
+    assert len({serve.box_edge(plan, r.n) for r in trace}) == 2
+    srv = serve.Server(capacity=200_000, max_boxes=600_000, slots=4, box=plan, keep_results=True)
+    srv.run(trace)
+    _, alone = serve.run_plain(trace, box=plan, keep_results=True)
+    for r in trace:
+        for k in ("x", "y", "z"):
+            assert np.array_equal(srv.results[r.rid][k], alone[r.rid][k]), (r.rid, k)
+
+
+def test_tune_plan_measures():
+    print("case: tune plan", flush=True)
+    from paper_2006_06775_amd import tune
+    plan = tune.plan(classes=(2000, 20000), factors=(1.0, 1.25), steps=2)
+    assert set(plan.best) == {2000, 20000} and set(plan.best.values()) <= {1.0, 1.25}
+    assert all(t > 0 for row in plan.table.values() for t in row.values())

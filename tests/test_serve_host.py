@@ -59,3 +59,15 @@ def test_box_reserve_covers_the_cube():
     for n in (1000, 4096, 2_000_000):
         per = round(box_reserve(n, 15.0) ** (1 / 3))
         assert per * 15.0 >= cube_edge(n) + 3 * 15.0
+
+
+def test_tune_pick_and_plan_lookup():
+    from paper_2006_06775_amd import serve, tune
+    table = {1000: {1.0: 3e-9, 1.2: 2e-9, 1.4: 2e-9}, 100_000: {1.0: 1e-9, 1.2: 1.5e-9, 1.4: 2e-9}}
+    best = tune.pick(table)
+    assert best == {1000: 1.2, 100_000: 1.0}  # ties go to the smaller factor
+    plan = tune.BoxPlan(15.0, best, table)
+    assert plan.box_for(900) == 15.0 * 1.2 and plan.box_for(5000) == 15.0 * 1.2
+    assert plan.box_for(20_000) == 15.0 and plan.box_for(3_000_000) == 15.0
+    assert serve.box_edge(plan, 900) == 18.0 and serve.box_edge(15.0, 900) == 15.0
+    assert tune.fixed(1.0).box_for(123456) == 15.0
