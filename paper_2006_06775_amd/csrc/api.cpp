@@ -249,7 +249,7 @@ int bdm_mech_step(const bdm_soa *soa, const bdm_params *params, const bdm_worksp
     rc = check_mech_params(params);
     if (rc) return rc;
     const bdm::SlotDev rec = slot_record(params, 0, soa->capacity, 0, w.lay.max_boxes, 1, true);
-    bdm::launch_mech(*soa, plain_slots(w, rec), soa->capacity, params->force_bits, w, as_stream(stream));
+    bdm::launch_mech(*soa, plain_slots(w, rec), soa->capacity, params->force_bits, false, w, as_stream(stream));
     return hip_check("mech_step launch");
 }
 
@@ -281,7 +281,8 @@ int bdm_sim_step(const bdm_soa *soa, int32_t model, const bdm_params *params, in
         bdm::launch_grid_build(*soa, plain_slots(w, rec), soa->capacity, w, st);
         rc = hip_check("grid_build launch");
         if (rc) return rc;
-        bdm::launch_mech(*soa, plain_slots(w, rec), soa->capacity, params->force_bits, w, st);
+        bdm::launch_mech(*soa, plain_slots(w, rec), soa->capacity, params->force_bits, model == BDM_MODEL_SPHEROID, w,
+                         st);
         return hip_check("mech_step launch");
     }
     case BDM_MODEL_SIR: {
@@ -501,7 +502,7 @@ int bdm_batch_step(const bdm_soa *packed, const bdm_batch *b, void *stream) {
     sl.grids = w.grid;
     sl.nslots = b->slots;
     bdm::launch_grid_build(*packed, sl, b->capacity, w, st);
-    bdm::launch_mech(*packed, sl, b->capacity, 0, w, st);
+    bdm::launch_mech(*packed, sl, b->capacity, 0, false, w, st);
     bdm::launch_batch_advance(w, st);
     return hip_check("batch_step launch");
 }

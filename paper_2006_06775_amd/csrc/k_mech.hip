@@ -23,7 +23,8 @@
 
 namespace bdm {
 
-constexpr int kQueue = 8;  // queued candidates per lane before an exact pass
+constexpr int kQueue = 8;          // queued candidates per lane before an exact pass
+constexpr int kQueueCrowded = 16;  // the same for crowded populations (tens of contacts per agent)
 
 template <bool F32>
 __device__ __forceinline__ void exact_pair(const double4 &p, const double4 &q, float rif, const SlotDev &a,
@@ -155,7 +156,7 @@ __device__ __forceinline__ void key_coords(const GridDev *__restrict__ g, uint32
 // The candidates are walked as one counted stream, two per iteration with the next record
 // loaded one ahead.  Survivors of the pre-test go to the queue (written unconditionally,
 // kept when they pass), which the exact law empties in order when full and at the end.
-template <bool F32, class Rec>
+template <bool F32, int kQ, class Rec>
 __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const double4 &p, const Rec &rec,
                                             float slack, const uint2 (*s_run)[kBlock], int col, uint32_t cnt,
                                             uint32_t (*s_q)[kBlock], int t, double &fx, double &fy, double &fz) {
@@ -200,7 +201,7 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
             j = jn;
             left = ln;
             r = rn;
-            if (++c == cnt || qn == kQueue) {
+            if (++c == cnt || qn == kQ) {
                 ca = cb;
                 break;
             }
@@ -210,7 +211,7 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
             j = jn;
             left = ln;
             r = rn;
-            if (++c == cnt || qn == kQueue) break;
+            if (++c == cnt || qn == kQ) break;
         }
         flush();
     }
@@ -218,7 +219,7 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
 
 // One tile: 256 agents of one slot, one lane per agent.  precision: 64 or 32 for a plain call;
 // 0 = per slot.
-template <int kPrec, class Rec>
+template <int kPrec, int kQ, class Rec>
 __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const Rec &rec,
                                           const double *__restrict__ adh_s, const uint32_t *__restrict__ id_s,
                                           const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
@@ -239,9 +240,9 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
     const double4 p = rec(q);
     double fx, fy, fz;
     if (f32)
-        mech_forces<true>(S, q, p, rec, pretest_slack(g), s_run, t, cnt, s_q, t, fx, fy, fz);
+        mech_forces<true, kQ>(S, q, p, rec, pretest_slack(g), s_run, t, cnt, s_q, t, fx, fy, fz);
     else
-        mech_forces<false>(S, q, p, rec, pretest_slack(g), s_run, t, cnt, s_q, t, fx, fy, fz);
+        mech_forces<false, kQ>(S, q, p, rec, pretest_slack(g), s_run, t, cnt, s_q, t, fx, fy, fz);
 
     // adherence gate, clamp, integrate (binary64)
     const double adh = adh_s[q];
@@ -273,7 +274,7 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
     if (out.fz) __builtin_nontemporal_store(fz, &out.fz[o]);
 }
 
-template <int kPrec, class Rec>
+template <int kPrec, int kQ, class Rec>
 __global__ __launch_bounds__(kBlock) void k_mech(Slots sl, int64_t ntiles, const uint32_t *__restrict__ order, Rec rec,
                                                  const double *__restrict__ adh_s,
                                                  const uint32_t *__restrict__ id_s,
@@ -281,20 +282,20 @@ __global__ __launch_bounds__(kBlock) void k_mech(Slots sl, int64_t ntiles, const
                                                  const uint32_t *__restrict__ key_s,
                                                  const uint32_t *__restrict__ start, bdm_soa out) {
     __shared__ uint2 s_run[9][kBlock];
-    __shared__ uint32_t s_q[kQueue][kBlock];
+    __shared__ uint32_t s_q[kQ][kBlock];
     if (order) {  // plain call: pencil order, one contiguous part of it per XCD
         const GridDev *g0 = &sl.grids[0];
         if (!g0->valid) return;
         const uint32_t live_tiles = uint32_t((g0->n + kBlock - 1) / kBlock);
         if (blockIdx.x >= live_tiles) return;
-        mech_tile<kPrec>(sl, order[xcd_tile(blockIdx.x, live_tiles)], rec, adh_s, id_s, state_s, key_s, start, out,
+        mech_tile<kPrec, kQ>(sl, order[xcd_tile(blockIdx.x, live_tiles)], rec, adh_s, id_s, state_s, key_s, start, out,
                          s_run, s_q);
         return;
     }
     // batch: the workgroups stride over the tiles (a simulation's tiles spread over all of them),
     // neighbouring tiles of a round going to workgroups of one XCD
     for (int64_t tile = xcd_tile(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x)
-        mech_tile<kPrec>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q);
+        mech_tile<kPrec, kQ>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q);
 }
 
 // Test hook: contact lists per sorted slot in force-sum order (mechanical contact, plain calls).
@@ -342,19 +343,29 @@ __global__ __launch_bounds__(kBlock) void k_contacts_mech(Slots sl, const double
 
 template <class Rec>
 static void launch_mech_rec(const bdm_soa &s, const Slots &sl, int64_t ntiles, unsigned nb, int precision,
-                            const uint32_t *order, const Rec &rec, const Ws &w, hipStream_t st) {
-    if (precision == 32)
-        hipLaunchKernelGGL((k_mech<32, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, ntiles, order, rec, w.adh, w.ids,
-                           w.state, w.rank, w.start, s);
-    else if (precision == 64)
-        hipLaunchKernelGGL((k_mech<64, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, ntiles, order, rec, w.adh, w.ids,
-                           w.state, w.rank, w.start, s);
-    else
-        hipLaunchKernelGGL((k_mech<0, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, ntiles, order, rec, w.adh, w.ids,
-                           w.state, w.rank, w.start, s);
+                            bool crowded, const uint32_t *order, const Rec &rec, const Ws &w, hipStream_t st) {
+#define BDM_MECH(P, Q)                                                                                      \
+    hipLaunchKernelGGL((k_mech<P, Q, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, ntiles, order, rec, w.adh, w.ids, \
+                       w.state, w.rank, w.start, s)
+    if (precision == 32) {
+        if (crowded)
+            BDM_MECH(32, kQueueCrowded);
+        else
+            BDM_MECH(32, kQueue);
+    } else if (precision == 64) {
+        if (crowded)
+            BDM_MECH(64, kQueueCrowded);
+        else
+            BDM_MECH(64, kQueue);
+    } else {
+        BDM_MECH(0, kQueue);
+    }
+#undef BDM_MECH
 }
 
-void launch_mech(const bdm_soa &s, const Slots &sl, int64_t capacity, int precision, const Ws &w,
+// crowded: a population packed so densely that agents have tens of contacts (the growing
+// spheroid); a longer queue then saves exact-law rounds, at the cost of LDS (occupancy).
+void launch_mech(const bdm_soa &s, const Slots &sl, int64_t capacity, int precision, bool crowded, const Ws &w,
                  hipStream_t st) {
     const int64_t ntiles = (capacity + kBlock - 1) / kBlock;
     const unsigned nb = tile_grid(sl, ntiles);
@@ -362,9 +373,9 @@ void launch_mech(const bdm_soa &s, const Slots &sl, int64_t capacity, int precis
     const uint64_t bytes = uint64_t(w.lay.capacity) * 32u;
     if (bytes <= 0xFFFFFFE0ull) {
         RecBuf rec{static_cast<void *>(w.pos4), static_cast<void *>(w.pos4f), uint32_t(bytes)};
-        launch_mech_rec(s, sl, ntiles, nb, precision, order, rec, w, st);
+        launch_mech_rec(s, sl, ntiles, nb, precision, crowded, order, rec, w, st);
     } else {
-        launch_mech_rec(s, sl, ntiles, nb, precision, order, RecGlobal{w.pos4, w.pos4f}, w, st);
+        launch_mech_rec(s, sl, ntiles, nb, precision, crowded, order, RecGlobal{w.pos4, w.pos4f}, w, st);
     }
 }
 

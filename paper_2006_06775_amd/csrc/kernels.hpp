@@ -51,7 +51,7 @@ void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, cons
 // Exclusive scan of in[0, len) into out[0, len] (len read on the device).
 void launch_scan(uint32_t *in, uint32_t *out, const int64_t *len_ptr, int64_t max_len, const Ws &w,
                  int zero_in, bool prepare, hipStream_t st);
-void launch_mech(const bdm_soa &s, const Slots &sl, int64_t capacity, int precision, const Ws &w,
+void launch_mech(const bdm_soa &s, const Slots &sl, int64_t capacity, int precision, bool crowded, const Ws &w,
                  hipStream_t st);
 void launch_sir(const bdm_soa &s, const Slots &sl, int64_t capacity, const SirArgs &a, const Ws &w,
                 hipStream_t st);
