@@ -24,6 +24,7 @@ constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kBucketShift = 6;       // 64 consecutive boxes per bucket of the two-level sort
 constexpr int kBucketBoxes = 1 << kBucketShift;
 constexpr int kOrderBins = 8192;      // largest (y-pencil x z-plane) count of the tile order
+constexpr double kPretestRadius = 1.0006;  // radius scale of the binary32 pre-test copy of a record
 constexpr uint32_t kScanSpinLimit = 1u << 22;  // polls before a look-back gives up
 
 // Philox draw purposes: counter word 0 = purpose + (attempt << 8).

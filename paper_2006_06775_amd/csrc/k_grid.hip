@@ -599,7 +599,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbucke
             const GridDev *g = &sl.grids[a.slot];
             const double b = g->b;
             o.pos4f[dst] = make_float4(float(a.x - double(g->cmin[0]) * b), float(a.y - double(g->cmin[1]) * b),
-                                       float(a.z - double(g->cmin[2]) * b), float(a.rad));
+                                       float(a.z - double(g->cmin[2]) * b), float(a.rad * kPretestRadius));
         }
         if (s.adh) o.adh[dst] = a.adh;
         o.id[dst] = a.id;

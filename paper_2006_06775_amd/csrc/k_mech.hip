@@ -4,11 +4,13 @@
 //
 // One lane per agent in box-sorted order.  The 27 neighbour boxes are 9 contiguous key runs
 // (dz, dy in {-1, 0, 1}; dx = -1..+1 adjacent in key space because x varies fastest), so
-// candidates arrive in ascending (key, id) order -- the canonical summation order.
+// candidates arrive in ascending (key, id) order -- the canonical summation order.  Boxes that
+// no sphere in them can reach are dropped from the ends of these runs (about a third of the 27
+// at uniform density; see load_runs), which removes only non-contacts.
 //
 // The work is split in two so that the wavefront does not pay the expensive exact law for
 // every candidate of every lane:
-//   1. candidate stream: each lane walks its 9 runs as one flattened stream (run table in LDS)
+//   1. candidate stream: each lane walks its runs as one flattened stream (run table in LDS)
 //      and keeps the candidates that pass a cheap conservative squared-distance test in a small
 //      per-lane queue in LDS;
 //   2. exact pass: the queued candidates, still in canonical order, are re-read and evaluated
@@ -26,11 +28,12 @@ namespace bdm {
 constexpr int kQueue = 8;          // queued candidates per lane before an exact pass
 constexpr int kQueueCrowded = 16;  // the same for crowded populations (tens of contacts per agent)
 
+// The pair law for agent i with record p and a candidate j at offset (dx, dy, dz) = p - q with
+// radius rj, added to (fx, fy, fz) when the spheres overlap (a non-contact adds nothing).
 template <bool F32>
-__device__ __forceinline__ void exact_pair(const double4 &p, const double4 &q, float rif, const SlotDev &a,
-                                           double &fx, double &fy, double &fz) {
-    const double dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
-    const double ri = p.w, rj = q.w;
+__device__ __forceinline__ void exact_pair(const double4 &p, double dx, double dy, double dz, double rj, float rif,
+                                           const SlotDev &a, double &fx, double &fy, double &fz) {
+    const double ri = p.w;
     if constexpr (!F32) {
         const double s = ri + rj;
         const double dist = __builtin_sqrt((dx * dx + dy * dy) + dz * dz);
@@ -58,70 +61,119 @@ __device__ __forceinline__ void exact_pair(const double4 &p, const double4 &q, f
     }
 }
 
-// The 9 key runs of the box (cx, cy, cz) as [lo, hi) ranges of sorted positions, the non-empty
-// ones first in canonical order, then the empty ones, in column t; returns the candidate count.
-__device__ __forceinline__ uint32_t load_runs(const GridDev *__restrict__ g, const uint32_t *__restrict__ start,
-                                              int cx, int cy, int cz, uint2 (*s_run)[kBlock], int t) {
+// Key range [lo, hi) of row r (dz = r / 3 - 1, dy = r % 3 - 1) of the 27 boxes around the box
+// (cx, cy, cz): boxes x0..x1 of that row, clipped to the lattice; an empty range off it.
+__device__ __forceinline__ void row_range(const GridDev *__restrict__ g, const uint32_t *__restrict__ start, int cx,
+                                          int cy, int cz, int r, uint32_t &lo, uint32_t &hi) {
     const int nx = g->dims[0], ny = g->dims[1], nz = g->dims[2];
+    const int zz = cz + r / 3 - 1, yy = cy + r % 3 - 1;
+    lo = hi = 0;
+    if (zz < 0 || zz >= nz || yy < 0 || yy >= ny) return;
     const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < nx - 1 ? cx + 1 : nx - 1;
+    const uint32_t kb = uint32_t(x0) + uint32_t(nx) * (uint32_t(yy) + uint32_t(ny) * uint32_t(zz));
+    lo = start[kb];
+    hi = start[kb + uint32_t(x1 - x0) + 1u];
+}
+
+// The candidate runs of the agent with record p in box (cx, cy, cz), in canonical order, into
+// column t of s_run as (first record offset in units of kUnit, length), the non-empty runs
+// first, then (0, 0); returns the candidate count.
+//
+// A box of the 27 is dropped when no sphere in it can reach the agent: every sphere has
+// r <= b / 2 (the box edge is at least the largest diameter), so a contact needs a centre
+// within r_p + b / 2 of p, and the box's nearest point is farther than that.  The distance to a
+// box follows from the gaps between p and the faces of its own box (a candidate's key puts its
+// centre beyond the shared face).  The test keeps a relative margin of 1e-3 on the squared
+// reach, far above the rounding of the gaps and of either exact contact test, so every box
+// holding a contact is kept.  Dropped boxes sit at the ends of a row (a row's middle box is the
+// nearest of the three) or are the whole row, so each row stays one contiguous run, and the
+// kept candidates keep their order.  Dropping them changes no sum: a non-contact adds nothing.
+template <uint32_t kUnit>
+__device__ __forceinline__ uint32_t load_runs(const GridDev *__restrict__ g, const uint32_t *__restrict__ start,
+                                              int cx, int cy, int cz, const double4 &p, uint2 (*s_run)[kBlock],
+                                              int t) {
+    const int nx = g->dims[0], ny = g->dims[1], nz = g->dims[2];
+    const double b = g->b;
+    const double ox = double(g->cmin[0]) + double(cx), oy = double(g->cmin[1]) + double(cy),
+                 oz = double(g->cmin[2]) + double(cz);
+    const double gxl = fmax(p.x - ox * b, 0.0), gxr = fmax((ox + 1.0) * b - p.x, 0.0);
+    const double gyl = fmax(p.y - oy * b, 0.0), gyr = fmax((oy + 1.0) * b - p.y, 0.0);
+    const double gzl = fmax(p.z - oz * b, 0.0), gzr = fmax((oz + 1.0) * b - p.z, 0.0);
+    const double reach = p.w + 0.5 * b;
+    const double T = (reach * reach) * 1.001;
+    const double gx2l = gxl * gxl, gx2r = gxr * gxr;
+    // every row loads its bounds (a row off the lattice reads a clamped, valid box and is then
+    // emptied), so the 18 loads are issued together, without branches
     uint32_t lo[9], hi[9];
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
-        const int zz = cz + r / 3 - 1, yy = cy + r % 3 - 1;
-        lo[r] = 0;
-        hi[r] = 0;
-        if (zz >= 0 && zz < nz && yy >= 0 && yy < ny) {
-            const uint32_t kb = uint32_t(x0) + uint32_t(nx) * (uint32_t(yy) + uint32_t(ny) * uint32_t(zz));
-            lo[r] = start[kb];
-            hi[r] = start[kb + uint32_t(x1 - x0) + 1u];
-        }
+        const int dz = r / 3 - 1, dy = r % 3 - 1;
+        const int zz = cz + dz, yy = cy + dy;
+        const double gy = dy < 0 ? gyl : gyr, gz = dz < 0 ? gzl : gzr;
+        const double gyz = (dy != 0 ? gy * gy : 0.0) + (dz != 0 ? gz * gz : 0.0);
+        const bool in = zz >= 0 && zz < nz && yy >= 0 && yy < ny && gyz < T;
+        const uint32_t left = (cx > 0 && gyz + gx2l < T) ? 1u : 0u;
+        const uint32_t right = (cx < nx - 1 && gyz + gx2r < T) ? 1u : 0u;
+        const uint32_t yc = uint32_t(min(max(yy, 0), ny - 1)), zc = uint32_t(min(max(zz, 0), nz - 1));
+        const uint32_t kb = uint32_t(cx) + uint32_t(nx) * (yc + uint32_t(ny) * zc);
+        const uint32_t a = start[kb - left], e = start[kb + 1u + right];
+        lo[r] = in ? a : 0u;
+        hi[r] = in ? e : 0u;
     }
-    uint32_t cnt = 0;
-    int k = 0;
+    // non-empty runs to the front in order, empty ones to the back: a permutation of the 9 rows
+    uint32_t cnt = 0, k = 0;
 #pragma unroll
-    for (int r = 0; r < 9; ++r)
-        if (hi[r] > lo[r]) {
-            s_run[k++][t] = make_uint2(lo[r], hi[r]);
-            cnt += hi[r] - lo[r];
-        }
-    for (int r = k; r < 9; ++r) s_run[r][t] = make_uint2(0u, 0u);  // empty runs after them
+    for (int r = 0; r < 9; ++r) {
+        const uint32_t len = hi[r] - lo[r];
+        const bool ne = len != 0u;
+        const uint32_t pos = ne ? k : 8u - (uint32_t(r) - k);
+        s_run[pos][t] = ne ? make_uint2(lo[r] * kUnit, len) : make_uint2(0u, 0u);
+        k += ne ? 1u : 0u;
+        cnt += len;
+    }
     return cnt;
 }
 
-// Packed-record loads: a raw buffer resource with 32-bit byte offsets when the sorted arrays
-// are below 4 GiB (one shift per address, out-of-range offsets read zero), else global loads.
-// operator() reads the binary64 record (x, y, z, r), f() its binary32 pre-test copy.
+// Packed-record loads by candidate offset u in units of kUnit.  RecBuf: a raw buffer resource
+// with 32-bit byte offsets (u is the byte offset of the binary32 copy, twice that of the
+// binary64 record) when the sorted arrays are below 4 GiB; out-of-range offsets read zero.
+// RecGlobal: plain indices.  full() reads the binary64 record (x, y, z, r), pre() its binary32
+// pre-test copy.
 struct RecBuf {
+    static constexpr uint32_t kUnit = 16;
     void *base, *basef;
     uint32_t bytes;  // of the binary64 records (the binary32 copy is half as long)
-    __device__ __forceinline__ double4 operator()(uint32_t j) const {
+    __device__ __forceinline__ double4 full(uint32_t u) const {
         const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, 0, bytes, 0x00020000);
-        const uint32_t off = j * 32u;
+        const uint32_t off = u * 2u;
         const auto lo = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
         const auto hi = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16u, 0, 0);
         const double2 a = __builtin_bit_cast(double2, lo), c = __builtin_bit_cast(double2, hi);
         return make_double4(a.x, a.y, c.x, c.y);
     }
-    __device__ __forceinline__ float4 f(uint32_t j) const {
+    __device__ __forceinline__ float4 pre(uint32_t u) const {
         const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(basef, 0, bytes / 2u, 0x00020000);
-        return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, j * 16u, 0, 0));
+        return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, u, 0, 0));
     }
 };
 struct RecGlobal {
+    static constexpr uint32_t kUnit = 1;
     const double4 *__restrict__ p;
     const float4 *__restrict__ pf;
-    __device__ __forceinline__ double4 operator()(uint32_t j) const { return p[j]; }
-    __device__ __forceinline__ float4 f(uint32_t j) const { return pf[j]; }
+    __device__ __forceinline__ double4 full(uint32_t u) const { return p[u]; }
+    __device__ __forceinline__ float4 pre(uint32_t u) const { return pf[u]; }
 };
 
 // Absolute slack of the binary32 pre-test of a slot.  Stored coordinates are relative to the
 // lattice origin o and lie within M = (largest dims + 1) * b of it (plus the rounding of x / b
 // at the lattice edges), so each is off by at most 2^-24 M and a difference by at most
 // e = 2^-23 (M + b) (with b >= r_i + r_j >= the distance of any contact).  Then the binary32
-// squared distance exceeds the true one by at most (1 + 2^-24)^3 (2 sqrt(3) d e + 3 e^2); with
-// e doubled, 4 (b + e) e bounds that.  The relative factor 1.001 on (r_i + r_j)^2 covers the
-// rounding of the radii, of their sum and square, and the rounding of every exact law's own
-// contact test.  So no pair that the exact law counts as a contact can fail the pre-test.
+// squared distance, one product and two fused multiply-adds, exceeds the true one by at most
+// (1 + 2^-24)^3 (2 sqrt(3) d e + 3 e^2); with e doubled, 4 (b + e) e bounds that.  The copy's
+// radii are scaled by 1.0006, so after the rounding of the radii, of their sum and of the fused
+// square-and-add the threshold is at least 1.0012 (r_i + r_j)^2 + slack: the relative margin
+// covers the rounding of every exact law's own contact test.  So no pair that the exact law
+// counts as a contact can fail the pre-test.
 __device__ __forceinline__ float pretest_slack(const GridDev *__restrict__ g) {
     const double b = g->b;
     int dm = g->dims[0];
@@ -137,9 +189,9 @@ __device__ __forceinline__ float pretest_slack(const GridDev *__restrict__ g) {
 // Conservative contact pre-test in binary32 (every real contact passes; see pretest_slack).
 __device__ __forceinline__ bool maybe_touch(const float4 &a, const float4 &c, float slack) {
     const float dx = a.x - c.x, dy = a.y - c.y, dz = a.z - c.z;
-    const float d2 = (dx * dx + dy * dy) + dz * dz;
-    const float s = a.w + c.w;
-    return d2 < (s * s) * 1.001f + slack;
+    const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+    const float s = a.w + c.w;  // scaled radii
+    return d2 < __builtin_fmaf(s, s, slack);
 }
 
 // Box coordinates of a key (x fastest) by fast division.
@@ -151,76 +203,99 @@ __device__ __forceinline__ void key_coords(const GridDev *__restrict__ g, uint32
     cz = int(z);
 }
 
+// Walk over a lane's packed runs (column col of s_run): next() returns the offset of the next
+// candidate in canonical order.  It has no branch: the following run is read from LDS on
+// every call and taken when the current one ends.  The run index stops at the last row, so
+// the reads stay in the table after the stream's end (candidates produced past the end are
+// only prefetched, never tested).
+struct Walker {
+    uint32_t off, left, row;
+    uint2 nxt;
+    template <uint32_t kUnit>
+    __device__ __forceinline__ uint32_t next(const uint2 (*s_run)[kBlock], int col) {
+        const uint32_t u = off;
+        const bool sw = left == 1u;
+        off = sw ? nxt.x : off + kUnit;
+        left = sw ? nxt.y : left - 1u;
+        row = sw ? min(row + 1u, 8u) : row;
+        nxt = s_run[row][col];
+        return u;
+    }
+};
+
 // Summed force on the agent with record p at sorted position q whose `cnt` candidates are the
-// runs in column `col` of s_run (canonical order); the queue uses this lane's column t.
-// The candidates are walked as one counted stream, two per iteration with the next record
-// loaded one ahead.  Survivors of the pre-test go to the queue (written unconditionally,
-// kept when they pass), which the exact law empties in order when full and at the end.
-template <bool F32, int kQ, class Rec>
+// runs in column t of s_run (canonical order); the queue uses the same column.
+// The candidates are tested two per iteration, each pre-test record loaded two candidates
+// ahead.  Survivors of the pre-test go to the queue (written unconditionally, kept when they
+// pass), which the exact law empties in order, with the next record always in flight.
+// With the normal queue the pairs run while the queue has room for two; the exact law then
+// empties it with every lane of the wavefront together (a lane whose queue fills early waits
+// for the others instead of running its own exact pass alone).  In crowded populations nearly
+// every lane fills its longer queue within a few candidates of the others, and each lane
+// empties it where it fills (measured faster there).
+template <bool F32, int kQ, class Rec, class Pre>
 __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const double4 &p, const Rec &rec,
-                                            float slack, const uint2 (*s_run)[kBlock], int col, uint32_t cnt,
-                                            uint32_t (*s_q)[kBlock], int t, double &fx, double &fy, double &fz) {
+                                            float slack, const uint2 (*s_run)[kBlock], uint32_t cnt,
+                                            uint32_t (*s_q)[kBlock], int t, const Pre &pre_final, double &fx,
+                                            double &fy, double &fz) {
+    constexpr uint32_t U = Rec::kUnit;
+    constexpr bool kSync = kQ == kQueue;
+    const uint32_t qu = q * U;
     const float rif = float(p.w);
-    const float4 pf = rec.f(q);
+    const float4 pf = rec.pre(qu);
     fx = 0.0;
     fy = 0.0;
     fz = 0.0;
-    int qn = 0;
+    uint32_t qn = 0;
+    // the record of the next queued candidate is loaded while the current one is evaluated
+    // (its registers are free once the differences are taken)
     auto flush = [&]() {
-        for (int k = 0; k < qn; ++k) exact_pair<F32>(p, rec(s_q[k][t]), rif, S, fx, fy, fz);
+        if (qn > 0) {
+            double4 r = rec.full(s_q[0][t]);
+            for (uint32_t k = 0; k < qn; ++k) {
+                const double dx = p.x - r.x, dy = p.y - r.y, dz = p.z - r.z, rj = r.w;
+                r = rec.full(s_q[k + 1u < qn ? k + 1u : k][t]);
+                exact_pair<F32>(p, dx, dy, dz, rj, rif, S, fx, fy, fz);
+            }
+        }
         qn = 0;
     };
-    int r = 0;
-    uint2 run = s_run[0][col];
-    uint32_t j = run.x, left = run.y - run.x;  // current candidate, candidates left in its run
-    // position after j (a run switch reads the next packed run)
-    auto advance = [&](uint32_t &jj, uint32_t &ll, int &rr) {
-        ++jj;
-        if (--ll == 0 && rr < 8) {
-            const uint2 u = s_run[++rr][col];
-            jj = u.x;
-            ll = u.y - u.x;
-        }
-    };
-    constexpr bool kSync = kQ == kQueue;
-    auto visit = [&](uint32_t jj, const float4 &c) {
-        s_q[qn][t] = jj;
-        qn += (maybe_touch(pf, c, slack) && jj != q) ? 1 : 0;
+    auto push = [&](uint32_t u, const float4 &c) {
+        s_q[qn][t] = u;
+        qn += (maybe_touch(pf, c, slack) && u != qu) ? 1u : 0u;
         if constexpr (!kSync) {
-            if (qn == kQ) flush();
+            if (qn == uint32_t(kQ)) flush();
         }
     };
-    // with the normal queue the inner loop fills the queue and stops at a full queue or the end
-    // of the stream; the exact law then empties it with every lane of the wavefront together (a
-    // lane whose queue fills early waits for the others instead of running its own exact pass
-    // alone).  In crowded populations nearly every lane fills its longer queue within a few
-    // candidates of the others, and each lane empties it where it fills (measured faster there).
-    float4 ca = rec.f(cnt ? j : q), cb;
+    const uint2 r0 = s_run[0][t];
+    Walker w{r0.x, r0.y, 1u, s_run[1][t]};
+    uint32_t ua = w.next<U>(s_run, t);
+    float4 ca = rec.pre(ua);
+    uint32_t ub = w.next<U>(s_run, t);
+    float4 cb = rec.pre(ub);
     uint32_t c = 0;
-    while (c < cnt) {
-        for (;;) {
-            uint32_t jn = j, ln = left;
-            int rn = r;
-            advance(jn, ln, rn);
-            cb = rec.f(c + 1 < cnt ? jn : q);
-            visit(j, ca);
-            j = jn;
-            left = ln;
-            r = rn;
-            if (++c == cnt || (kSync && qn == kQ)) {
-                ca = cb;
-                break;
-            }
-            advance(jn, ln, rn);
-            ca = rec.f(c + 1 < cnt ? jn : q);
-            visit(j, cb);
-            j = jn;
-            left = ln;
-            r = rn;
-            if (++c == cnt || (kSync && qn == kQ)) break;
+    const uint32_t pairs_end = cnt ? cnt - 1u : 0u;  // a pair starts at c while c < cnt - 1
+    for (;;) {
+        while (c < pairs_end && (!kSync || qn <= uint32_t(kQ - 2))) {
+            push(ua, ca);
+            ua = w.next<U>(s_run, t);
+            ca = rec.pre(ua);
+            push(ub, cb);
+            ub = w.next<U>(s_run, t);
+            cb = rec.pre(ub);
+            c += 2u;
         }
+        if (c >= pairs_end) break;
         flush();
+        ca = rec.pre(ua);  // reloaded rather than held in registers across the exact pass
+        cb = rec.pre(ub);
     }
+    if (c < cnt) {  // odd count: the last candidate
+        if (qn == uint32_t(kQ)) flush();
+        push(ua, ca);
+    }
+    pre_final();
+    flush();
 }
 
 // One tile: 256 agents of one slot, one lane per agent.  precision: 64 or 32 for a plain call;
@@ -240,18 +315,26 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
     if (!g->valid || l >= g->n || l >= S.capacity) return;
     const bool f32 = kPrec == 32 || (kPrec == 0 && S.force_bits == 32);
     const uint32_t q = uint32_t(g->sorted_base + l);
+    const double4 p = rec.full(q * Rec::kUnit);
     int cx, cy, cz;
     key_coords(g, key_s[q], cx, cy, cz);
-    const uint32_t cnt = load_runs(g, start_all + S.box_off, cx, cy, cz, s_run, t);
-    const double4 p = rec(q);
+    const uint32_t cnt = load_runs<Rec::kUnit>(g, start_all + S.box_off, cx, cy, cz, p, s_run, t);
     double fx, fy, fz;
+    // the agent's remaining inputs are loaded before the last exact pass, which hides their latency
+    double adh;
+    uint32_t id;
+    uint8_t state = 0;
+    auto pre = [&]() {
+        adh = adh_s[q];
+        id = id_s[q];
+        if (out.state) state = state_s[q];
+    };
     if (f32)
-        mech_forces<true, kQ>(S, q, p, rec, pretest_slack(g), s_run, t, cnt, s_q, t, fx, fy, fz);
+        mech_forces<true, kQ>(S, q, p, rec, pretest_slack(g), s_run, cnt, s_q, t, pre, fx, fy, fz);
     else
-        mech_forces<false, kQ>(S, q, p, rec, pretest_slack(g), s_run, t, cnt, s_q, t, fx, fy, fz);
+        mech_forces<false, kQ>(S, q, p, rec, pretest_slack(g), s_run, cnt, s_q, t, pre, fx, fy, fz);
 
     // adherence gate, clamp, integrate (binary64)
-    const double adh = adh_s[q];
     double nxp = p.x, nyp = p.y, nzp = p.z;
     const double fn = __builtin_sqrt((fx * fx + fy * fy) + fz * fz);
     if (!(fn < adh)) {
@@ -273,35 +356,63 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
     __builtin_nontemporal_store(nzp, &out.z[o]);
     __builtin_nontemporal_store(2.0 * p.w, &out.diam[o]);
     __builtin_nontemporal_store(adh, &out.adh[o]);
-    __builtin_nontemporal_store(id_s[q], &out.id[o]);
-    if (out.state) out.state[o] = state_s[q];
+    __builtin_nontemporal_store(id, &out.id[o]);
+    if (out.state) out.state[o] = state;
     if (out.fx) __builtin_nontemporal_store(fx, &out.fx[o]);
     if (out.fy) __builtin_nontemporal_store(fy, &out.fy[o]);
     if (out.fz) __builtin_nontemporal_store(fz, &out.fz[o]);
 }
 
+// Plain call: the tiles in the pencil order, one contiguous part of it per XCD.
 template <int kPrec, int kQ, class Rec>
-__global__ __launch_bounds__(kBlock) void k_mech(Slots sl, int64_t ntiles, const uint32_t *__restrict__ order, Rec rec,
-                                                 const double *__restrict__ adh_s,
-                                                 const uint32_t *__restrict__ id_s,
-                                                 const uint8_t *__restrict__ state_s,
-                                                 const uint32_t *__restrict__ key_s,
-                                                 const uint32_t *__restrict__ start, bdm_soa out) {
+__device__ __forceinline__ void mech_plain(const Slots &sl, const uint32_t *__restrict__ order, const Rec &rec,
+                                           const double *__restrict__ adh_s, const uint32_t *__restrict__ id_s,
+                                           const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
+                                           const uint32_t *__restrict__ start, const bdm_soa &out) {
     __shared__ uint2 s_run[9][kBlock];
     __shared__ uint32_t s_q[kQ][kBlock];
-    if (order) {  // plain call: pencil order, one contiguous part of it per XCD
-        const GridDev *g0 = &sl.grids[0];
-        if (!g0->valid) return;
-        const uint32_t live_tiles = uint32_t((g0->n + kBlock - 1) / kBlock);
-        if (blockIdx.x >= live_tiles) return;
-        mech_tile<kPrec, kQ>(sl, order[xcd_tile(blockIdx.x, live_tiles)], rec, adh_s, id_s, state_s, key_s, start, out,
+    const GridDev *g0 = &sl.grids[0];
+    if (!g0->valid) return;
+    const uint32_t live_tiles = uint32_t((g0->n + kBlock - 1) / kBlock);
+    if (blockIdx.x >= live_tiles) return;
+    mech_tile<kPrec, kQ>(sl, order[xcd_tile(blockIdx.x, live_tiles)], rec, adh_s, id_s, state_s, key_s, start, out,
                          s_run, s_q);
-        return;
-    }
-    // batch: the workgroups stride over the tiles (a simulation's tiles spread over all of them),
-    // neighbouring tiles of a round going to workgroups of one XCD
+}
+
+// The normal queue: six wavefronts per SIMD (80 registers), which is also what the LDS of a
+// workgroup allows.
+template <int kPrec, class Rec>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_mech(
+    Slots sl, const uint32_t *__restrict__ order, Rec rec, const double *__restrict__ adh_s,
+    const uint32_t *__restrict__ id_s, const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
+    const uint32_t *__restrict__ start, bdm_soa out) {
+    mech_plain<kPrec, kQueue>(sl, order, rec, adh_s, id_s, state_s, key_s, start, out);
+}
+
+// The crowded queue (its LDS allows four wavefronts per SIMD).
+template <int kPrec, class Rec>
+__global__ __launch_bounds__(kBlock) void k_mech_crowded(Slots sl, const uint32_t *__restrict__ order, Rec rec,
+                                                         const double *__restrict__ adh_s,
+                                                         const uint32_t *__restrict__ id_s,
+                                                         const uint8_t *__restrict__ state_s,
+                                                         const uint32_t *__restrict__ key_s,
+                                                         const uint32_t *__restrict__ start, bdm_soa out) {
+    mech_plain<kPrec, kQueueCrowded>(sl, order, rec, adh_s, id_s, state_s, key_s, start, out);
+}
+
+// Batch (precision per slot): the workgroups stride over the tiles (a simulation's tiles spread
+// over all of them), neighbouring tiles of a round going to workgroups of one XCD.
+template <class Rec>
+__global__ __launch_bounds__(kBlock) void k_mech_batch(Slots sl, int64_t ntiles, Rec rec,
+                                                       const double *__restrict__ adh_s,
+                                                       const uint32_t *__restrict__ id_s,
+                                                       const uint8_t *__restrict__ state_s,
+                                                       const uint32_t *__restrict__ key_s,
+                                                       const uint32_t *__restrict__ start, bdm_soa out) {
+    __shared__ uint2 s_run[9][kBlock];
+    __shared__ uint32_t s_q[kQueue][kBlock];
     for (int64_t tile = xcd_tile(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x)
-        mech_tile<kPrec, kQ>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q);
+        mech_tile<0, kQueue>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q);
 }
 
 // Test hook: contact lists per sorted slot in force-sum order (mechanical contact, plain calls).
@@ -310,9 +421,7 @@ __global__ __launch_bounds__(kBlock) void k_contacts_mech(Slots sl, const double
                                                           const uint32_t *__restrict__ start, int f32,
                                                           uint32_t *counts, const int64_t *offsets,
                                                           uint32_t *ids) {
-    __shared__ uint2 s_run[9][kBlock];
-    const int t = threadIdx.x;
-    const int64_t s = int64_t(blockIdx.x) * blockDim.x + t;
+    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const GridDev *g = &sl.grids[0];
     if (!g->valid || s >= g->n) return;
     const double b = g->b;
@@ -320,13 +429,13 @@ __global__ __launch_bounds__(kBlock) void k_contacts_mech(Slots sl, const double
     const int cx = box_coord(p.x, b, g->cmin[0], g->dims[0], false);
     const int cy = box_coord(p.y, b, g->cmin[1], g->dims[1], false);
     const int cz = box_coord(p.z, b, g->cmin[2], g->dims[2], false);
-    load_runs(g, start, cx, cy, cz, s_run, t);
     const double ri = p.w;
     const float rif = float(ri);
     uint32_t c = 0;
     for (int r = 0; r < 9; ++r) {
-        const uint2 run = s_run[r][t];
-        for (uint32_t j = run.x; j < run.y; ++j) {
+        uint32_t lo, hi;
+        row_range(g, start, cx, cy, cz, r, lo, hi);
+        for (uint32_t j = lo; j < hi; ++j) {
             if (j == uint32_t(s)) continue;
             const double4 q = pos4[j];
             const double dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
@@ -350,21 +459,22 @@ __global__ __launch_bounds__(kBlock) void k_contacts_mech(Slots sl, const double
 template <class Rec>
 static void launch_mech_rec(const bdm_soa &s, const Slots &sl, int64_t ntiles, unsigned nb, int precision,
                             bool crowded, const uint32_t *order, const Rec &rec, const Ws &w, hipStream_t st) {
-#define BDM_MECH(P, Q)                                                                                      \
-    hipLaunchKernelGGL((k_mech<P, Q, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, ntiles, order, rec, w.adh, w.ids, \
-                       w.state, w.rank, w.start, s)
+#define BDM_MECH(K, P)                                                                                     \
+    hipLaunchKernelGGL((K<P, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, order, rec, w.adh, w.ids, w.state, w.rank, \
+                       w.start, s)
     if (precision == 32) {
         if (crowded)
-            BDM_MECH(32, kQueueCrowded);
+            BDM_MECH(k_mech_crowded, 32);
         else
-            BDM_MECH(32, kQueue);
+            BDM_MECH(k_mech, 32);
     } else if (precision == 64) {
         if (crowded)
-            BDM_MECH(64, kQueueCrowded);
+            BDM_MECH(k_mech_crowded, 64);
         else
-            BDM_MECH(64, kQueue);
+            BDM_MECH(k_mech, 64);
     } else {
-        BDM_MECH(0, kQueue);
+        hipLaunchKernelGGL((k_mech_batch<Rec>), dim3(nb), dim3(kBlock), 0, st, sl, ntiles, rec, w.adh, w.ids,
+                           w.state, w.rank, w.start, s);
     }
 #undef BDM_MECH
 }

@@ -59,3 +59,33 @@ def sir_uniform(n, L, infected_fraction=0.01, seed=0):
     r = np.random.default_rng(seed)
     st = (r.random(n) < infected_fraction).astype(np.uint8)
     return dict(x=r.uniform(0, L, n), y=r.uniform(0, L, n), z=r.uniform(0, L, n), state=st)
+
+
+def reach_adversarial(pairs, b=12.0, seed=0):
+    """Pairs of spheres across box corners, edges and faces at the edge of the 27-box reach.
+
+    Sphere c has the largest diameter b (it fixes the box edge) and sits just inside the
+    neighbour box along a corner, edge or face direction u; sphere a (radius in [b/4, b/2])
+    sits at c - dist * u, with dist = (r_a + r_c) (1 -+ 1e-12): even-numbered pairs touch,
+    odd-numbered ones miss.  Along u the nearest point of c's box is then almost as far from a
+    as the whole reach r_a + b/2.  Pairs are 4 boxes apart, so no two pairs interact."""
+    r = np.random.default_rng(seed)
+    dirs = (np.array([1.0, 1.0, 1.0]), np.array([1.0, 1.0, 0.0]), np.array([1.0, 0.0, 0.0]))
+    xs, ds = [], []
+    for k in range(pairs):
+        m = np.array([k % 8, (k // 8) % 8, k // 64], dtype=np.float64) * 4.0 + 2.0
+        d = dirs[k % 3] * r.choice([-1.0, 1.0], 3)
+        perm = r.permutation(3)
+        d = d[perm]
+        u = d / np.linalg.norm(d)
+        # the corner, edge or face point of the lattice, mid-box along the unused axes
+        point = np.where(d != 0.0, m * b, (m + 0.5) * b)
+        c = point + np.sign(d) * (1e-9 * b)
+        ra = r.uniform(0.25 * b, 0.5 * b)
+        dist = (ra + 0.5 * b) * (1.0 - 1e-12 if k % 2 == 0 else 1.0 + 1e-12)
+        a = c - dist * u
+        xs += [a, c]
+        ds += [2.0 * ra, b]
+    pos = np.array(xs)
+    return dict(x=pos[:, 0].copy(), y=pos[:, 1].copy(), z=pos[:, 2].copy(), d=np.array(ds),
+                adh=np.full(len(ds), 0.4))

@@ -101,6 +101,7 @@ def grid_cases():
         "negative": {k: (v - 500.0 if k in "xyz" else v) for k, v in inputs.uniform_cube(2000, 150.0, seed=5).items()},
         "single": dict(x=np.array([3.0]), y=np.array([4.0]), z=np.array([5.0]), d=np.array([10.0]), adh=np.array([0.4])),
         "empty": dict(x=np.zeros(0), y=np.zeros(0), z=np.zeros(0), d=np.zeros(0), adh=np.zeros(0)),
+        "reach": inputs.reach_adversarial(192, 12.0, seed=7),
         "onebox": dict(x=np.full(300, 1.0) + np.arange(300) * 1e-3, y=np.ones(300), z=np.ones(300), d=np.full(300, 10.0), adh=np.full(300, 0.4)),
     }
 
@@ -179,7 +180,7 @@ def test_argument_validation():
 
 # ---------------------------------------------------------------------------------------------
 @pytest.mark.parametrize("case,bits", [("c0", 64), ("c0", 32), ("faces", 64), ("clustered", 64),
-                                       ("clustered", 32)])
+                                       ("clustered", 32), ("reach", 64), ("reach", 32)])
 def test_contacts_bit_exact(case, bits):
     say(f"case: contacts {case} bits={bits}")
     s = grid_cases()[case]
@@ -245,7 +246,8 @@ def compare_state(got, ref, L, what, fabs=None, fref=None):
 
 
 @pytest.mark.parametrize("case,bits", [("c0", 64), ("ragged", 64), ("clustered", 64), ("faces", 64),
-                                       ("c0", 32), ("clustered", 32), ("single", 64), ("empty", 64)])
+                                       ("reach", 64), ("c0", 32), ("clustered", 32), ("reach", 32),
+                                       ("single", 64), ("empty", 64)])
 def test_mech_step_lockstep(case, bits):
     say(f"case: mech lockstep {case} bits={bits}")
     s = grid_cases()[case]

@@ -164,6 +164,27 @@ def test_summed_force_vs_brute_force(orc, bits):
     assert np.all(err <= 1e-13 * np.maximum(absum, 1e-300) + 1e-300)
 
 
+@pytest.mark.parametrize("bits", [64, 32])
+def test_reach_adversarial_pairs(orc, bits):
+    """Pairs at the edge of the 27-box reach (across corners, edges and faces, the partner of
+    the largest diameter): the grid finds exactly the brute-force contacts, and in binary64 the
+    even-numbered pairs touch and the odd-numbered ones miss, as built."""
+    s = inputs.reach_adversarial(96, 12.0, seed=7)
+    n = len(s["x"])
+    pos = np.stack([s["x"], s["y"], s["z"]], axis=1)
+    near = np.linalg.norm(pos[:, None, :] - pos[None, :, :], axis=2) < 24.0
+    nref = np.zeros(n, dtype=np.int64)
+    for i in range(n):
+        for j in np.nonzero(near[i])[0]:
+            if j != i:
+                nref[i] += bool(orc_pair(s, i, j, bits, 2.0, 1.0)[0])
+    s2 = {k: v.copy() for k, v in s.items()}
+    fx, fy, fz, nc, fl = orc.mech_step(s2, force_bits=bits)
+    assert np.array_equal(nc, nref)
+    if bits == 64:
+        assert np.array_equal(nref.reshape(-1, 2)[:, 0], np.tile([1, 0], 48))
+
+
 def test_net_force_vanishes(orc):
     s = inputs.uniform_cube(4096, 200.0, seed=0)
     s2 = {k: v.copy() for k, v in s.items()}
