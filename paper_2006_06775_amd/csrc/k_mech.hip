@@ -29,35 +29,48 @@ constexpr int kQueue = 8;          // queued candidates per lane before an exact
 constexpr int kQueueCrowded = 16;  // the same for crowded populations (tens of contacts per agent)
 
 // The pair law for agent i with record p and a candidate j at offset (dx, dy, dz) = p - q with
-// radius rj, added to (fx, fy, fz) when the spheres overlap (a non-contact adds nothing).
+// radius rj: whether the spheres overlap and, if so, the term (tx, ty, tz) that j adds to the
+// force on i.  A non-contact adds nothing.
 template <bool F32>
-__device__ __forceinline__ void exact_pair(const double4 &p, double dx, double dy, double dz, double rj, float rif,
-                                           const SlotDev &a, double &fx, double &fy, double &fz) {
+__device__ __forceinline__ bool pair_term(const double4 &p, double dx, double dy, double dz, double rj, float rif,
+                                          const SlotDev &a, double &tx, double &ty, double &tz) {
     const double ri = p.w;
     if constexpr (!F32) {
         const double s = ri + rj;
         const double dist = __builtin_sqrt((dx * dx + dy * dy) + dz * dz);
         const double delta = s - dist;
-        if (!(delta > 0.0) || dist == 0.0) return;
+        if (!(delta > 0.0) || dist == 0.0) return false;
         const double rhat = (ri * rj) / s;
         const double F = a.k * delta - a.gamma * __builtin_sqrt(rhat * delta);
         const double sc = F / dist;
-        fx = fx + sc * dx;
-        fy = fy + sc * dy;
-        fz = fz + sc * dz;
+        tx = sc * dx;
+        ty = sc * dy;
+        tz = sc * dz;
     } else {
         const float dxf = float(dx), dyf = float(dy), dzf = float(dz);
         const float dist = __builtin_sqrtf((dxf * dxf + dyf * dyf) + dzf * dzf);
         const float rjf = float(rj);
         const float sf = rif + rjf;
         const float delta = sf - dist;
-        if (!(delta > 0.0f) || dist == 0.0f) return;
+        if (!(delta > 0.0f) || dist == 0.0f) return false;
         const float rhat = (rif * rjf) / sf;
         const float F = a.kf * delta - a.gf * __builtin_sqrtf(rhat * delta);
         const float sc = F / dist;
-        fx = fx + double(sc * dxf);
-        fy = fy + double(sc * dyf);
-        fz = fz + double(sc * dzf);
+        tx = double(sc * dxf);
+        ty = double(sc * dyf);
+        tz = double(sc * dzf);
+    }
+    return true;
+}
+
+template <bool F32>
+__device__ __forceinline__ void exact_pair(const double4 &p, double dx, double dy, double dz, double rj, float rif,
+                                           const SlotDev &a, double &fx, double &fy, double &fz) {
+    double tx, ty, tz;
+    if (pair_term<F32>(p, dx, dy, dz, rj, rif, a, tx, ty, tz)) {
+        fx = fx + tx;
+        fy = fy + ty;
+        fz = fz + tz;
     }
 }
 
@@ -223,6 +236,63 @@ struct Walker {
     }
 };
 
+// Orders the LDS accesses of one wavefront: the lanes' writes before the barrier are seen by the
+// reads after it (the LDS serves a wavefront's accesses in issue order; this keeps the compiler
+// from moving them across).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Final exact pass of a whole wavefront at once.  The lanes' queued candidates are laid out one
+// after another (lane order, each lane's queue order kept) and evaluated 64 at a time, one pair
+// per lane, instead of each lane walking its own queue while the lanes with shorter queues idle.
+// Each lane then adds the terms of its own pairs in its queue order, so its sum is the one its
+// own walk would give.  The run table is no longer needed here: rows 0-3 of the wavefront's
+// columns hold a round's terms, rows 4-5 the layout (lane | slot << 6 per pair, at most 512).
+// Every lane of the wavefront must take part (qbase: sorted position of its first lane).
+template <bool F32, int kQ, class Rec>
+__device__ __forceinline__ void exact_packed(const SlotDev &S, uint32_t qbase, const Rec &rec, uint32_t qn,
+                                             uint2 (*s_run)[kBlock], const uint32_t (*s_q)[kBlock], int t,
+                                             double &fx, double &fy, double &fz) {
+    static_assert(kQ <= 8, "the layout holds 64 lanes x 8 slots");
+    const int lane = t & 63, w0 = t - lane;
+    const uint32_t incl = wave_incl_scan(qn), excl = incl - qn;
+    const uint32_t total = uint32_t(__shfl(int(incl), 63, 64));
+    if (total == 0) return;
+    auto layout = [&](uint32_t e) -> uint16_t * {
+        return reinterpret_cast<uint16_t *>(&s_run[4 + (e >> 8)][w0]) + (e & 255u);
+    };
+    for (uint32_t k = 0; k < qn; ++k) *layout(excl + k) = uint16_t(uint32_t(lane) | (k << 6));
+    for (uint32_t base = 0; base < total; base += 64) {
+        wave_lds_sync();
+        const uint32_t e = base + uint32_t(lane);
+        double tx = 0.0, ty = 0.0, tz = 0.0;
+        uint32_t hit = 0;
+        if (e < total) {
+            const uint32_t m = *layout(e), o = m & 63u;
+            const double4 po = rec.full((qbase + o) * Rec::kUnit);
+            const double4 r = rec.full(s_q[m >> 6][w0 + o]);
+            hit = pair_term<F32>(po, po.x - r.x, po.y - r.y, po.z - r.z, r.w, float(po.w), S, tx, ty, tz) ? 1u : 0u;
+        }
+        s_run[0][t] = __builtin_bit_cast(uint2, tx);
+        s_run[1][t] = __builtin_bit_cast(uint2, ty);
+        s_run[2][t] = __builtin_bit_cast(uint2, tz);
+        s_run[3][t] = make_uint2(hit, 0u);
+        wave_lds_sync();
+        const uint32_t lo = excl > base ? excl : base, hi = incl < base + 64u ? incl : base + 64u;
+        for (uint32_t f = lo; f < hi; ++f) {
+            const int col = w0 + int(f - base);
+            if (s_run[3][col].x) {
+                fx = fx + __builtin_bit_cast(double, s_run[0][col]);
+                fy = fy + __builtin_bit_cast(double, s_run[1][col]);
+                fz = fz + __builtin_bit_cast(double, s_run[2][col]);
+            }
+        }
+    }
+}
+
 // Summed force on the agent with record p at sorted position q whose `cnt` candidates are the
 // runs in column t of s_run (canonical order); the queue uses the same column.
 // The candidates are tested two per iteration, each pre-test record loaded two candidates
@@ -234,8 +304,8 @@ struct Walker {
 // every lane fills its longer queue within a few candidates of the others, and each lane
 // empties it where it fills (measured faster there).
 template <bool F32, int kQ, class Rec, class Pre>
-__device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const double4 &p, const Rec &rec,
-                                            float slack, const uint2 (*s_run)[kBlock], uint32_t cnt,
+__device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, uint32_t qbase, const double4 &p,
+                                            const Rec &rec, float slack, uint2 (*s_run)[kBlock], uint32_t cnt,
                                             uint32_t (*s_q)[kBlock], int t, const Pre &pre_final, double &fx,
                                             double &fy, double &fz) {
     constexpr uint32_t U = Rec::kUnit;
@@ -295,7 +365,10 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
         push(ua, ca);
     }
     pre_final();
-    flush();
+    if constexpr (kSync)
+        exact_packed<F32, kQ>(S, qbase, rec, qn, s_run, s_q, t, fx, fy, fz);
+    else
+        flush();
 }
 
 // One tile: 256 agents of one slot, one lane per agent.  precision: 64 or 32 for a plain call;
@@ -311,14 +384,20 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
     if (slot < 0) return;
     const GridDev *g = &sl.grids[slot];
     const SlotDev S = slot_record(sl, slot);
-    const int64_t l = tile * kBlock + t - S.agent_off;  // local (sorted) index in the slot
-    if (!g->valid || l >= g->n || l >= S.capacity) return;
+    const int64_t l0 = tile * kBlock - S.agent_off;  // local (sorted) index of the tile's first agent
+    if (!g->valid || l0 >= g->n) return;
+    // Lanes past the slot's agents stay, with no candidates, because the final exact pass needs
+    // every lane of the wavefront; they read the last agent's inputs and write nothing.
+    const int64_t l = l0 + t;
+    const bool live = l < g->n && l < S.capacity;
     const bool f32 = kPrec == 32 || (kPrec == 0 && S.force_bits == 32);
-    const uint32_t q = uint32_t(g->sorted_base + l);
+    const uint32_t q = uint32_t(g->sorted_base + (l < g->n ? l : g->n - 1));
+    const uint32_t qbase = uint32_t(g->sorted_base + l0 + (t & ~63));
     const double4 p = rec.full(q * Rec::kUnit);
     int cx, cy, cz;
     key_coords(g, key_s[q], cx, cy, cz);
-    const uint32_t cnt = load_runs<Rec::kUnit>(g, start_all + S.box_off, cx, cy, cz, p, s_run, t);
+    uint32_t cnt = load_runs<Rec::kUnit>(g, start_all + S.box_off, cx, cy, cz, p, s_run, t);
+    if (!live) cnt = 0;
     double fx, fy, fz;
     // the agent's remaining inputs are loaded before the last exact pass, which hides their latency
     double adh;
@@ -330,9 +409,10 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
         if (out.state) state = state_s[q];
     };
     if (f32)
-        mech_forces<true, kQ>(S, q, p, rec, pretest_slack(g), s_run, cnt, s_q, t, pre, fx, fy, fz);
+        mech_forces<true, kQ>(S, q, qbase, p, rec, pretest_slack(g), s_run, cnt, s_q, t, pre, fx, fy, fz);
     else
-        mech_forces<false, kQ>(S, q, p, rec, pretest_slack(g), s_run, cnt, s_q, t, pre, fx, fy, fz);
+        mech_forces<false, kQ>(S, q, qbase, p, rec, pretest_slack(g), s_run, cnt, s_q, t, pre, fx, fy, fz);
+    if (!live) return;
 
     // adherence gate, clamp, integrate (binary64)
     double nxp = p.x, nyp = p.y, nzp = p.z;
