@@ -99,7 +99,7 @@ inline bool ws_layout(int64_t capacity, int64_t max_boxes, int64_t slots, WsLayo
     L->partials = take(64 * ((cap + kBoundsTile - 1) / kBoundsTile + 1));
     L->count = take(4 * (nbk + 1));
     L->bstart = take(4 * (nbk + 1));
-    L->start = take(4 * (mb + 1));
+    L->start = take(4 * (mb + 3)) + 4;  // one spare entry on each side (16-byte reads of kb - 1 .. kb + 2)
     L->tiles = take(8 * tiles);
     L->key = take(4 * cap);
     L->rank = take(4 * cap);

@@ -116,7 +116,11 @@ __device__ __forceinline__ uint32_t load_runs(const GridDev *__restrict__ g, con
     const double T = (reach * reach) * 1.001;
     const double gx2l = gxl * gxl, gx2r = gxr * gxr;
     // every row loads its bounds (a row off the lattice reads a clamped, valid box and is then
-    // emptied), so the 18 loads are issued together, without branches
+    // emptied), so the loads are issued together, without branches: one 16-byte load of the
+    // starts of boxes kb - 1 .. kb + 2 per row, through a range-checked buffer resource based
+    // one entry before the slot's starts (the workspace holds memory on both sides of them)
+    const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t *>(start - 1), 0, uint32_t(g->nboxes + 3) * 4u, 0x00020000);
     uint32_t lo[9], hi[9];
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
@@ -129,9 +133,9 @@ __device__ __forceinline__ uint32_t load_runs(const GridDev *__restrict__ g, con
         const uint32_t right = (cx < nx - 1 && gyz + gx2r < T) ? 1u : 0u;
         const uint32_t yc = uint32_t(min(max(yy, 0), ny - 1)), zc = uint32_t(min(max(zz, 0), nz - 1));
         const uint32_t kb = uint32_t(cx) + uint32_t(nx) * (yc + uint32_t(ny) * zc);
-        const uint32_t a = start[kb - left], e = start[kb + 1u + right];
-        lo[r] = in ? a : 0u;
-        hi[r] = in ? e : 0u;
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(srs, kb * 4u, 0, 0);  // kb - 1 .. kb + 2
+        lo[r] = in ? (left ? v[0] : v[1]) : 0u;
+        hi[r] = in ? (right ? v[3] : v[2]) : 0u;
     }
     // non-empty runs to the front in order, empty ones to the back: a permutation of the 9 rows
     uint32_t cnt = 0, k = 0;
