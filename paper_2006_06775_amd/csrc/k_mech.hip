@@ -253,11 +253,12 @@ __device__ __forceinline__ void wave_lds_sync() {
 // after another (lane order, each lane's queue order kept) and evaluated 64 at a time, one pair
 // per lane, instead of each lane walking its own queue while the lanes with shorter queues idle.
 // Each lane then adds the terms of its own pairs in its queue order, so its sum is the one its
-// own walk would give.  The run table is no longer needed here: rows 0-3 of the wavefront's
-// columns hold a round's terms, rows 4-5 the layout (lane | slot << 6 per pair, at most 512).
-// Every lane of the wavefront must take part (qbase: sorted position of its first lane).
+// own walk would give.  The run table is no longer needed here; in the wavefront's columns,
+// rows 0-2 hold a round's terms, rows 3 and 6-8 every lane's own record (r, x, y, z), rows 4-5
+// the layout (lane | slot << 6 per pair, at most 512; bit 15 set once the pair is a contact).
+// Every lane of the wavefront must take part.
 template <bool F32, int kQ, class Rec>
-__device__ __forceinline__ void exact_packed(const SlotDev &S, uint32_t qbase, const Rec &rec, uint32_t qn,
+__device__ __forceinline__ void exact_packed(const SlotDev &S, const double4 &p, const Rec &rec, uint32_t qn,
                                              uint2 (*s_run)[kBlock], const uint32_t (*s_q)[kBlock], int t,
                                              double &fx, double &fy, double &fz) {
     static_assert(kQ <= 8, "the layout holds 64 lanes x 8 slots");
@@ -268,27 +269,33 @@ __device__ __forceinline__ void exact_packed(const SlotDev &S, uint32_t qbase, c
     auto layout = [&](uint32_t e) -> uint16_t * {
         return reinterpret_cast<uint16_t *>(&s_run[4 + (e >> 8)][w0]) + (e & 255u);
     };
+    s_run[3][t] = __builtin_bit_cast(uint2, p.w);
+    s_run[6][t] = __builtin_bit_cast(uint2, p.x);
+    s_run[7][t] = __builtin_bit_cast(uint2, p.y);
+    s_run[8][t] = __builtin_bit_cast(uint2, p.z);
     for (uint32_t k = 0; k < qn; ++k) *layout(excl + k) = uint16_t(uint32_t(lane) | (k << 6));
     for (uint32_t base = 0; base < total; base += 64) {
         wave_lds_sync();
         const uint32_t e = base + uint32_t(lane);
         double tx = 0.0, ty = 0.0, tz = 0.0;
-        uint32_t hit = 0;
         if (e < total) {
-            const uint32_t m = *layout(e), o = m & 63u;
-            const double4 po = rec.full((qbase + o) * Rec::kUnit);
+            uint16_t *le = layout(e);
+            const uint32_t m = *le, o = m & 63u;
+            const double4 po = make_double4(
+                __builtin_bit_cast(double, s_run[6][w0 + o]), __builtin_bit_cast(double, s_run[7][w0 + o]),
+                __builtin_bit_cast(double, s_run[8][w0 + o]), __builtin_bit_cast(double, s_run[3][w0 + o]));
             const double4 r = rec.full(s_q[m >> 6][w0 + o]);
-            hit = pair_term<F32>(po, po.x - r.x, po.y - r.y, po.z - r.z, r.w, float(po.w), S, tx, ty, tz) ? 1u : 0u;
+            if (pair_term<F32>(po, po.x - r.x, po.y - r.y, po.z - r.z, r.w, float(po.w), S, tx, ty, tz))
+                *le = uint16_t(m | 0x8000u);
         }
         s_run[0][t] = __builtin_bit_cast(uint2, tx);
         s_run[1][t] = __builtin_bit_cast(uint2, ty);
         s_run[2][t] = __builtin_bit_cast(uint2, tz);
-        s_run[3][t] = make_uint2(hit, 0u);
         wave_lds_sync();
         const uint32_t lo = excl > base ? excl : base, hi = incl < base + 64u ? incl : base + 64u;
         for (uint32_t f = lo; f < hi; ++f) {
-            const int col = w0 + int(f - base);
-            if (s_run[3][col].x) {
+            if (*layout(f) & 0x8000u) {
+                const int col = w0 + int(f - base);
                 fx = fx + __builtin_bit_cast(double, s_run[0][col]);
                 fy = fy + __builtin_bit_cast(double, s_run[1][col]);
                 fz = fz + __builtin_bit_cast(double, s_run[2][col]);
@@ -308,7 +315,7 @@ __device__ __forceinline__ void exact_packed(const SlotDev &S, uint32_t qbase, c
 // every lane fills its longer queue within a few candidates of the others, and each lane
 // empties it where it fills (measured faster there).
 template <bool F32, int kQ, class Rec, class Pre>
-__device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, uint32_t qbase, const double4 &p,
+__device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const double4 &p,
                                             const Rec &rec, float slack, uint2 (*s_run)[kBlock], uint32_t cnt,
                                             uint32_t (*s_q)[kBlock], int t, const Pre &pre_final, double &fx,
                                             double &fy, double &fz) {
@@ -370,7 +377,7 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, uint32
     }
     pre_final();
     if constexpr (kSync)
-        exact_packed<F32, kQ>(S, qbase, rec, qn, s_run, s_q, t, fx, fy, fz);
+        exact_packed<F32, kQ>(S, p, rec, qn, s_run, s_q, t, fx, fy, fz);
     else
         flush();
 }
@@ -396,7 +403,6 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
     const bool live = l < g->n && l < S.capacity;
     const bool f32 = kPrec == 32 || (kPrec == 0 && S.force_bits == 32);
     const uint32_t q = uint32_t(g->sorted_base + (l < g->n ? l : g->n - 1));
-    const uint32_t qbase = uint32_t(g->sorted_base + l0 + (t & ~63));
     const double4 p = rec.full(q * Rec::kUnit);
     int cx, cy, cz;
     key_coords(g, key_s[q], cx, cy, cz);
@@ -413,9 +419,9 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
         if (out.state) state = state_s[q];
     };
     if (f32)
-        mech_forces<true, kQ>(S, q, qbase, p, rec, pretest_slack(g), s_run, cnt, s_q, t, pre, fx, fy, fz);
+        mech_forces<true, kQ>(S, q, p, rec, pretest_slack(g), s_run, cnt, s_q, t, pre, fx, fy, fz);
     else
-        mech_forces<false, kQ>(S, q, qbase, p, rec, pretest_slack(g), s_run, cnt, s_q, t, pre, fx, fy, fz);
+        mech_forces<false, kQ>(S, q, p, rec, pretest_slack(g), s_run, cnt, s_q, t, pre, fx, fy, fz);
     if (!live) return;
 
     // adherence gate, clamp, integrate (binary64)
