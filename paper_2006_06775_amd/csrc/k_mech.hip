@@ -27,6 +27,7 @@ namespace bdm {
 
 constexpr int kQueue = 8;          // queued candidates per lane before an exact pass
 constexpr int kQueueCrowded = 16;  // the same for crowded populations (tens of contacts per agent)
+constexpr uint32_t kCullMaxBox = 8;  // agents in a box up to which its agents drop out-of-reach boxes
 
 // The pair law for agent i with record p and a candidate j at offset (dx, dy, dz) = p - q with
 // radius rj: whether the spheres overlap and, if so, the term (tx, ty, tz) that j adds to the
@@ -112,8 +113,6 @@ __device__ __forceinline__ uint32_t load_runs(const GridDev *__restrict__ g, con
     const double gxl = fmax(p.x - ox * b, 0.0), gxr = fmax((ox + 1.0) * b - p.x, 0.0);
     const double gyl = fmax(p.y - oy * b, 0.0), gyr = fmax((oy + 1.0) * b - p.y, 0.0);
     const double gzl = fmax(p.z - oz * b, 0.0), gzr = fmax((oz + 1.0) * b - p.z, 0.0);
-    const double reach = p.w + 0.5 * b;
-    const double T = (reach * reach) * 1.001;
     const double gx2l = gxl * gxl, gx2r = gxr * gxr;
     // every row loads its bounds (a row off the lattice reads a clamped, valid box and is then
     // emptied), so the loads are issued together, without branches: one 16-byte load of the
@@ -121,6 +120,20 @@ __device__ __forceinline__ uint32_t load_runs(const GridDev *__restrict__ g, con
     // one entry before the slot's starts (the workspace holds memory on both sides of them)
     const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint32_t *>(start - 1), 0, uint32_t(g->nboxes + 3) * 4u, 0x00020000);
+    __attribute__((ext_vector_type(4))) uint32_t v[9];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        const int yc = min(max(cy + r % 3 - 1, 0), ny - 1), zc = min(max(cz + r / 3 - 1, 0), nz - 1);
+        const uint32_t kb = uint32_t(cx) + uint32_t(nx) * (uint32_t(yc) + uint32_t(ny) * uint32_t(zc));
+        v[r] = __builtin_amdgcn_raw_buffer_load_b128(srs, kb * 4u, 0, 0);  // kb - 1 .. kb + 2
+    }
+    // Dropping boxes pays where an agent shares its box with few others.  Agents of one box walk
+    // the same runs in step when none are dropped, so a wavefront's lanes read the same records
+    // together; dropping boxes per agent breaks that, which costs more than it saves in crowded
+    // boxes (measured: at about one agent per box dropping is faster even for boxes of four; at
+    // a few hundred per box it is a third slower).
+    const double reach = p.w + 0.5 * b;
+    const double T = v[4][2] - v[4][1] <= kCullMaxBox ? (reach * reach) * 1.001 : __builtin_inf();
     uint32_t lo[9], hi[9];
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
@@ -129,13 +142,9 @@ __device__ __forceinline__ uint32_t load_runs(const GridDev *__restrict__ g, con
         const double gy = dy < 0 ? gyl : gyr, gz = dz < 0 ? gzl : gzr;
         const double gyz = (dy != 0 ? gy * gy : 0.0) + (dz != 0 ? gz * gz : 0.0);
         const bool in = zz >= 0 && zz < nz && yy >= 0 && yy < ny && gyz < T;
-        const uint32_t left = (cx > 0 && gyz + gx2l < T) ? 1u : 0u;
-        const uint32_t right = (cx < nx - 1 && gyz + gx2r < T) ? 1u : 0u;
-        const uint32_t yc = uint32_t(min(max(yy, 0), ny - 1)), zc = uint32_t(min(max(zz, 0), nz - 1));
-        const uint32_t kb = uint32_t(cx) + uint32_t(nx) * (yc + uint32_t(ny) * zc);
-        const auto v = __builtin_amdgcn_raw_buffer_load_b128(srs, kb * 4u, 0, 0);  // kb - 1 .. kb + 2
-        lo[r] = in ? (left ? v[0] : v[1]) : 0u;
-        hi[r] = in ? (right ? v[3] : v[2]) : 0u;
+        const bool left = cx > 0 && gyz + gx2l < T, right = cx < nx - 1 && gyz + gx2r < T;
+        lo[r] = in ? (left ? v[r][0] : v[r][1]) : 0u;
+        hi[r] = in ? (right ? v[r][3] : v[r][2]) : 0u;
     }
     // non-empty runs to the front in order, empty ones to the back: a permutation of the 9 rows
     uint32_t cnt = 0, k = 0;
