@@ -265,6 +265,27 @@ def test_mech_step_lockstep(case, bits):
     assert bit.all(), "expected bit equality with the oracle (same operations, same order)"
 
 
+@pytest.mark.parametrize("bits", [64, 32])
+def test_mech_step_past_4gib_records(bits):
+    """A workspace whose packed records pass 4 GiB (capacity above 2^27) switches the mechanics
+    kernel from range-checked 32-bit buffer offsets to plain global loads; a small population in
+    it must still step bit for bit like the oracle."""
+    say(f"case: mech lockstep, capacity 2^27 + 256, bits={bits}")
+    s = grid_cases()["ragged"]
+    pop = population(s, capacity=(1 << 27) + 256, max_boxes=1 << 16)
+    p = mech_p(force_bits=bits)
+    bdm.grid_build(pop.soa, p, pop.ws)
+    bdm.mech_step(pop.soa, p, pop.ws)
+    assert bdm.status(pop.ws) == 0
+    got = pop.read()
+    ref = {k: v.copy() for k, v in s.items()}
+    fx, fy, fz, nc, fl = orc.mech_step(ref, force_bits=bits)
+    bit = compare_state(got, ref, 230.0, f"mech 2^27 capacity/{bits}", pair_abs_sum(s, bits), (fx, fy, fz))
+    assert bit.all()
+    del pop
+    torch.cuda.empty_cache()
+
+
 def test_mech_clamp_and_gate_regimes():
     say("case: mech clamp/gate")
     s = inputs.uniform_cube(3000, 200.0, seed=21)  # with dt 0.5 all three regimes occur
