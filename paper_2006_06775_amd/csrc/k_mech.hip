@@ -4,9 +4,10 @@
 //
 // One lane per agent in box-sorted order.  The 27 neighbour boxes are 9 contiguous key runs
 // (dz, dy in {-1, 0, 1}; dx = -1..+1 adjacent in key space because x varies fastest), so
-// candidates arrive in ascending (key, id) order -- the canonical summation order.  Boxes that
-// no sphere in them can reach are dropped from the ends of these runs (about a third of the 27
-// at uniform density; see load_runs), which removes only non-contacts.
+// candidates arrive in ascending (key, id) order -- the canonical summation order.  For agents
+// in sparsely filled boxes, boxes that no sphere in them can reach are dropped from the ends of
+// these runs (about a third of the 27 at uniform density; see load_runs), which removes only
+// non-contacts.
 //
 // The work is split in two so that the wavefront does not pay the expensive exact law for
 // every candidate of every lane:
@@ -14,7 +15,9 @@
 //      and keeps the candidates that pass a cheap conservative squared-distance test in a small
 //      per-lane queue in LDS;
 //   2. exact pass: the queued candidates, still in canonical order, are re-read and evaluated
-//      exactly as the definition spells the law (binary64 or binary32) and summed.
+//      exactly as the definition spells the law (binary64 or binary32) and summed.  At the end
+//      of the stream the wavefront evaluates all its lanes' queued pairs together, one pair per
+//      lane (exact_packed); each lane still adds its own terms in its own order.
 // The packed record holds (x, y, z, r) with r = d/2.
 //
 // Schedule: a tile is 256 consecutive sorted agents.  A plain call processes its tiles in the
@@ -320,9 +323,9 @@ __device__ __forceinline__ void exact_packed(const SlotDev &S, const double4 &p,
 // pass), which the exact law empties in order, with the next record always in flight.
 // With the normal queue the pairs run while the queue has room for two; the exact law then
 // empties it with every lane of the wavefront together (a lane whose queue fills early waits
-// for the others instead of running its own exact pass alone).  In crowded populations nearly
-// every lane fills its longer queue within a few candidates of the others, and each lane
-// empties it where it fills (measured faster there).
+// for the others instead of running its own exact pass alone), and the last pass is the
+// packed one.  In crowded populations nearly every lane fills its longer queue within a few
+// candidates of the others, and each lane empties it where it fills (measured faster there).
 template <bool F32, int kQ, class Rec, class Pre>
 __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const double4 &p,
                                             const Rec &rec, float slack, uint2 (*s_run)[kBlock], uint32_t cnt,
