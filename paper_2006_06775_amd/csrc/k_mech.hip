@@ -473,8 +473,11 @@ __device__ __forceinline__ void mech_plain(const Slots &sl, const uint32_t *__re
                                            const uint32_t *__restrict__ start, const bdm_soa &out) {
     __shared__ uint2 s_run[9][kBlock];
     __shared__ uint32_t s_q[kQ][kBlock];
-    const GridDev *g0 = &sl.grids[0];
-    if (!g0->valid) return;
+    GridDev *g0 = &sl.grids[0];
+    if (!g0->valid) {  // no grid of these agents (never built, or its build failed): report it
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&g0->flags, BDM_FLAG_NOGRID);
+        return;
+    }
     const uint32_t live_tiles = uint32_t((g0->n + kBlock - 1) / kBlock);
     if (blockIdx.x >= live_tiles) return;
     mech_tile<kPrec, kQ>(sl, order[xcd_tile(blockIdx.x, live_tiles)], rec, adh_s, id_s, state_s, key_s, start, out,

@@ -153,6 +153,12 @@ def test_grid_explicit_box_and_flags():
     x0 = pop.t["x"][:1000].clone()
     bdm.mech_step(pop.soa, mech_p(box=5.0), pop.ws)
     assert torch.equal(pop.t["x"][:1000], x0)
+    assert bdm.status(pop.ws, clear=True) == bdm.FLAG_NOGRID  # the step reports the missing grid
+    # a mechanical step on a workspace that never held a grid moves nothing and says so
+    fresh = population(s, max_boxes=1 << 16)
+    bdm.mech_step(fresh.soa, mech_p(), fresh.ws)
+    assert torch.equal(fresh.t["x"][:1000], torch.as_tensor(s["x"], device="cuda"))
+    assert bdm.status(fresh.ws) == bdm.FLAG_NOGRID
     # too many boxes for the workspace
     small = population(s, max_boxes=10)
     bdm.grid_build(small.soa, mech_p(), small.ws)
