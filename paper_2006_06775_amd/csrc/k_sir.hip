@@ -37,8 +37,6 @@ __global__ __launch_bounds__(kBlock) void k_sir(Slots sl, const double4 *__restr
     const uint32_t *start = start_all + S.box_off;
     const int64_t l = tile * kBlock + threadIdx.x - S.agent_off;
     const bool live = g->valid && l < g->n && l < S.capacity;
-    if (!g->valid && !sl.table && tile == 0 && threadIdx.x == 0)  // a plain step with no grid
-        atomicOr(&g->flags, BDM_FLAG_NOGRID);
     uint8_t ns = 3;  // no agent
     if (live) {
         const uint32_t q = uint32_t(g->sorted_base + l);
