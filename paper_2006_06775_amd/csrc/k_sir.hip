@@ -4,7 +4,8 @@
 //
 // One lane per agent in box-sorted order on the periodic grid of positions at t.  Everything
 // reads state/positions at t (the sorted copies in the workspace) and writes t+1 into the
-// caller's arrays, so the update is synchronous.  Random numbers are Philox blocks keyed by
+// caller's arrays, so the update is synchronous.  The infected neighbours of each susceptible
+// agent are counted from the infected side (k_sir_seed) before the step.  Random numbers are Philox blocks keyed by
 // (seed, salt) at counter (purpose + attempt*2^8, agent id, step, 0): the outcome of every agent
 // depends only on its id and the step, never on the order of the lanes.
 #include "kernels.hpp"
@@ -24,17 +25,75 @@ __device__ __forceinline__ double wrap(double v, double L) {
     return v;
 }
 
+// Contact counts of the susceptible agents, zeroed before they are gathered.
+__global__ __launch_bounds__(kBlock) void k_sir_zero(Slots sl, uint32_t *__restrict__ m) {
+    const int64_t tile = blockIdx.x;
+    const int slot = slot_of_tile(sl, tile);
+    if (slot < 0) return;
+    const GridDev *g = &sl.grids[slot];
+    const SlotDev S = slot_record(sl, slot);
+    const int64_t l = tile * kBlock + threadIdx.x - S.agent_off;
+    if (g->valid && l < g->n) m[g->sorted_base + l] = 0u;
+}
+
+// Every infected agent adds one to the count m of each susceptible agent within the infection
+// radius (inclusive, periodic minimum image) among its 27 boxes.  This is the count each
+// susceptible agent would find among its own 27 boxes: the periodic box neighbourhood is
+// symmetric (at least 3 boxes per axis), and so is the minimum-image squared distance (a
+// difference and its negation round to opposite values, and the image shift is applied
+// symmetrically).  The count is an integer, so the order of the additions does not matter.  The
+// work is proportional to the infected agents, a small fraction of the population.
+__global__ __launch_bounds__(kBlock) void k_sir_seed(Slots sl, const double4 *__restrict__ pos4,
+                                                     const uint8_t *__restrict__ state_s,
+                                                     const uint32_t *__restrict__ start_all, SirArgs a,
+                                                     uint32_t *m) {
+    const int64_t tile = blockIdx.x;
+    const int slot = slot_of_tile(sl, tile);
+    if (slot < 0) return;
+    const GridDev *g = &sl.grids[slot];
+    const SlotDev S = slot_record(sl, slot);
+    const int64_t l = tile * kBlock + threadIdx.x - S.agent_off;
+    if (!g->valid || l >= g->n || l >= S.capacity) return;
+    const uint32_t q = uint32_t(g->sorted_base + l);
+    if (state_s[q] != 1) return;
+    const uint32_t *start = start_all + S.box_off;
+    const double4 p = pos4[q];
+    const int nb = g->dims[0];
+    const double b = g->b;
+    const int cx = box_coord(p.x, b, 0, nb, true);
+    const int cy = box_coord(p.y, b, 0, nb, true);
+    const int cz = box_coord(p.z, b, 0, nb, true);
+    for (int oz = -1; oz <= 1; ++oz) {
+        const int zz = (cz + oz + nb) % nb;
+        for (int oy = -1; oy <= 1; ++oy) {
+            const int yy = (cy + oy + nb) % nb;
+            for (int ox = -1; ox <= 1; ++ox) {
+                const int xx = (cx + ox + nb) % nb;
+                const uint32_t kb = uint32_t(xx) + uint32_t(nb) * (uint32_t(yy) + uint32_t(nb) * uint32_t(zz));
+                const uint32_t j1 = start[kb + 1];
+                for (uint32_t j = start[kb]; j < j1; ++j) {
+                    if (state_s[j] != 0) continue;
+                    const double4 c = pos4[j];
+                    const double dx = min_image(c.x - p.x, a.L, a.half);
+                    const double dy = min_image(c.y - p.y, a.L, a.half);
+                    const double dz = min_image(c.z - p.z, a.L, a.half);
+                    if (((dx * dx + dy * dy) + dz * dz) <= a.r2) atomicAdd(&m[j], 1u);
+                }
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_sir(Slots sl, const double4 *__restrict__ pos4,
                                                 const uint8_t *__restrict__ state_s,
                                                 const uint32_t *__restrict__ id_s,
-                                                const uint32_t *__restrict__ start_all, SirArgs a,
-                                                bdm_soa out) {
+                                                const uint32_t *__restrict__ m_s, SirArgs a,
+                                                bdm_soa out, uint32_t *__restrict__ tile_counts) {
     const int64_t tile = blockIdx.x;
     const int slot = slot_of_tile(sl, tile);
     if (slot < 0) return;
     GridDev *g = &sl.grids[slot];
     const SlotDev S = slot_record(sl, slot);
-    const uint32_t *start = start_all + S.box_off;
     const int64_t l = tile * kBlock + threadIdx.x - S.agent_off;
     const bool live = g->valid && l < g->n && l < S.capacity;
     uint8_t ns = 3;  // no agent
@@ -45,31 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_sir(Slots sl, const double4 *__restr
         const uint32_t me = id_s[q];
         ns = st;
         if (st == 0) {
-            const int nb = g->dims[0];
-            const double b = g->b;
-            const int cx = box_coord(p.x, b, 0, nb, true);
-            const int cy = box_coord(p.y, b, 0, nb, true);
-            const int cz = box_coord(p.z, b, 0, nb, true);
-            uint32_t m = 0;
-            for (int oz = -1; oz <= 1; ++oz) {
-                const int zz = (cz + oz + nb) % nb;
-                for (int oy = -1; oy <= 1; ++oy) {
-                    const int yy = (cy + oy + nb) % nb;
-                    for (int ox = -1; ox <= 1; ++ox) {
-                        const int xx = (cx + ox + nb) % nb;
-                        const uint32_t kb = uint32_t(xx) + uint32_t(nb) * (uint32_t(yy) + uint32_t(nb) * uint32_t(zz));
-                        const uint32_t j1 = start[kb + 1];
-                        for (uint32_t j = start[kb]; j < j1; ++j) {
-                            if (j == q || state_s[j] != 1) continue;
-                            const double4 c = pos4[j];
-                            const double dx = min_image(p.x - c.x, a.L, a.half);
-                            const double dy = min_image(p.y - c.y, a.L, a.half);
-                            const double dz = min_image(p.z - c.z, a.L, a.half);
-                            m += ((dx * dx + dy * dy) + dz * dz) <= a.r2;
-                        }
-                    }
-                }
-            }
+            const uint32_t m = m_s[q];  // infected agents within the radius (k_sir_seed)
             for (uint32_t c = 0; c < m; ++c) {
                 if (bernoulli(draw(a.seed, a.salt, kRngInf, c, me, a.step).w[0], a.tinf)) {
                     ns = 1;
@@ -87,13 +122,40 @@ __global__ __launch_bounds__(kBlock) void k_sir(Slots sl, const double4 *__restr
         out.state[o] = ns;
         out.id[o] = me;
     }
-    // S/I/R totals: one atomic per wavefront and group
+    // S/I/R totals of the tile, summed over the tiles by k_sir_total.  (Atomics from every
+    // wavefront onto the three totals serialised at the memory side: about 2 ms per step at
+    // 10^7 agents.)
+    __shared__ uint32_t s_cnt[kBlock / 64][3];
     const uint32_t cs = wave_sum(ns == 0), ci = wave_sum(ns == 1), cr = wave_sum(ns == 2);
     if ((threadIdx.x & 63) == 0) {
-        if (cs) atomicAdd(&g->sir_counts[0], static_cast<unsigned long long>(cs));
-        if (ci) atomicAdd(&g->sir_counts[1], static_cast<unsigned long long>(ci));
-        if (cr) atomicAdd(&g->sir_counts[2], static_cast<unsigned long long>(cr));
+        s_cnt[threadIdx.x >> 6][0] = cs;
+        s_cnt[threadIdx.x >> 6][1] = ci;
+        s_cnt[threadIdx.x >> 6][2] = cr;
     }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        uint32_t v = 0;
+        for (int w = 0; w < kBlock / 64; ++w) v += s_cnt[w][threadIdx.x];
+        tile_counts[4 * tile + threadIdx.x] = v;
+    }
+}
+
+// The S/I/R totals of a plain step: the sum of the tiles' counts (one workgroup).
+constexpr int kTotalThreads = 1024;
+__global__ __launch_bounds__(kTotalThreads) void k_sir_total(GridDev *g, const uint32_t *__restrict__ tile_counts,
+                                                             int64_t ntiles) {
+    unsigned long long v[3] = {0ull, 0ull, 0ull};
+    for (int64_t t = threadIdx.x; t < ntiles; t += kTotalThreads)
+        for (int k = 0; k < 3; ++k) v[k] += tile_counts[4 * t + k];
+    __shared__ unsigned long long s_sum[kTotalThreads][3];
+    for (int k = 0; k < 3; ++k) s_sum[threadIdx.x][k] = v[k];
+    __syncthreads();
+    for (int off = kTotalThreads / 2; off > 0; off >>= 1) {
+        if (int(threadIdx.x) < off)
+            for (int k = 0; k < 3; ++k) s_sum[threadIdx.x][k] += s_sum[threadIdx.x + off][k];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) g->sir_counts[threadIdx.x] = s_sum[0][threadIdx.x];
 }
 
 // Test hook: SIR contacts (any state) per sorted slot, boxes visited in (dz, dy, dx) order.
@@ -140,7 +202,16 @@ void launch_sir(const bdm_soa &s, const Slots &sl, int64_t capacity, const SirAr
                 hipStream_t st) {
     int64_t nb = (capacity + kBlock - 1) / kBlock;
     if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_sir, dim3(unsigned(nb)), dim3(kBlock), 0, st, sl, w.pos4, w.state, w.ids, w.start, a, s);
+    // the contact counts live in the division-flag array, free once the grid is built
+    hipLaunchKernelGGL(k_sir_zero, dim3(unsigned(nb)), dim3(kBlock), 0, st, sl, w.flagid);
+    hipLaunchKernelGGL(k_sir_seed, dim3(unsigned(nb)), dim3(kBlock), 0, st, sl, w.pos4, w.state, w.start, a,
+                       w.flagid);
+    // the tiles' S/I/R counts go to the bounds partials (free once the grid is built; 16 bytes
+    // per 256 agents fit in their 64 bytes per 1024)
+    uint32_t *tile_counts = reinterpret_cast<uint32_t *>(w.partials);
+    hipLaunchKernelGGL(k_sir, dim3(unsigned(nb)), dim3(kBlock), 0, st, sl, w.pos4, w.state, w.ids, w.flagid, a, s,
+                       tile_counts);
+    hipLaunchKernelGGL(k_sir_total, dim3(1), dim3(kTotalThreads), 0, st, sl.grids, tile_counts, nb);
 }
 
 void launch_contacts(const ContactArgs &a, const Slots &sl, const Ws &w, uint32_t *counts,
