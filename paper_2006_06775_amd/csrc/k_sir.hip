@@ -39,10 +39,9 @@ __global__ __launch_bounds__(kBlock) void k_sir_zero(Slots sl, uint32_t *__restr
 // Every infected agent adds one to the count m of each susceptible agent within the infection
 // radius (inclusive, periodic minimum image) among its 27 boxes.  This is the count each
 // susceptible agent would find among its own 27 boxes: the periodic box neighbourhood is
-// symmetric (at least 3 boxes per axis), and so is the minimum-image squared distance (a
-// difference and its negation round to opposite values, and the image shift is applied
-// symmetrically).  The count is an integer, so the order of the additions does not matter.  The
-// work is proportional to the infected agents, a small fraction of the population.
+// symmetric (at least 3 boxes per axis), and the differences are taken as susceptible minus
+// infected, exactly as the susceptible agent takes them.  The count is an integer, so the order
+// of the additions does not matter.  The work is proportional to the infected agents.
 __global__ __launch_bounds__(kBlock) void k_sir_seed(Slots sl, const double4 *__restrict__ pos4,
                                                      const uint8_t *__restrict__ state_s,
                                                      const uint32_t *__restrict__ start_all, SirArgs a,
