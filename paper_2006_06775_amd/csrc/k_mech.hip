@@ -105,10 +105,18 @@ __device__ __forceinline__ void row_range(const GridDev *__restrict__ g, const u
 // holding a contact is kept.  Dropped boxes sit at the ends of a row (a row's middle box is the
 // nearest of the three) or are the whole row, so each row stays one contiguous run, and the
 // kept candidates keep their order.  Dropping them changes no sum: a non-contact adds nothing.
-template <uint32_t kUnit>
+// Where the lanes of a wavefront walk nearly the same runs (agents packed into a few crowded
+// boxes), they walk the union of their runs together instead: row r's union is
+// [lo[r], hi[r]) in record indices, and `coop` says the wavefront does so (uniform).
+struct RowUnion {
+    uint32_t lo[9], hi[9];
+    bool coop;
+};
+
+template <uint32_t kUnit, bool kCoop>
 __device__ __forceinline__ uint32_t load_runs(const GridDev *__restrict__ g, const uint32_t *__restrict__ start,
-                                              int cx, int cy, int cz, const double4 &p, uint2 (*s_run)[kBlock],
-                                              int t) {
+                                              int cx, int cy, int cz, const double4 &p, bool live,
+                                              uint2 (*s_run)[kBlock], int t, RowUnion &un) {
     const int nx = g->dims[0], ny = g->dims[1], nz = g->dims[2];
     const double b = g->b;
     const double ox = double(g->cmin[0]) + double(cx), oy = double(g->cmin[1]) + double(cy),
@@ -146,8 +154,28 @@ __device__ __forceinline__ uint32_t load_runs(const GridDev *__restrict__ g, con
         const double gyz = (dy != 0 ? gy * gy : 0.0) + (dz != 0 ? gz * gz : 0.0);
         const bool in = zz >= 0 && zz < nz && yy >= 0 && yy < ny && gyz < T;
         const bool left = cx > 0 && gyz + gx2l < T, right = cx < nx - 1 && gyz + gx2r < T;
-        lo[r] = in ? (left ? v[r][0] : v[r][1]) : 0u;
-        hi[r] = in ? (right ? v[r][3] : v[r][2]) : 0u;
+        lo[r] = in && live ? (left ? v[r][0] : v[r][1]) : 0u;
+        hi[r] = in && live ? (right ? v[r][3] : v[r][2]) : 0u;
+    }
+    un.coop = false;
+    if constexpr (kCoop) {
+        // every lane takes part (the wavefront's lanes are all active here)
+        uint32_t own = 0, total = 0;
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            const bool ne = hi[r] > lo[r];
+            un.lo[r] = wave_min(ne ? lo[r] : 0xFFFFFFFFu);
+            un.hi[r] = wave_max(ne ? hi[r] : 0u);
+            own += hi[r] - lo[r];
+            total += un.hi[r] > un.lo[r] ? un.hi[r] - un.lo[r] : 0u;
+        }
+        // together when the union is at most twice the longest own stream
+        un.coop = total <= 2u * wave_max(own);
+        if (un.coop) {  // the table holds each row in place: (first, end) record indices
+#pragma unroll
+            for (int r = 0; r < 9; ++r) s_run[r][t] = make_uint2(lo[r], hi[r]);
+            return own;
+        }
     }
     // non-empty runs to the front in order, empty ones to the back: a permutation of the 9 rows
     uint32_t cnt = 0, k = 0;
@@ -329,8 +357,9 @@ __device__ __forceinline__ void exact_packed(const SlotDev &S, const double4 &p,
 template <bool F32, int kQ, class Rec, class Pre>
 __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const double4 &p,
                                             const Rec &rec, float slack, uint2 (*s_run)[kBlock], uint32_t cnt,
-                                            uint32_t (*s_q)[kBlock], int t, const Pre &pre_final, double &fx,
-                                            double &fy, double &fz) {
+                                            uint32_t (*s_q)[kBlock], int t, const Pre &pre_final,
+                                            const RowUnion &un, float4 *s_stage, double &fx, double &fy,
+                                            double &fz) {
     constexpr uint32_t U = Rec::kUnit;
     constexpr bool kSync = kQ == kQueue;
     const uint32_t qu = q * U;
@@ -360,6 +389,38 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
             if (qn == uint32_t(kQ)) flush();
         }
     };
+    if (un.coop) {
+        // The wavefront walks the union of its lanes' runs row by row, 64 records at a time:
+        // lane k loads record base + k (one coalesced load for the wavefront, the next chunk in
+        // flight while this one is tested), the chunk goes through LDS, and every lane tests
+        // each record that lies in its own run, in order.  A lane's candidates thus come in its
+        // canonical order.  The queues are emptied together when one of them is full.
+        const int lane = t & 63, w0 = t - lane;
+#pragma unroll 1
+        for (int r = 0; r < 9; ++r) {
+            const uint32_t ulo = un.lo[r], uhi = un.hi[r];
+            if (ulo >= uhi) continue;
+            const uint2 own = s_run[r][t];
+            float4 nxt = rec.pre(min(ulo + uint32_t(lane), uhi - 1u) * U);
+            for (uint32_t base = ulo; base < uhi; base += 64u) {
+                wave_lds_sync();
+                s_stage[t] = nxt;
+                if (base + 64u < uhi) nxt = rec.pre(min(base + 64u + uint32_t(lane), uhi - 1u) * U);
+                wave_lds_sync();
+                const uint32_t kn = min(64u, uhi - base);
+                for (uint32_t k = 0; k < kn; ++k) {
+                    const uint32_t j = base + k;
+                    const float4 cand = s_stage[w0 + int(k)];
+                    s_q[qn][t] = j * U;
+                    qn += (j >= own.x && j < own.y && j != q && maybe_touch(pf, cand, slack)) ? 1u : 0u;
+                    if (__any(qn == uint32_t(kQ))) flush();
+                }
+            }
+        }
+        pre_final();
+        flush();
+        return;
+    }
     const uint2 r0 = s_run[0][t];
     Walker w{r0.x, r0.y, 1u, s_run[1][t]};
     uint32_t ua = w.next<U>(s_run, t);
@@ -401,7 +462,7 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
                                           const double *__restrict__ adh_s, const uint32_t *__restrict__ id_s,
                                           const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
                                           const uint32_t *__restrict__ start_all, const bdm_soa &out,
-                                          uint2 (*s_run)[kBlock], uint32_t (*s_q)[kBlock]) {
+                                          uint2 (*s_run)[kBlock], uint32_t (*s_q)[kBlock], float4 *s_stage) {
     const int t = threadIdx.x;
     const int slot = slot_of_tile(sl, tile);
     if (slot < 0) return;
@@ -418,8 +479,9 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
     const double4 p = rec.full(q * Rec::kUnit);
     int cx, cy, cz;
     key_coords(g, key_s[q], cx, cy, cz);
-    uint32_t cnt = load_runs<Rec::kUnit>(g, start_all + S.box_off, cx, cy, cz, p, s_run, t);
-    if (!live) cnt = 0;
+    RowUnion un;
+    const uint32_t cnt = load_runs<Rec::kUnit, kQ == kQueueCrowded>(g, start_all + S.box_off, cx, cy, cz, p, live,
+                                                                  s_run, t, un);
     double fx, fy, fz;
     // the agent's remaining inputs are loaded before the last exact pass, which hides their latency
     double adh;
@@ -431,9 +493,9 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
         if (out.state) state = state_s[q];
     };
     if (f32)
-        mech_forces<true, kQ>(S, q, p, rec, pretest_slack(g), s_run, cnt, s_q, t, pre, fx, fy, fz);
+        mech_forces<true, kQ>(S, q, p, rec, pretest_slack(g), s_run, cnt, s_q, t, pre, un, s_stage, fx, fy, fz);
     else
-        mech_forces<false, kQ>(S, q, p, rec, pretest_slack(g), s_run, cnt, s_q, t, pre, fx, fy, fz);
+        mech_forces<false, kQ>(S, q, p, rec, pretest_slack(g), s_run, cnt, s_q, t, pre, un, s_stage, fx, fy, fz);
     if (!live) return;
 
     // adherence gate, clamp, integrate (binary64)
@@ -473,6 +535,7 @@ __device__ __forceinline__ void mech_plain(const Slots &sl, const uint32_t *__re
                                            const uint32_t *__restrict__ start, const bdm_soa &out) {
     __shared__ uint2 s_run[9][kBlock];
     __shared__ uint32_t s_q[kQ][kBlock];
+    __shared__ float4 s_stage[kQ == kQueueCrowded ? kBlock : 1];  // records of a cooperative walk
     GridDev *g0 = &sl.grids[0];
     if (!g0->valid) {  // no grid of these agents (never built, or its build failed): report it
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&g0->flags, BDM_FLAG_NOGRID);
@@ -481,7 +544,7 @@ __device__ __forceinline__ void mech_plain(const Slots &sl, const uint32_t *__re
     const uint32_t live_tiles = uint32_t((g0->n + kBlock - 1) / kBlock);
     if (blockIdx.x >= live_tiles) return;
     mech_tile<kPrec, kQ>(sl, order[xcd_tile(blockIdx.x, live_tiles)], rec, adh_s, id_s, state_s, key_s, start, out,
-                         s_run, s_q);
+                         s_run, s_q, s_stage);
 }
 
 // The normal queue: six wavefronts per SIMD (80 registers), which is also what the LDS of a
@@ -517,7 +580,7 @@ __global__ __launch_bounds__(kBlock) void k_mech_batch(Slots sl, int64_t ntiles,
     __shared__ uint2 s_run[9][kBlock];
     __shared__ uint32_t s_q[kQueue][kBlock];
     for (int64_t tile = xcd_tile(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x)
-        mech_tile<0, kQueue>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q);
+        mech_tile<0, kQueue>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q, nullptr);
 }
 
 // Test hook: contact lists per sorted slot in force-sum order (mechanical contact, plain calls).
