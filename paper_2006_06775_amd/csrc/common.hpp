@@ -40,7 +40,7 @@ struct GridDev {
     int32_t valid;                  // 1 when the last build succeeded
     uint32_t flags;                 // sticky BDM_FLAG_* bits
     uint32_t scan_ticket;           // dynamic tile index of the running scan (slot 0 only)
-    uint32_t pad0;
+    uint32_t crowd_n;               // crowded buckets listed by the bucket sort of the running build
     unsigned long long div_nx;      // fast-division multipliers of dims[0] and dims[1]
     unsigned long long div_ny;
     unsigned long long sir_counts[3];
@@ -69,7 +69,7 @@ struct SlotDev {
 // workspace (one grid record, slot passed by value); > 0 is a batch of that many slots.
 struct WsLayout {
     size_t grid, slots, tilemap, bucketmap, partials, count, bstart, start, tiles, key, rank, item, tmpid, pos4, pos4f, adh,
-        ids, state, flagid, rankid, order_bins;
+        ids, state, flagid, rankid, order_bins, crowd;
     size_t total;
     int64_t capacity, max_boxes, max_tiles, nslots, ntiles, nbuckets;
 };
@@ -113,6 +113,7 @@ inline bool ws_layout(int64_t capacity, int64_t max_boxes, int64_t slots, WsLayo
     L->flagid = take(4 * (cap + 1));
     L->rankid = take(4 * (cap + 1));
     L->order_bins = take(3 * 4 * size_t(kOrderBins));
+    L->crowd = take(4 * (nbk + 1));  // buckets the bucket sort hands to the crowded-box ranking
     L->total = off;
     L->capacity = capacity;
     L->max_boxes = max_boxes;
@@ -142,6 +143,7 @@ struct Ws {
     uint8_t *state;
     uint32_t *flagid, *rankid;
     uint32_t *order_first, *order_last, *order_shift;  // tile-order runs per bin (plain calls)
+    uint32_t *crowd;     // crowded buckets of the running build (bucket sort -> crowded-box ranking)
     WsLayout lay;
 };
 
@@ -168,6 +170,7 @@ inline Ws ws_view(void *base, const WsLayout &L) {
     w.state = reinterpret_cast<uint8_t *>(p + L.state);
     w.flagid = reinterpret_cast<uint32_t *>(p + L.flagid);
     w.rankid = reinterpret_cast<uint32_t *>(p + L.rankid);
+    w.crowd = reinterpret_cast<uint32_t *>(p + L.crowd);
     w.order_first = reinterpret_cast<uint32_t *>(p + L.order_bins);
     w.order_last = w.order_first + kOrderBins;
     w.order_shift = w.order_last + kOrderBins;

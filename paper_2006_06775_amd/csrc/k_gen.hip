@@ -70,6 +70,7 @@ __device__ void clear_grid(GridDev *g) {
     g->valid = 0;
     g->flags = 0u;
     g->scan_ticket = 0u;
+    g->crowd_n = 0u;
     g->sorted_base = 0;
 }
 

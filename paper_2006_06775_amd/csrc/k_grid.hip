@@ -21,6 +21,7 @@ namespace bdm {
 
 constexpr int kPencilRows = 16;       // y-rows per pencil of the processing order
 constexpr int kBucketLds = 1024;      // agents of a bucket whose ids the sort keeps in LDS
+constexpr int kCrowdedGroups = 1024;  // workgroups that rank the boxes of crowded buckets
 
 // Per workgroup of kBoundsTile agents: min/max of x, y, z, max diameter and a non-finite flag,
 // written as one 8-value partial record (no atomics).
@@ -98,7 +99,10 @@ __global__ __launch_bounds__(kBlock) void k_bounds(Slots sl, int64_t nbtiles, co
                                                    unsigned long long *tiles, int64_t max_tiles) {
     if (blockIdx.x == 0) {  // reset the scan tiles of the coming histogram scan
         for (int64_t t = threadIdx.x; t < max_tiles; t += blockDim.x) tiles[t] = 0ull;
-        if (threadIdx.x == 0) sl.grids[0].scan_ticket = 0u;
+        if (threadIdx.x == 0) {
+            sl.grids[0].scan_ticket = 0u;
+            sl.grids[0].crowd_n = 0u;
+        }
     }
     for (int64_t bt = blockIdx.x; bt < nbtiles; bt += gridDim.x) bounds_tile(sl, bt, n_ptr, x, y, z, d, partials);
 }
@@ -522,13 +526,65 @@ __device__ __forceinline__ void run_small(int lane, Fetch &fetch, Count &count, 
     for (int u = 0; u < K; ++u) emit(a[u]);
 }
 
+// What the bucket sort reads and writes, for the helpers below.
+struct SortCtx {
+    Slots sl;
+    SoaIn s;
+    const uint32_t *key;
+    SortOut o;
+    int periodic;
+    int64_t capacity;
+};
+
+// The agent at input index i, for a bucket whose first box is box0 (kl >= 64 marks an entry to
+// skip: an index or key that cannot come from a valid build); `full` also loads what the copy
+// needs.
+__device__ __forceinline__ BucketAgent sort_agent(const SortCtx &c, int64_t box0, int64_t i, bool full) {
+    BucketAgent a{};
+    a.kl = 0xFFFFFFFFu;
+    a.slot = -1;
+    a.i = i;
+    if (i < 0 || i >= c.capacity) return a;
+    a.slot = slot_of_tile(c.sl, i / kBlock);
+    if (a.slot < 0) return a;
+    const SlotDev S = slot_record(c.sl, a.slot);
+    a.k = c.key[i];
+    a.kl = uint32_t(int64_t(S.box_off) + int64_t(a.k) - box0);
+    a.id = c.s.id[i];
+    if (full) {
+        a.x = c.s.x[i];
+        a.y = c.s.y[i];
+        a.z = c.s.z[i];
+        a.rad = c.s.d ? 0.5 * c.s.d[i] : 0.0;  // radius, exact
+        a.adh = c.s.adh ? c.s.adh[i] : 0.0;
+        a.st = c.s.state ? c.s.state[i] : 0;
+    }
+    return a;
+}
+
+// The sorted copy of agent a at sorted position dst.
+__device__ __forceinline__ void sort_write(const SortCtx &c, const BucketAgent &a, uint32_t dst) {
+    c.o.pos4[dst] = make_double4(a.x, a.y, a.z, a.rad);
+    if (!c.periodic) {
+        const GridDev *g = &c.sl.grids[a.slot];
+        const double b = g->b;
+        c.o.pos4f[dst] = make_float4(float(a.x - double(g->cmin[0]) * b), float(a.y - double(g->cmin[1]) * b),
+                                     float(a.z - double(g->cmin[2]) * b), float(a.rad * kPretestRadius));
+    }
+    if (c.s.adh) c.o.adh[dst] = a.adh;
+    c.o.id[dst] = a.id;
+    c.o.key[dst] = a.k;
+    if (c.s.state) c.o.state[dst] = a.st;
+    if (c.o.tile_key && (dst & (kBlock - 1)) == 0) c.o.tile_key[dst / kBlock] = a.k;
+}
+
 __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbuckets, int64_t max_boxes,
                                                         SoaIn s, const uint32_t *__restrict__ key,
                                                         const uint32_t *__restrict__ bstart,
                                                         const uint32_t *__restrict__ item,
                                                         uint32_t *__restrict__ grouped, uint32_t *__restrict__ grouped_i,
                                                         uint32_t *__restrict__ start, SortOut o, int periodic,
-                                                        int64_t capacity) {
+                                                        int64_t capacity, uint32_t *__restrict__ crowd) {
     __shared__ uint32_t s_hist[kBlock / 64][kBucketBoxes];
     __shared__ uint32_t s_ls[kBlock / 64][kBucketBoxes];
     __shared__ uint32_t s_cur[kBlock / 64][kBucketBoxes];
@@ -546,30 +602,8 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbucke
     const int64_t box0 = bk << kBucketShift;
     hist[lane] = 0u;
 
-    // the agent at input index i (kl >= 64 marks an entry to skip: an index or key that cannot
-    // come from a valid build); `full` also loads what the copy needs
-    auto from_index = [&](int64_t i, bool full) {
-        BucketAgent a{};
-        a.kl = 0xFFFFFFFFu;
-        a.slot = -1;
-        a.i = i;
-        if (i < 0 || i >= capacity) return a;
-        a.slot = slot_of_tile(sl, i / kBlock);
-        if (a.slot < 0) return a;
-        const SlotDev S = slot_record(sl, a.slot);
-        a.k = key[i];
-        a.kl = uint32_t(int64_t(S.box_off) + int64_t(a.k) - box0);
-        a.id = s.id[i];
-        if (full) {
-            a.x = s.x[i];
-            a.y = s.y[i];
-            a.z = s.z[i];
-            a.rad = s.d ? 0.5 * s.d[i] : 0.0;  // radius, exact
-            a.adh = s.adh ? s.adh[i] : 0.0;
-            a.st = s.state ? s.state[i] : 0;
-        }
-        return a;
-    };
+    const SortCtx ctx{sl, s, key, o, periodic, capacity};
+    auto from_index = [&](int64_t i, bool full) { return sort_agent(ctx, box0, i, full); };
     // the agent of item slot c
     auto fetch = [&](uint32_t c, bool full) {
         if (c >= m) {
@@ -593,20 +627,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbucke
             __hip_atomic_store(&grouped_i[b0 + p], uint32_t(a.i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     };
-    auto write_out = [&](const BucketAgent &a, uint32_t dst) {
-        o.pos4[dst] = make_double4(a.x, a.y, a.z, a.rad);
-        if (!periodic) {
-            const GridDev *g = &sl.grids[a.slot];
-            const double b = g->b;
-            o.pos4f[dst] = make_float4(float(a.x - double(g->cmin[0]) * b), float(a.y - double(g->cmin[1]) * b),
-                                       float(a.z - double(g->cmin[2]) * b), float(a.rad * kPretestRadius));
-        }
-        if (s.adh) o.adh[dst] = a.adh;
-        o.id[dst] = a.id;
-        o.key[dst] = a.k;
-        if (s.state) o.state[dst] = a.st;
-        if (o.tile_key && (dst & (kBlock - 1)) == 0) o.tile_key[dst / kBlock] = a.k;
-    };
+    auto write_out = [&](const BucketAgent &a, uint32_t dst) { sort_write(ctx, a, dst); };
     auto emit = [&](const BucketAgent &a) {  // rank among the ids of its box, kept in LDS
         if (a.kl >= uint32_t(kBucketBoxes)) return;
         const uint32_t l0 = lst[a.kl], gn = hist[a.kl];
@@ -651,31 +672,58 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbucke
         for (uint32_t c = lane; c < m; c += 64) emit(fetch(c, true));
         return;
     }
-    // a crowded bucket: box by box, 64 members at a time; the box's ids are staged in LDS,
-    // kBucketLds at a time, and each member counts the smaller ones
-    for (int kl = 0; kl < kBucketBoxes; ++kl) {
-        const uint32_t l0 = lst[kl], gn = hist[kl];
+    // a crowded bucket: its boxes are ranked by k_bucket_crowded, many wavefronts per bucket
+    if (lane == 0) crowd[atomicAdd(&sl.grids[0].crowd_n, 1u)] = uint32_t(bk);
+}
+
+// The boxes of crowded buckets (more agents than the sort keeps in LDS), whose ids the bucket
+// sort left grouped by box in `grouped` (agent indices in `grouped_i`): each wavefront takes
+// whole boxes, 64 members at a time; the box's ids are staged in LDS, kBucketLds at a time, and
+// each member counts the smaller ones, which gives its position.  A fixed grid strides over the
+// listed buckets' boxes, so a few crowded buckets still spread over the whole device.
+__global__ __launch_bounds__(kBlock) void k_bucket_crowded(Slots sl, int64_t max_boxes, SoaIn s,
+                                                           const uint32_t *__restrict__ key,
+                                                           const uint32_t *__restrict__ bstart,
+                                                           const uint32_t *__restrict__ grouped,
+                                                           const uint32_t *__restrict__ grouped_i,
+                                                           const uint32_t *__restrict__ start, SortOut o,
+                                                           int periodic, int64_t capacity,
+                                                           const uint32_t *__restrict__ crowd) {
+    __shared__ uint32_t s_grp[kBlock / 64][kBucketLds];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t *grp = s_grp[wave];
+    const uint32_t nc = sl.grids[0].crowd_n;
+    const SortCtx ctx{sl, s, key, o, periodic, capacity};
+    const int64_t nwaves = int64_t(gridDim.x) * (kBlock / 64);
+    for (int64_t w = int64_t(blockIdx.x) * (kBlock / 64) + wave; w < int64_t(nc) * kBucketBoxes; w += nwaves) {
+        const int64_t bk = crowd[w / kBucketBoxes];
+        const int kl = int(w % kBucketBoxes);
+        const int64_t box0 = bk << kBucketShift;
+        if (box0 + kl + 1 > max_boxes) continue;
+        const uint32_t b0 = bstart[bk], s0 = start[box0 + kl], s1 = start[box0 + kl + 1];
+        if (s1 <= s0 || s0 < b0) continue;
+        const uint32_t l0 = s0 - b0, gn = s1 - s0;
         for (uint32_t m0 = 0; m0 < gn; m0 += 64) {
             const uint32_t pm = m0 + uint32_t(lane);
             const bool mine = pm < gn;
-            const uint32_t me =
-                mine ? __hip_atomic_load(&grouped[b0 + l0 + pm], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+            const uint32_t me = mine ? grouped[b0 + l0 + pm] : 0u;
             uint32_t r = 0;
             for (uint32_t w0 = 0; w0 < gn; w0 += uint32_t(kBucketLds)) {
                 const uint32_t wn = gn - w0 < uint32_t(kBucketLds) ? gn - w0 : uint32_t(kBucketLds);
                 __builtin_amdgcn_wave_barrier();
-                for (uint32_t e = uint32_t(lane); e < wn; e += 64)
-                    grp[e] = __hip_atomic_load(&grouped[b0 + l0 + w0 + e], __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+                for (uint32_t e = uint32_t(lane); e < wn; e += 64) grp[e] = grouped[b0 + l0 + w0 + e];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 if (mine)
                     for (uint32_t e = 0; e < wn; ++e) r += grp[e] < me;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
             if (!mine || r >= gn) continue;  // (r >= gn: duplicate ids, not a valid population)
-            const uint32_t i =
-                __hip_atomic_load(&grouped_i[b0 + l0 + pm], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const BucketAgent a = from_index(int64_t(i), true);
-            if (a.kl == uint32_t(kl)) write_out(a, b0 + l0 + r);
+            const BucketAgent a = sort_agent(ctx, box0, int64_t(grouped_i[b0 + l0 + pm]), true);
+            if (a.kl == uint32_t(kl)) sort_write(ctx, a, b0 + l0 + r);
         }
     }
 }
@@ -826,7 +874,9 @@ void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, cons
     const int64_t nwg = (w.lay.nbuckets + kBlock / 64 - 1) / (kBlock / 64);
     hipLaunchKernelGGL(k_bucket_sort, dim3(unsigned(nwg)), dim3(kBlock), 0, st, sl, w.lay.nbuckets,
                        w.lay.max_boxes, in, w.key, w.bstart, w.item, w.tmpid, w.flagid, w.start, o, periodic,
-                       capacity);
+                       capacity, w.crowd);
+    hipLaunchKernelGGL(k_bucket_crowded, dim3(kCrowdedGroups), dim3(kBlock), 0, st, sl, w.lay.max_boxes, in, w.key,
+                       w.bstart, w.tmpid, w.flagid, w.start, o, periodic, capacity, w.crowd);
     if (!sl.table && !sl.one.periodic) {
         const unsigned nto = blocks_for(w.lay.ntiles);
         hipLaunchKernelGGL(k_order_runs, dim3(nto), dim3(kBlock), 0, st, w.grid, tile_key, w.order_first,

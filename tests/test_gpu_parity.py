@@ -102,6 +102,7 @@ def grid_cases():
         "single": dict(x=np.array([3.0]), y=np.array([4.0]), z=np.array([5.0]), d=np.array([10.0]), adh=np.array([0.4])),
         "empty": dict(x=np.zeros(0), y=np.zeros(0), z=np.zeros(0), d=np.zeros(0), adh=np.zeros(0)),
         "reach": inputs.reach_adversarial(192, 12.0, seed=7),
+        "crowded": inputs.uniform_cube(3000, 10.0, dmin=10.0, dmax=10.0, seed=11),
         "onebox": dict(x=np.full(300, 1.0) + np.arange(300) * 1e-3, y=np.ones(300), z=np.ones(300), d=np.full(300, 10.0), adh=np.full(300, 0.4)),
     }
 
@@ -253,7 +254,7 @@ def compare_state(got, ref, L, what, fabs=None, fref=None):
 
 @pytest.mark.parametrize("case,bits", [("c0", 64), ("ragged", 64), ("clustered", 64), ("faces", 64),
                                        ("reach", 64), ("c0", 32), ("clustered", 32), ("reach", 32),
-                                       ("single", 64), ("empty", 64)])
+                                       ("crowded", 64), ("single", 64), ("empty", 64)])
 def test_mech_step_lockstep(case, bits):
     say(f"case: mech lockstep {case} bits={bits}")
     s = grid_cases()[case]
