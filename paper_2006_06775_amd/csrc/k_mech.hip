@@ -373,11 +373,23 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
     // (its registers are free once the differences are taken)
     auto flush = [&]() {
         if (qn > 0) {
-            double4 r = rec.full(s_q[0][t]);
-            for (uint32_t k = 0; k < qn; ++k) {
-                const double dx = p.x - r.x, dy = p.y - r.y, dz = p.z - r.z, rj = r.w;
-                r = rec.full(s_q[k + 1u < qn ? k + 1u : k][t]);
-                exact_pair<F32>(p, dx, dy, dz, rj, rif, S, fx, fy, fz);
+            if constexpr (kSync) {
+                double4 r = rec.full(s_q[0][t]);
+                for (uint32_t k = 0; k < qn; ++k) {
+                    const double dx = p.x - r.x, dy = p.y - r.y, dz = p.z - r.z, rj = r.w;
+                    r = rec.full(s_q[k + 1u < qn ? k + 1u : k][t]);
+                    exact_pair<F32>(p, dx, dy, dz, rj, rif, S, fx, fy, fz);
+                }
+            } else {  // the longer queue's kernel has registers to spare: two records ahead
+                const uint32_t last = qn - 1u;
+                double4 r = rec.full(s_q[0][t]);
+                double4 r1 = rec.full(s_q[min(1u, last)][t]);
+                for (uint32_t k = 0; k < qn; ++k) {
+                    const double dx = p.x - r.x, dy = p.y - r.y, dz = p.z - r.z, rj = r.w;
+                    r = r1;
+                    r1 = rec.full(s_q[min(k + 2u, last)][t]);
+                    exact_pair<F32>(p, dx, dy, dz, rj, rif, S, fx, fy, fz);
+                }
             }
         }
         qn = 0;
@@ -394,7 +406,7 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
         // lane k loads record base + k (one coalesced load for the wavefront, the next chunk in
         // flight while this one is tested), the chunk goes through LDS, and every lane tests
         // each record that lies in its own run, in order.  A lane's candidates thus come in its
-        // canonical order.  The queues are emptied together when one of them is full.
+        // canonical order.  The queues are emptied together when one of them could fill.
         const int lane = t & 63, w0 = t - lane;
 #pragma unroll 1
         for (int r = 0; r < 9; ++r) {
@@ -407,13 +419,24 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
                 s_stage[t] = nxt;
                 if (base + 64u < uhi) nxt = rec.pre(min(base + 64u + uint32_t(lane), uhi - 1u) * U);
                 wave_lds_sync();
+                // four records per step, read from LDS together; the queues are emptied first
+                // when one of them could fill within the step.  [a, b) is the lane's own run
+                // within the chunk (entries past the chunk's end are valid LDS and outside it).
+                // The agent itself may enter its queue: the law adds nothing at zero distance.
                 const uint32_t kn = min(64u, uhi - base);
-                for (uint32_t k = 0; k < kn; ++k) {
-                    const uint32_t j = base + k;
-                    const float4 cand = s_stage[w0 + int(k)];
-                    s_q[qn][t] = j * U;
-                    qn += (j >= own.x && j < own.y && j != q && maybe_touch(pf, cand, slack)) ? 1u : 0u;
-                    if (__any(qn == uint32_t(kQ))) flush();
+                const uint32_t a = own.x > base ? min(own.x - base, kn) : 0u;
+                const uint32_t b = own.y > base ? min(own.y - base, kn) : 0u;
+                for (uint32_t k = 0; k < kn; k += 4u) {
+                    if (__any(qn > uint32_t(kQ - 4))) flush();
+                    float4 cand[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) cand[i] = s_stage[w0 + int(k) + i];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const uint32_t e = k + uint32_t(i);
+                        s_q[qn][t] = (base + e) * U;
+                        qn += ((e >= a) & (e < b) & maybe_touch(pf, cand[i], slack)) ? 1u : 0u;
+                    }
                 }
             }
         }
@@ -559,7 +582,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
 
 // The crowded queue (its LDS allows four wavefronts per SIMD).
 template <int kPrec, class Rec>
-__global__ __launch_bounds__(kBlock) void k_mech_crowded(Slots sl, const uint32_t *__restrict__ order, Rec rec,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_mech_crowded(Slots sl, const uint32_t *__restrict__ order, Rec rec,
                                                          const double *__restrict__ adh_s,
                                                          const uint32_t *__restrict__ id_s,
                                                          const uint8_t *__restrict__ state_s,
