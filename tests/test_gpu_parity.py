@@ -222,15 +222,26 @@ def test_sir_contacts_bit_exact():
 
 # ---------------------------------------------------------------------------------------------
 def pair_abs_sum(s, force_bits=64):
-    """sum_j |F_ij| per agent (oracle pair law) for the force tolerance."""
+    """sum_j |F_ij| per agent over the oracle's contact lists, for the force tolerance.  Only a
+    scale: the magnitudes are evaluated in numpy (binary64, k = 2, gamma = 1), all pairs at once,
+    since a population of a few thousand agents in one box has millions of contacts."""
     counts, offsets, ids = orc.contacts(s["x"], s["y"], s["z"], s["d"], force_bits=force_bits)
-    out = np.zeros(len(s["x"]))
-    for i in range(len(s["x"])):
-        for j in ids[offsets[i]: offsets[i] + counts[i]]:
-            _, f = orc.pair_force((s["x"][i], s["y"][i], s["z"][i]), s["d"][i],
-                                  (s["x"][j], s["y"][j], s["z"][j]), s["d"][j], 2.0, 1.0, force_bits)
-            out[i] += np.linalg.norm(f)
-    return out
+    n = len(s["x"])
+    counts = np.asarray(counts, dtype=np.int64)
+    total = int(counts.sum())
+    if total == 0:
+        return np.zeros(n)
+    owner = np.repeat(np.arange(n), counts)
+    first = np.repeat(np.asarray(offsets, dtype=np.int64), counts)
+    within = np.arange(total) - np.repeat(np.cumsum(counts) - counts, counts)
+    j = np.asarray(ids, dtype=np.int64)[first + within]
+    x, y, z, r = (np.asarray(s[k], dtype=np.float64) for k in ("x", "y", "z", "d"))
+    r = 0.5 * r
+    dist = np.sqrt((x[owner] - x[j]) ** 2 + (y[owner] - y[j]) ** 2 + (z[owner] - z[j]) ** 2)
+    delta = np.maximum(r[owner] + r[j] - dist, 0.0)
+    rhat = r[owner] * r[j] / (r[owner] + r[j])
+    f = np.abs(2.0 * delta - np.sqrt(rhat * delta))
+    return np.bincount(owner, weights=f, minlength=n)
 
 
 def compare_state(got, ref, L, what, fabs=None, fref=None):
@@ -269,6 +280,30 @@ def test_mech_step_lockstep(case, bits):
     fx, fy, fz, nc, fl = orc.mech_step(ref, force_bits=bits)
     fabs = pair_abs_sum(s, bits) if n else np.zeros(0)
     bit = compare_state(got, ref, 200.0, f"mech {case}/{bits}", fabs, (fx, fy, fz))
+    assert bit.all(), "expected bit equality with the oracle (same operations, same order)"
+
+
+@pytest.mark.parametrize("case,bits", [("c0", 64), ("clustered", 64), ("crowded", 64), ("onebox", 64),
+                                       ("crowded8", 64), ("crowded8", 32), ("crowded", 32), ("ragged", 32)])
+def test_crowded_kernel_lockstep(case, bits):
+    """The spheroid model's mechanics kernel (longer queue; wavefronts whose lanes share their
+    boxes walk the union of their runs together) with growth 1 and no division is one plain
+    mechanical step, so it must equal the oracle's bit for bit.  `crowded8`: about 150 agents
+    in each of 8 boxes, so wavefronts straddle boxes and rows end in ragged chunks."""
+    say(f"case: crowded-kernel lockstep {case} bits={bits}")
+    if case == "crowded8":
+        s = inputs.uniform_cube(1237, 20.0, dmin=10.0, dmax=10.0, seed=12)
+    else:
+        s = grid_cases()[case]
+    pop = population(s)
+    p = mech_p(force_bits=bits, grow=1.0, div_d=1e300, half_cbrt=0.5 ** (1 / 3), seed=3)
+    bdm.sim_step(pop.soa, bdm.MODEL_SPHEROID, p, 0, pop.ws)
+    assert bdm.status(pop.ws) == 0
+    assert pop.n == len(s["x"])
+    got = pop.read()
+    ref = {k: v.copy() for k, v in s.items()}
+    fx, fy, fz, nc, fl = orc.mech_step(ref, force_bits=bits)
+    bit = compare_state(got, ref, 200.0, f"crowded kernel {case}/{bits}", pair_abs_sum(s, bits), (fx, fy, fz))
     assert bit.all(), "expected bit equality with the oracle (same operations, same order)"
 
 
