@@ -123,7 +123,7 @@ def serving(args):
 
     from paper_2006_06775_amd import serve, tune
     plan = tune.plan()  # box edge per request size, measured on this device
-    per_agent = 68 + 85 + 4
+    per_agent = 68 + 93 + 4
     cap = int(args.serve_budget_gib * (1 << 30) / (per_agent + (4 + 12 / 64) * 1.6))
     boxes = int(cap * 1.6)
     slots = 64

@@ -149,7 +149,7 @@ int plain_grid(const bdm_soa *s, const bdm_params *p, bool periodic, const bdm::
         int rc = periodic_boxes(p, w.lay.max_boxes, &rec.nb);
         if (rc) return rc;
     }
-    bdm::launch_grid_build(*s, plain_slots(w, rec), s->capacity, w, st);
+    bdm::launch_grid_build(*s, plain_slots(w, rec), s->capacity, false, w, st);
     if (rec_out) *rec_out = rec;
     return hip_check("grid_build launch");
 }
@@ -278,7 +278,7 @@ int bdm_sim_step(const bdm_soa *soa, int32_t model, const bdm_params *params, in
             rc = hip_check("grow_divide launch");
             if (rc) return rc;
         }
-        bdm::launch_grid_build(*soa, plain_slots(w, rec), soa->capacity, w, st);
+        bdm::launch_grid_build(*soa, plain_slots(w, rec), soa->capacity, model == BDM_MODEL_SPHEROID, w, st);
         rc = hip_check("grid_build launch");
         if (rc) return rc;
         bdm::launch_mech(*soa, plain_slots(w, rec), soa->capacity, params->force_bits, model == BDM_MODEL_SPHEROID, w,
@@ -501,7 +501,7 @@ int bdm_batch_step(const bdm_soa *packed, const bdm_batch *b, void *stream) {
     sl.bucketmap = w.bucketmap;
     sl.grids = w.grid;
     sl.nslots = b->slots;
-    bdm::launch_grid_build(*packed, sl, b->capacity, w, st);
+    bdm::launch_grid_build(*packed, sl, b->capacity, false, w, st);
     bdm::launch_mech(*packed, sl, b->capacity, 0, false, w, st);
     bdm::launch_batch_advance(w, st);
     return hip_check("batch_step launch");

@@ -24,7 +24,27 @@ constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kBucketShift = 6;       // 64 consecutive boxes per bucket of the two-level sort
 constexpr int kBucketBoxes = 1 << kBucketShift;
 constexpr int kOrderBins = 8192;      // largest (y-pencil x z-plane) count of the tile order
+
 constexpr double kPretestRadius = 1.0006;  // radius scale of the binary32 pre-test copy of a record
+
+// The 8-byte pre-test record of a sphere in an open lattice of box edge b, in units of
+// b / 2^14.  Per axis 16 bits: the sphere's box index c (the key's) mod 4 (2 bits) above its
+// offset within the box, q = floor((v / b - c) * 2^14) clamped to [0, 2^14 - 1] (14 bits; v / b
+// is formed as v times the rounded 1/b, which is within 2^-14 units of it for any lattice that
+// fits the keys).  Two spheres whose boxes differ by at most one along the axis then differ in
+// these 16 bits, modulo 2^16 and read as a signed 16-bit value, by exactly
+// (c_j - c_i) * 2^14 + q_j - q_i: their offset in units to within 1 + 2^-13.  The radius is
+// rounded up and one unit added (at most 2^13 + 2 for r <= b / 2).
+__device__ __forceinline__ uint32_t pre8_axis(double v, double inv_b, int c) {
+    const double u = (v * inv_b - double(c)) * 16384.0;
+    uint32_t q = u > 0.0 ? uint32_t(u) : 0u;
+    q = q > 16383u ? 16383u : q;
+    return (uint32_t(c) & 3u) << 14 | q;
+}
+__device__ __forceinline__ uint32_t pre8_radius(double r, double inv_b) {
+    const double u = ceil(r * inv_b * 16384.0) + 1.0;
+    return u < 65535.0 ? uint32_t(u) : 65535u;
+}
 constexpr uint32_t kScanSpinLimit = 1u << 22;  // polls before a look-back gives up
 
 // Philox draw purposes: counter word 0 = purpose + (attempt << 8).
@@ -45,6 +65,7 @@ struct GridDev {
     unsigned long long div_ny;
     unsigned long long sir_counts[3];
     int64_t sorted_base;            // first sorted position of this slot (start[box_off])
+    double inv_b;                   // 1 / b, rounded (the pre-test records' scale)
 };
 static_assert(sizeof(GridDev) <= 256, "grid record must fit its slot");
 
@@ -68,8 +89,8 @@ struct SlotDev {
 // Byte offsets of every workspace region (256-byte aligned).  `slots` = 0 is a plain
 // workspace (one grid record, slot passed by value); > 0 is a batch of that many slots.
 struct WsLayout {
-    size_t grid, slots, tilemap, bucketmap, partials, count, bstart, start, tiles, key, rank, item, tmpid, pos4, pos4f, adh,
-        ids, state, flagid, rankid, order_bins, crowd;
+    size_t grid, slots, tilemap, bucketmap, partials, count, bstart, start, tiles, key, rank, item, tmpid, pos4, pos4f, pos8,
+        adh, ids, state, flagid, rankid, order_bins, crowd;
     size_t total;
     int64_t capacity, max_boxes, max_tiles, nslots, ntiles, nbuckets;
 };
@@ -107,6 +128,7 @@ inline bool ws_layout(int64_t capacity, int64_t max_boxes, int64_t slots, WsLayo
     L->tmpid = take(4 * cap);
     L->pos4 = take(32 * cap);
     L->pos4f = take(16 * cap);
+    L->pos8 = take(8 * cap);
     L->adh = take(8 * cap);
     L->ids = take(4 * cap);
     L->state = take(cap);
@@ -137,7 +159,8 @@ struct Ws {
     unsigned long long *tiles;
     uint32_t *key, *rank, *item, *tmpid;
     double4 *pos4;
-    float4 *pos4f;       // binary32 filter copy of pos4 (mechanics slots)
+    float4 *pos4f;       // binary32 filter copy of pos4 (crowded mechanics: spheroid steps)
+    uint2 *pos8;         // 8-byte fixed-point filter record (mechanics slots)
     double *adh;
     uint32_t *ids;
     uint8_t *state;
@@ -165,6 +188,7 @@ inline Ws ws_view(void *base, const WsLayout &L) {
     w.tmpid = reinterpret_cast<uint32_t *>(p + L.tmpid);
     w.pos4 = reinterpret_cast<double4 *>(p + L.pos4);
     w.pos4f = reinterpret_cast<float4 *>(p + L.pos4f);
+    w.pos8 = reinterpret_cast<uint2 *>(p + L.pos8);
     w.adh = reinterpret_cast<double *>(p + L.adh);
     w.ids = reinterpret_cast<uint32_t *>(p + L.ids);
     w.state = reinterpret_cast<uint8_t *>(p + L.state);
@@ -271,6 +295,15 @@ __host__ __device__ __forceinline__ unsigned long long fastdiv_magic(uint32_t d)
 }
 __device__ __forceinline__ uint32_t fastdiv(uint32_t a, unsigned long long m) {
     return m ? uint32_t(__umul64hi(m, a)) : a;
+}
+
+// Box coordinates of a key (x fastest) by fast division.
+__device__ __forceinline__ void key_coords(const GridDev *__restrict__ g, uint32_t key, int &cx, int &cy, int &cz) {
+    const uint32_t row = fastdiv(key, g->div_nx);
+    cx = int(key - row * uint32_t(g->dims[0]));
+    const uint32_t z = fastdiv(row, g->div_ny);
+    cy = int(row - z * uint32_t(g->dims[1]));
+    cz = int(z);
 }
 
 // Wavefront-wide inclusive prefix sum (64 lanes).

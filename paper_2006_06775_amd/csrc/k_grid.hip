@@ -223,6 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Slots sl, const int64_t *n_
         return;
     }
     g->nboxes = int64_t(g->dims[0]) * g->dims[1] * g->dims[2];
+    g->inv_b = 1.0 / g->b;
     g->div_nx = fastdiv_magic(uint32_t(g->dims[0]));
     g->div_ny = fastdiv_magic(uint32_t(g->dims[1]));
     g->valid = 1;
@@ -489,7 +490,8 @@ __global__ __launch_bounds__(kBlock) void k_bucket_scatter(Slots sl, int64_t nti
 // A bucket holds any number of agents (the wavefront walks them 64 at a time).
 struct SortOut {
     double4 *pos4;
-    float4 *pos4f;
+    float4 *pos4f;  // binary32 copy for the crowded mechanics kernel (null: not written)
+    uint2 *pos8;
     double *adh;
     uint32_t *id;
     uint8_t *state;
@@ -527,6 +529,27 @@ __device__ __forceinline__ void run_small(int lane, Fetch &fetch, Count &count, 
 }
 
 // What the bucket sort reads and writes, for the helpers below.
+// The lattice of the grid a wavefront's agents belong to (one slot per bucket), read once per
+// wavefront for the pre-test records.
+struct PreGrid {
+    double b, inv_b;
+    int32_t cmin[3];
+    uint32_t nx, ny;
+    unsigned long long div_nx, div_ny;
+};
+
+__device__ __forceinline__ PreGrid pre_grid(const GridDev *g) {
+    PreGrid p;
+    p.b = g->b;
+    p.inv_b = g->inv_b;
+    for (int a = 0; a < 3; ++a) p.cmin[a] = g->cmin[a];
+    p.nx = uint32_t(g->dims[0]);
+    p.ny = uint32_t(g->dims[1]);
+    p.div_nx = g->div_nx;
+    p.div_ny = g->div_ny;
+    return p;
+}
+
 struct SortCtx {
     Slots sl;
     SoaIn s;
@@ -534,6 +557,7 @@ struct SortCtx {
     SortOut o;
     int periodic;
     int64_t capacity;
+    PreGrid pg;  // the bucket's grid (open lattices only)
 };
 
 // The agent at input index i, for a bucket whose first box is box0 (kl >= 64 marks an entry to
@@ -566,10 +590,15 @@ __device__ __forceinline__ BucketAgent sort_agent(const SortCtx &c, int64_t box0
 __device__ __forceinline__ void sort_write(const SortCtx &c, const BucketAgent &a, uint32_t dst) {
     c.o.pos4[dst] = make_double4(a.x, a.y, a.z, a.rad);
     if (!c.periodic) {
-        const GridDev *g = &c.sl.grids[a.slot];
-        const double b = g->b;
-        c.o.pos4f[dst] = make_float4(float(a.x - double(g->cmin[0]) * b), float(a.y - double(g->cmin[1]) * b),
-                                     float(a.z - double(g->cmin[2]) * b), float(a.rad * kPretestRadius));
+        const PreGrid &g = c.pg;
+        const uint32_t row = fastdiv(a.k, g.div_nx), zc = fastdiv(row, g.div_ny);
+        const int cx = int(a.k - row * g.nx), cy = int(row - zc * g.ny), cz = int(zc);
+        c.o.pos8[dst] = make_uint2(
+            pre8_axis(a.x, g.inv_b, g.cmin[0] + cx) | pre8_axis(a.y, g.inv_b, g.cmin[1] + cy) << 16,
+            pre8_axis(a.z, g.inv_b, g.cmin[2] + cz) | pre8_radius(a.rad, g.inv_b) << 16);
+        if (c.o.pos4f)
+            c.o.pos4f[dst] = make_float4(float(a.x - double(g.cmin[0]) * g.b), float(a.y - double(g.cmin[1]) * g.b),
+                                         float(a.z - double(g.cmin[2]) * g.b), float(a.rad * kPretestRadius));
     }
     if (c.s.adh) c.o.adh[dst] = a.adh;
     c.o.id[dst] = a.id;
@@ -602,7 +631,8 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbucke
     const int64_t box0 = bk << kBucketShift;
     hist[lane] = 0u;
 
-    const SortCtx ctx{sl, s, key, o, periodic, capacity};
+    const SortCtx ctx{sl, s, key, o, periodic, capacity,
+                      pre_grid(&sl.grids[sl.bucketmap ? sl.bucketmap[bk] : 0])};
     auto from_index = [&](int64_t i, bool full) { return sort_agent(ctx, box0, i, full); };
     // the agent of item slot c
     auto fetch = [&](uint32_t c, bool full) {
@@ -693,7 +723,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_crowded(Slots sl, int64_t max
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t *grp = s_grp[wave];
     const uint32_t nc = sl.grids[0].crowd_n;
-    const SortCtx ctx{sl, s, key, o, periodic, capacity};
+    SortCtx ctx{sl, s, key, o, periodic, capacity, {}};
     const int64_t nwaves = int64_t(gridDim.x) * (kBlock / 64);
     for (int64_t w = int64_t(blockIdx.x) * (kBlock / 64) + wave; w < int64_t(nc) * kBucketBoxes; w += nwaves) {
         const int64_t bk = crowd[w / kBucketBoxes];
@@ -703,6 +733,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_crowded(Slots sl, int64_t max
         const uint32_t b0 = bstart[bk], s0 = start[box0 + kl], s1 = start[box0 + kl + 1];
         if (s1 <= s0 || s0 < b0) continue;
         const uint32_t l0 = s0 - b0, gn = s1 - s0;
+        ctx.pg = pre_grid(&sl.grids[sl.bucketmap ? sl.bucketmap[bk] : 0]);
         for (uint32_t m0 = 0; m0 < gn; m0 += 64) {
             const uint32_t pm = m0 + uint32_t(lane);
             const bool mine = pm < gn;
@@ -848,7 +879,8 @@ unsigned tile_grid(const Slots &sl, int64_t ntiles) {
     return unsigned(sl.table && ntiles > cap ? cap : ntiles);
 }
 
-void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, const Ws &w, hipStream_t st) {
+void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, bool f32_copy, const Ws &w,
+                       hipStream_t st) {
     const bool has_d = sl.table ? true : sl.one.has_d != 0;
     const double *d = has_d ? s.diam : nullptr;
     const int64_t nbt = (capacity + kBoundsTile - 1) / kBoundsTile;
@@ -870,7 +902,7 @@ void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, cons
     uint32_t *tile_key = sl.table ? nullptr : w.rankid;
     const int periodic = sl.table ? 0 : sl.one.periodic;
     SoaIn in{s.x, s.y, s.z, d, s.adh, s.id, s.state};
-    SortOut o{w.pos4, w.pos4f, w.adh, w.ids, w.state, w.rank, tile_key};
+    SortOut o{w.pos4, f32_copy ? w.pos4f : nullptr, w.pos8, w.adh, w.ids, w.state, w.rank, tile_key};
     const int64_t nwg = (w.lay.nbuckets + kBlock / 64 - 1) / (kBlock / 64);
     hipLaunchKernelGGL(k_bucket_sort, dim3(unsigned(nwg)), dim3(kBlock), 0, st, sl, w.lay.nbuckets,
                        w.lay.max_boxes, in, w.key, w.bstart, w.item, w.tmpid, w.flagid, w.start, o, periodic,

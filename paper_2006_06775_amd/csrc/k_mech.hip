@@ -191,13 +191,59 @@ __device__ __forceinline__ uint32_t load_runs(const GridDev *__restrict__ g, con
     return cnt;
 }
 
-// Packed-record loads by candidate offset u in units of kUnit.  RecBuf: a raw buffer resource
-// with 32-bit byte offsets (u is the byte offset of the binary32 copy, twice that of the
-// binary64 record) when the sorted arrays are below 4 GiB; out-of-range offsets read zero.
-// RecGlobal: plain indices.  full() reads the binary64 record (x, y, z, r), pre() its binary32
-// pre-test copy.
+// Conservative contact pre-test in binary32 (every real contact passes; see pretest_slack).
+__device__ __forceinline__ bool maybe_touch(const float4 &a, const float4 &c, float slack) {
+    const float dx = a.x - c.x, dy = a.y - c.y, dz = a.z - c.z;
+    const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+    const float s = a.w + c.w;  // scaled radii
+    return d2 < __builtin_fmaf(s, s, slack);
+}
+
+// Conservative contact pre-test on the 8-byte records (units of b / 2^14, see pre8_axis).  Each
+// coordinate difference is within one unit of the true one and each stored radius at least one
+// unit above the true one, so a pair the exact law counts as a contact has a rounded distance
+// below r_i + r_j + sqrt(3) < R_i + R_j; binary32 holds the integer differences exactly, and
+// the one unit of slack covers the rounding of the squares and of either law's contact test.
+__device__ __forceinline__ bool touch8(const uint2 &a, const uint2 &c) {
+    const int dx = int(int16_t(uint16_t(c.x - a.x)));
+    const int dy = int(c.x - (a.x & 0xFFFF0000u)) >> 16;
+    const int dz = int(int16_t(uint16_t(c.y - a.y)));
+    const float fx = float(dx), fy = float(dy), fz = float(dz);
+    const float d2 = __builtin_fmaf(fz, fz, __builtin_fmaf(fy, fy, fx * fx));
+    const float sr = float((a.y >> 16) + (c.y >> 16) + 1u);
+    return d2 < sr * sr;
+}
+
+// Packed-record loads by candidate offset u in units of kUnit.  RecBuf: raw buffer resources
+// with 32-bit byte offsets when the sorted arrays are below 4 GiB (u is 16 times the sorted
+// position: the binary64 record sits at byte 2u, the 8-byte record at u / 2); out-of-range
+// offsets read zero.  RecGlobal: plain indices.  full() reads the binary64 record (x, y, z, r),
+// pre() the 8-byte pre-test record.
 struct RecBuf {
     static constexpr uint32_t kUnit = 16;
+    static constexpr bool kF32Copy = false;
+    using Pre = uint2;
+    void *base, *base8;
+    uint32_t bytes;  // of the binary64 records (the 8-byte records are a quarter of it)
+    __device__ __forceinline__ double4 full(uint32_t u) const {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, 0, bytes, 0x00020000);
+        const uint32_t off = u * 2u;
+        const auto lo = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        const auto hi = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16u, 0, 0);
+        const double2 a = __builtin_bit_cast(double2, lo), c = __builtin_bit_cast(double2, hi);
+        return make_double4(a.x, a.y, c.x, c.y);
+    }
+    __device__ __forceinline__ uint2 pre(uint32_t u) const {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base8, 0, bytes / 4u, 0x00020000);
+        return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, u / 2u, 0, 0));
+    }
+    static __device__ __forceinline__ bool touch(const uint2 &a, const uint2 &c, float) { return touch8(a, c); }
+};
+// The binary32 copies instead (the crowded kernel: its walk is bound by VALU, not by memory).
+struct RecBuf4 {
+    static constexpr uint32_t kUnit = 16;
+    static constexpr bool kF32Copy = true;
+    using Pre = float4;
     void *base, *basef;
     uint32_t bytes;  // of the binary64 records (the binary32 copy is half as long)
     __device__ __forceinline__ double4 full(uint32_t u) const {
@@ -212,14 +258,33 @@ struct RecBuf {
         const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(basef, 0, bytes / 2u, 0x00020000);
         return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, u, 0, 0));
     }
+    static __device__ __forceinline__ bool touch(const float4 &a, const float4 &c, float slack) {
+        return maybe_touch(a, c, slack);
+    }
 };
 struct RecGlobal {
     static constexpr uint32_t kUnit = 1;
+    static constexpr bool kF32Copy = false;
+    using Pre = uint2;
+    const double4 *__restrict__ p;
+    const uint2 *__restrict__ p8;
+    __device__ __forceinline__ double4 full(uint32_t u) const { return p[u]; }
+    __device__ __forceinline__ uint2 pre(uint32_t u) const { return p8[u]; }
+    static __device__ __forceinline__ bool touch(const uint2 &a, const uint2 &c, float) { return touch8(a, c); }
+};
+struct RecGlobal4 {
+    static constexpr uint32_t kUnit = 1;
+    static constexpr bool kF32Copy = true;
+    using Pre = float4;
     const double4 *__restrict__ p;
     const float4 *__restrict__ pf;
     __device__ __forceinline__ double4 full(uint32_t u) const { return p[u]; }
     __device__ __forceinline__ float4 pre(uint32_t u) const { return pf[u]; }
+    static __device__ __forceinline__ bool touch(const float4 &a, const float4 &c, float slack) {
+        return maybe_touch(a, c, slack);
+    }
 };
+
 
 // Absolute slack of the binary32 pre-test of a slot.  Stored coordinates are relative to the
 // lattice origin o and lie within M = (largest dims + 1) * b of it (plus the rounding of x / b
@@ -241,23 +306,6 @@ __device__ __forceinline__ float pretest_slack(const GridDev *__restrict__ g) {
     const double M = (double(dm) + 1.0) * b + 0x1p-48 * omax;
     const double e = 0x1p-22 * (M + b);
     return float(4.0 * (b + e) * e) * 1.001f;
-}
-
-// Conservative contact pre-test in binary32 (every real contact passes; see pretest_slack).
-__device__ __forceinline__ bool maybe_touch(const float4 &a, const float4 &c, float slack) {
-    const float dx = a.x - c.x, dy = a.y - c.y, dz = a.z - c.z;
-    const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-    const float s = a.w + c.w;  // scaled radii
-    return d2 < __builtin_fmaf(s, s, slack);
-}
-
-// Box coordinates of a key (x fastest) by fast division.
-__device__ __forceinline__ void key_coords(const GridDev *__restrict__ g, uint32_t key, int &cx, int &cy, int &cz) {
-    const uint32_t row = fastdiv(key, g->div_nx);
-    cx = int(key - row * uint32_t(g->dims[0]));
-    const uint32_t z = fastdiv(row, g->div_ny);
-    cy = int(row - z * uint32_t(g->dims[1]));
-    cz = int(z);
 }
 
 // Walk over a lane's packed runs (column col of s_run): next() returns the offset of the next
@@ -358,13 +406,13 @@ template <bool F32, int kQ, class Rec, class Pre>
 __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const double4 &p,
                                             const Rec &rec, float slack, uint2 (*s_run)[kBlock], uint32_t cnt,
                                             uint32_t (*s_q)[kBlock], int t, const Pre &pre_final,
-                                            const RowUnion &un, float4 *s_stage, double &fx, double &fy,
+                                            const RowUnion &un, typename Rec::Pre *s_stage, double &fx, double &fy,
                                             double &fz) {
     constexpr uint32_t U = Rec::kUnit;
     constexpr bool kSync = kQ == kQueue;
     const uint32_t qu = q * U;
     const float rif = float(p.w);
-    const float4 pf = rec.pre(qu);
+    const typename Rec::Pre pf = rec.pre(qu);
     fx = 0.0;
     fy = 0.0;
     fz = 0.0;
@@ -394,9 +442,9 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
         }
         qn = 0;
     };
-    auto push = [&](uint32_t u, const float4 &c) {
+    auto push = [&](uint32_t u, const typename Rec::Pre &c) {
         s_q[qn][t] = u;
-        qn += (maybe_touch(pf, c, slack) && u != qu) ? 1u : 0u;
+        qn += (Rec::touch(pf, c, slack) && u != qu) ? 1u : 0u;
         if constexpr (!kSync) {
             if (qn == uint32_t(kQ)) flush();
         }
@@ -413,7 +461,7 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
             const uint32_t ulo = un.lo[r], uhi = un.hi[r];
             if (ulo >= uhi) continue;
             const uint2 own = s_run[r][t];
-            float4 nxt = rec.pre(min(ulo + uint32_t(lane), uhi - 1u) * U);
+            typename Rec::Pre nxt = rec.pre(min(ulo + uint32_t(lane), uhi - 1u) * U);
             for (uint32_t base = ulo; base < uhi; base += 64u) {
                 wave_lds_sync();
                 s_stage[t] = nxt;
@@ -428,14 +476,14 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
                 const uint32_t b = own.y > base ? min(own.y - base, kn) : 0u;
                 for (uint32_t k = 0; k < kn; k += 4u) {
                     if (__any(qn > uint32_t(kQ - 4))) flush();
-                    float4 cand[4];
+                    typename Rec::Pre cand[4];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) cand[i] = s_stage[w0 + int(k) + i];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const uint32_t e = k + uint32_t(i);
                         s_q[qn][t] = (base + e) * U;
-                        qn += ((e >= a) & (e < b) & maybe_touch(pf, cand[i], slack)) ? 1u : 0u;
+                        qn += ((e >= a) & (e < b) & Rec::touch(pf, cand[i], slack)) ? 1u : 0u;
                     }
                 }
             }
@@ -447,9 +495,9 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
     const uint2 r0 = s_run[0][t];
     Walker w{r0.x, r0.y, 1u, s_run[1][t]};
     uint32_t ua = w.next<U>(s_run, t);
-    float4 ca = rec.pre(ua);
+    typename Rec::Pre ca = rec.pre(ua);
     uint32_t ub = w.next<U>(s_run, t);
-    float4 cb = rec.pre(ub);
+    typename Rec::Pre cb = rec.pre(ub);
     uint32_t c = 0;
     const uint32_t pairs_end = cnt ? cnt - 1u : 0u;  // a pair starts at c while c < cnt - 1
     for (;;) {
@@ -485,7 +533,7 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
                                           const double *__restrict__ adh_s, const uint32_t *__restrict__ id_s,
                                           const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
                                           const uint32_t *__restrict__ start_all, const bdm_soa &out,
-                                          uint2 (*s_run)[kBlock], uint32_t (*s_q)[kBlock], float4 *s_stage) {
+                                          uint2 (*s_run)[kBlock], uint32_t (*s_q)[kBlock], typename Rec::Pre *s_stage) {
     const int t = threadIdx.x;
     const int slot = slot_of_tile(sl, tile);
     if (slot < 0) return;
@@ -558,7 +606,7 @@ __device__ __forceinline__ void mech_plain(const Slots &sl, const uint32_t *__re
                                            const uint32_t *__restrict__ start, const bdm_soa &out) {
     __shared__ uint2 s_run[9][kBlock];
     __shared__ uint32_t s_q[kQ][kBlock];
-    __shared__ float4 s_stage[kQ == kQueueCrowded ? kBlock : 1];  // records of a cooperative walk
+    __shared__ typename Rec::Pre s_stage[kQ == kQueueCrowded ? kBlock : 1];  // records of a cooperative walk
     GridDev *g0 = &sl.grids[0];
     if (!g0->valid) {  // no grid of these agents (never built, or its build failed): report it
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&g0->flags, BDM_FLAG_NOGRID);
@@ -649,20 +697,19 @@ __global__ __launch_bounds__(kBlock) void k_contacts_mech(Slots sl, const double
 
 template <class Rec>
 static void launch_mech_rec(const bdm_soa &s, const Slots &sl, int64_t ntiles, unsigned nb, int precision,
-                            bool crowded, const uint32_t *order, const Rec &rec, const Ws &w, hipStream_t st) {
+                            const uint32_t *order, const Rec &rec, const Ws &w, hipStream_t st) {
 #define BDM_MECH(K, P)                                                                                     \
     hipLaunchKernelGGL((K<P, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, order, rec, w.adh, w.ids, w.state, w.rank, \
                        w.start, s)
-    if (precision == 32) {
-        if (crowded)
+    if constexpr (Rec::kF32Copy) {  // the crowded kernel
+        if (precision == 32)
             BDM_MECH(k_mech_crowded, 32);
         else
-            BDM_MECH(k_mech, 32);
-    } else if (precision == 64) {
-        if (crowded)
             BDM_MECH(k_mech_crowded, 64);
-        else
-            BDM_MECH(k_mech, 64);
+    } else if (precision == 32) {
+        BDM_MECH(k_mech, 32);
+    } else if (precision == 64) {
+        BDM_MECH(k_mech, 64);
     } else {
         hipLaunchKernelGGL((k_mech_batch<Rec>), dim3(nb), dim3(kBlock), 0, st, sl, ntiles, rec, w.adh, w.ids,
                            w.state, w.rank, w.start, s);
@@ -679,10 +726,16 @@ void launch_mech(const bdm_soa &s, const Slots &sl, int64_t capacity, int precis
     const uint32_t *order = sl.table ? nullptr : w.flagid;  // plain: order built with the grid
     const uint64_t bytes = uint64_t(w.lay.capacity) * 32u;
     if (bytes <= 0xFFFFFFE0ull) {
-        RecBuf rec{static_cast<void *>(w.pos4), static_cast<void *>(w.pos4f), uint32_t(bytes)};
-        launch_mech_rec(s, sl, ntiles, nb, precision, crowded, order, rec, w, st);
+        if (crowded)
+            launch_mech_rec(s, sl, ntiles, nb, precision, order,
+                            RecBuf4{static_cast<void *>(w.pos4), static_cast<void *>(w.pos4f), uint32_t(bytes)}, w, st);
+        else
+            launch_mech_rec(s, sl, ntiles, nb, precision, order,
+                            RecBuf{static_cast<void *>(w.pos4), static_cast<void *>(w.pos8), uint32_t(bytes)}, w, st);
+    } else if (crowded) {
+        launch_mech_rec(s, sl, ntiles, nb, precision, order, RecGlobal4{w.pos4, w.pos4f}, w, st);
     } else {
-        launch_mech_rec(s, sl, ntiles, nb, precision, crowded, order, RecGlobal{w.pos4, w.pos4f}, w, st);
+        launch_mech_rec(s, sl, ntiles, nb, precision, order, RecGlobal{w.pos4, w.pos8}, w, st);
     }
 }
 

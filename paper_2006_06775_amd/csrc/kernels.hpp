@@ -47,7 +47,9 @@ struct ContactArgs {
 // Workgroups of a per-tile launch (one per tile for a plain call, capped for a batch).
 unsigned tile_grid(const Slots &sl, int64_t ntiles);
 // Grid build (bounds, finalize, key/histogram, scan, scatter, canonical order) of every slot.
-void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, const Ws &w, hipStream_t st);
+// f32_copy: also write the binary32 pre-test copies (read by the crowded mechanics kernel).
+void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, bool f32_copy, const Ws &w,
+                       hipStream_t st);
 // Exclusive scan of in[0, len) into out[0, len] (len read on the device).
 void launch_scan(uint32_t *in, uint32_t *out, const int64_t *len_ptr, int64_t max_len, const Ws &w,
                  int zero_in, bool prepare, hipStream_t st);

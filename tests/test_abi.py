@@ -44,9 +44,10 @@ def test_workspace_bytes_host_only():
     a = bdm.workspace_bytes(4096, 3000)
     b = bdm.workspace_bytes(8192, 3000)
     assert 0 < a < b and a % 256 == 0
-    # per agent: packed double4 record 32 B and its binary32 copy 16, adherence 8, id 4, key 4,
-    # rank 4, bucket item 4, scratch id 4, state 1, division flag and rank 4 + 4 = 85 B
-    assert b - a == 4096 * 85 + 4 * 64  # plus one 64-byte bounds partial per 1024 agents
+    # per agent: packed double4 record 32 B, its binary32 copy 16 and 8-byte pre-test record,
+    # adherence 8, id 4, key 4, rank 4, bucket item 4, scratch id 4, state 1, division flag and
+    # rank 4 + 4 = 93 B
+    assert b - a == 4096 * 93 + 4 * 64  # plus one 64-byte bounds partial per 1024 agents
     # per box: start 4 B, plus bucket count, bucket start and crowded-bucket entry 4 + 4 + 4 per
     # 64 boxes
     c = bdm.workspace_bytes(4096, 3000 + 64 * 1000)
