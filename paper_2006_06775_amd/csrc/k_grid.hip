@@ -11,8 +11,10 @@
 //   canon      each agent counts the smaller ids in its box (ascending-id order inside a box)
 //              and copies itself into the sorted copy: (x, y, z, r = d/2) packed as double4
 //              (halving and doubling a binary64 are exact, so d = 2r is recovered bit for bit)
-//              plus its box key, and for mechanics a binary32 copy (x - o, y - o, z - o, r)
-//              relative to the lattice origin o that only the conservative contact pre-test reads
+//              plus its box key, and for mechanics the records that only the conservative
+//              contact pre-test reads: an 8-byte fixed-point record (offsets within the box) and,
+//              for spheroid steps, a binary32 copy (x - o, y - o, z - o, r) relative to the
+//              lattice origin o
 //   order      one workgroup: the processing order of the mechanics tiles (pencils of rows
 //              swept along z, so that the three z-planes a tile reads stay in one XCD's L2)
 #include "kernels.hpp"
@@ -485,8 +487,8 @@ __global__ __launch_bounds__(kBlock) void k_bucket_scatter(Slots sl, int64_t nti
 //      LDS up to kBucketLds agents, else in the scratch id array);
 //   4. each agent counts the smaller ids of its box, which gives its final position, and copies
 //      (x, y, z, r = d/2) packed as a double4 (halving and doubling a binary64 are exact, so d =
-//      2r is recovered bit for bit), its binary32 copy relative to the lattice origin (for the
-//      mechanics pre-test), adh, id, state and its box key there.
+//      2r is recovered bit for bit), its pre-test records (the 8-byte one; the binary32 copy
+//      relative to the lattice origin when asked for), adh, id, state and its box key there.
 // A bucket holds any number of agents (the wavefront walks them 64 at a time).
 struct SortOut {
     double4 *pos4;
