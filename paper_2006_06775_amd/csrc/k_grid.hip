@@ -620,7 +620,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbucke
     __shared__ uint32_t s_ls[kBlock / 64][kBucketBoxes];
     __shared__ uint32_t s_cur[kBlock / 64][kBucketBoxes];
     __shared__ uint32_t s_grp[kBlock / 64][kBucketLds];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (uniform)
     const int64_t bk = int64_t(xcd_tile(blockIdx.x, gridDim.x)) * (kBlock / 64) + wave;
     if (bk >= nbuckets) return;  // (the whole wavefront; no workgroup barrier below)
     if (sl.bucketmap && sl.bucketmap[bk] < 0) return;  // a batch bucket no simulation owns
@@ -722,7 +722,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_crowded(Slots sl, int64_t max
                                                            int periodic, int64_t capacity,
                                                            const uint32_t *__restrict__ crowd) {
     __shared__ uint32_t s_grp[kBlock / 64][kBucketLds];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (uniform)
     uint32_t *grp = s_grp[wave];
     const uint32_t nc = sl.grids[0].crowd_n;
     SortCtx ctx{sl, s, key, o, periodic, capacity, {}};
