@@ -30,10 +30,10 @@ constexpr double kPretestRadius = 1.0006;  // radius scale of the binary32 pre-t
 // The 8-byte pre-test record of a sphere in an open lattice of box edge b, in units of
 // b / 2^14.  Per axis 16 bits: the sphere's box index c (the key's) mod 4 (2 bits) above its
 // offset within the box, q = floor((v / b - c) * 2^14) clamped to [0, 2^14 - 1] (14 bits; v / b
-// is formed as v times the rounded 1/b, which is within 2^-14 units of it for any lattice that
-// fits the keys).  Two spheres whose boxes differ by at most one along the axis then differ in
-// these 16 bits, modulo 2^16 and read as a signed 16-bit value, by exactly
-// (c_j - c_i) * 2^14 + q_j - q_i: their offset in units to within 1 + 2^-13.  The radius is
+// is formed as v times the rounded 1/b, which for |v / b| < 2^31, the lattice's int32 range,
+// is within 2^-7 units of it).  Two spheres whose boxes differ by at most one along the axis
+// then differ in these 16 bits, modulo 2^16 and read as a signed 16-bit value, by exactly
+// (c_j - c_i) * 2^14 + q_j - q_i: their offset in units to within 1 + 2^-6.  The radius is
 // rounded up and one unit added (at most 2^13 + 2 for r <= b / 2).
 __device__ __forceinline__ uint32_t pre8_axis(double v, double inv_b, int c) {
     const double u = (v * inv_b - double(c)) * 16384.0;

@@ -200,10 +200,11 @@ __device__ __forceinline__ bool maybe_touch(const float4 &a, const float4 &c, fl
 }
 
 // Conservative contact pre-test on the 8-byte records (units of b / 2^14, see pre8_axis).  Each
-// coordinate difference is within one unit of the true one and each stored radius at least one
-// unit above the true one, so a pair the exact law counts as a contact has a rounded distance
-// below r_i + r_j + sqrt(3) < R_i + R_j; binary32 holds the integer differences exactly, and
-// the one unit of slack covers the rounding of the squares and of either law's contact test.
+// coordinate difference is within 1 + 2^-6 units of the true one and each stored radius at
+// least one unit above the true one, so a pair the exact law counts as a contact has a decoded
+// distance below r_i + r_j + 1.76 < R_i + R_j; binary32 holds the integer differences exactly,
+// and the one unit of slack covers the rounding of the squares and of either law's contact
+// test (binary32: about 2^-21 of r_i + r_j <= b, under 2^-7 units).
 __device__ __forceinline__ bool touch8(const uint2 &a, const uint2 &c) {
     const int dx = int(int16_t(uint16_t(c.x - a.x)));
     const int dy = int(c.x - (a.x & 0xFFFF0000u)) >> 16;
