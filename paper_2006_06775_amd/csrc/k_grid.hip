@@ -245,30 +245,11 @@ struct KeyLane {
     int head;
 };
 
-__device__ __forceinline__ KeyLane key_bucket_issue(const Slots &sl, int64_t tile, int64_t ntiles,
-                                                    const double *__restrict__ x, const double *__restrict__ y,
-                                                    const double *__restrict__ z, uint32_t *count) {
-    KeyLane r{};
-    r.i = tile * kBlock + threadIdx.x;
+// The run of equal buckets the lane belongs to, and (on the run's first lane) the run's slots
+// reserved in its bucket.
+__device__ __forceinline__ void key_bucket_run(KeyLane &r, uint32_t *count) {
     const int lane = threadIdx.x & 63;
     r.head = lane;
-    if (tile < ntiles) {
-        const int slot = slot_of_tile(sl, tile);
-        if (slot >= 0) {
-            const GridDev *g = &sl.grids[slot];
-            const SlotDev S = slot_record(sl, slot);
-            r.live = g->valid && r.i - S.agent_off < g->n;
-            if (r.live) {
-                const double b = g->b;
-                const bool per = S.periodic != 0;
-                const int cx = box_coord(x[r.i], b, g->cmin[0], g->dims[0], per);
-                const int cy = box_coord(y[r.i], b, g->cmin[1], g->dims[1], per);
-                const int cz = box_coord(z[r.i], b, g->cmin[2], g->dims[2], per);
-                r.k = uint32_t(cx) + uint32_t(g->dims[0]) * (uint32_t(cy) + uint32_t(g->dims[1]) * uint32_t(cz));
-                r.bk = uint32_t((uint64_t(S.box_off) + r.k) >> kBucketShift);
-            }
-        }
-    }
     if (!r.live) r.bk = 0xFFFFFFFFu;
     const uint32_t prev = __shfl_up(r.bk, 1, 64);
     const unsigned long long heads = __ballot(r.live && (lane == 0 || prev != r.bk));
@@ -280,9 +261,39 @@ __device__ __forceinline__ KeyLane key_bucket_issue(const Slots &sl, int64_t til
     const unsigned long long stop = (heads | ~__ballot(r.live)) & after;
     const int end = stop ? __ffsll(static_cast<long long>(stop)) - 1 : 64;
     if (r.live && lane == r.head) r.base = atomicAdd(&count[r.bk], uint32_t(end - r.head));
-    return r;
 }
 
+// What the key of an agent needs from its tile's slot.
+struct KeyGrid {
+    bool valid;
+    bool per;
+    int64_t n, agent_off, box_off;
+    double b;
+    int32_t cmin[3], dims[3];
+};
+
+__device__ __forceinline__ KeyGrid key_grid(const Slots &sl, int slot) {
+    KeyGrid k{};
+    if (slot < 0) return k;
+    const GridDev *g = &sl.grids[slot];
+    const SlotDev S = slot_record(sl, slot);
+    k.valid = g->valid != 0;
+    k.per = S.periodic != 0;
+    k.n = g->n;
+    k.agent_off = S.agent_off;
+    k.box_off = S.box_off;
+    k.b = g->b;
+    for (int a = 0; a < 3; ++a) {
+        k.cmin[a] = g->cmin[a];
+        k.dims[a] = g->dims[a];
+    }
+    return k;
+}
+
+// The kKeyTiles tiles of a group go through each phase together (grid records, then the
+// coordinates, then the keys, then the atomics), so that their memory accesses are in flight
+// together rather than one tile's chain of dependent accesses after another's.  A plain call
+// reads its one grid record once per group.
 __global__ __launch_bounds__(kBlock) void k_key_bucket(Slots sl, int64_t ntiles, const double *__restrict__ x,
                                                        const double *__restrict__ y,
                                                        const double *__restrict__ z, uint32_t *count,
@@ -292,9 +303,38 @@ __global__ __launch_bounds__(kBlock) void k_key_bucket(Slots sl, int64_t ntiles,
     const int64_t ngroups = (ntiles + kKeyTiles - 1) / kKeyTiles;
     for (int64_t grp = xcd_tile(blockIdx.x, gridDim.x); grp < ngroups; grp += gridDim.x) {
         const int64_t tile = grp * kKeyTiles;
-        KeyLane r[kKeyTiles];
+        KeyGrid kg[kKeyTiles];
+        if (!sl.tilemap) {
+            const KeyGrid k0 = key_grid(sl, 0);
 #pragma unroll
-        for (int u = 0; u < kKeyTiles; ++u) r[u] = key_bucket_issue(sl, tile + u, ntiles, x, y, z, count);
+            for (int u = 0; u < kKeyTiles; ++u) kg[u] = k0;
+        } else {
+#pragma unroll
+            for (int u = 0; u < kKeyTiles; ++u) kg[u] = key_grid(sl, tile + u < ntiles ? slot_of_tile(sl, tile + u) : -1);
+        }
+        KeyLane r[kKeyTiles];
+        double xv[kKeyTiles], yv[kKeyTiles], zv[kKeyTiles];
+#pragma unroll
+        for (int u = 0; u < kKeyTiles; ++u) {
+            r[u] = KeyLane{};
+            r[u].i = (tile + u) * kBlock + threadIdx.x;
+            r[u].live = tile + u < ntiles && kg[u].valid && r[u].i - kg[u].agent_off < kg[u].n;
+            xv[u] = r[u].live ? x[r[u].i] : 0.0;
+            yv[u] = r[u].live ? y[r[u].i] : 0.0;
+            zv[u] = r[u].live ? z[r[u].i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kKeyTiles; ++u) {
+            if (!r[u].live) continue;
+            const KeyGrid &k = kg[u];
+            const int cx = box_coord(xv[u], k.b, k.cmin[0], k.dims[0], k.per);
+            const int cy = box_coord(yv[u], k.b, k.cmin[1], k.dims[1], k.per);
+            const int cz = box_coord(zv[u], k.b, k.cmin[2], k.dims[2], k.per);
+            r[u].k = uint32_t(cx) + uint32_t(k.dims[0]) * (uint32_t(cy) + uint32_t(k.dims[1]) * uint32_t(cz));
+            r[u].bk = uint32_t((uint64_t(k.box_off) + r[u].k) >> kBucketShift);
+        }
+#pragma unroll
+        for (int u = 0; u < kKeyTiles; ++u) key_bucket_run(r[u], count);
 #pragma unroll
         for (int u = 0; u < kKeyTiles; ++u) {
             const uint32_t base = __shfl(r[u].base, r[u].head, 64);
