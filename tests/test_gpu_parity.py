@@ -99,6 +99,9 @@ def grid_cases():
         "faces": inputs.box_face_adversarial(3000, 12.0, seed=2),
         "clustered": inputs.clustered(4000, 300.0, seed=3),
         "negative": {k: (v - 500.0 if k in "xyz" else v) for k, v in inputs.uniform_cube(2000, 150.0, seed=5).items()},
+        # far from the origin: lattice coordinates near 10^8 (the pre-test records keep the box
+        # index mod 4 and the offset within the box)
+        "far": {k: (v + 1.0e9 if k in "xyz" else v) for k, v in inputs.uniform_cube(2000, 150.0, seed=6).items()},
         "single": dict(x=np.array([3.0]), y=np.array([4.0]), z=np.array([5.0]), d=np.array([10.0]), adh=np.array([0.4])),
         "empty": dict(x=np.zeros(0), y=np.zeros(0), z=np.zeros(0), d=np.zeros(0), adh=np.zeros(0)),
         "reach": inputs.reach_adversarial(192, 12.0, seed=7),
@@ -265,7 +268,8 @@ def compare_state(got, ref, L, what, fabs=None, fref=None):
 
 @pytest.mark.parametrize("case,bits", [("c0", 64), ("ragged", 64), ("clustered", 64), ("faces", 64),
                                        ("reach", 64), ("c0", 32), ("clustered", 32), ("reach", 32),
-                                       ("crowded", 64), ("single", 64), ("empty", 64)])
+                                       ("crowded", 64), ("single", 64), ("empty", 64), ("far", 64),
+                                       ("far", 32), ("negative", 64)])
 def test_mech_step_lockstep(case, bits):
     say(f"case: mech lockstep {case} bits={bits}")
     s = grid_cases()[case]
