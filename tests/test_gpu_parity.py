@@ -332,6 +332,24 @@ def test_mech_step_past_4gib_records(bits):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("bits", [64, 32])
+def test_mech_step_explicit_box(bits):
+    """An explicit box edge of three times the largest diameter: spheres are small against the
+    box, so the pre-test records hold radii of a few hundred units and many boxes per reach."""
+    say(f"case: mech lockstep, explicit box 45, bits={bits}")
+    s = grid_cases()["c0"]
+    pop = population(s)
+    p = mech_p(force_bits=bits, box=45.0)
+    bdm.grid_build(pop.soa, p, pop.ws)
+    bdm.mech_step(pop.soa, p, pop.ws)
+    assert bdm.status(pop.ws) == 0
+    got = pop.read()
+    ref = {k: v.copy() for k, v in s.items()}
+    fx, fy, fz, nc, fl = orc.mech_step(ref, box=45.0, force_bits=bits)
+    bit = compare_state(got, ref, 200.0, f"mech box 45/{bits}", pair_abs_sum(s, bits), (fx, fy, fz))
+    assert bit.all()
+
+
 def test_mech_clamp_and_gate_regimes():
     say("case: mech clamp/gate")
     s = inputs.uniform_cube(3000, 200.0, seed=21)  # with dt 0.5 all three regimes occur
