@@ -845,31 +845,32 @@ __global__ __launch_bounds__(kBlock) void k_order_runs(const GridDev *__restrict
 // One workgroup: exclusive scan of the runs' lengths in (pencil, z) order; shift[b] is set so
 // that tile c of bin b goes to position c + shift[b] (mod 2^32).  Clears the run ends for the
 // next build.
+// Only the bins below the grid's bin count can hold tiles (every entry is kNoTile between
+// builds), so only those are read and reset; a small grid's scan skips the rest.
 __global__ __launch_bounds__(1024) void k_order_scan(const GridDev *__restrict__ g, uint32_t *first,
                                                      uint32_t *last, uint32_t *shift) {
-    __shared__ uint32_t s_part[1024];
+    __shared__ uint32_t s_part[1024 / 64];
     const OrderGeom o(g);
     const int t = threadIdx.x;
     const int per = (kOrderBins + 1023) / 1024;
+    const int nbins = o.ok ? int(o.nbins) : 0;
     const int b0 = t * per;
     uint32_t len[per], sum = 0;
     for (int j = 0; j < per; ++j) {
         const int b = b0 + j;
         len[j] = 0;
-        if (o.ok && b < int(o.nbins) && first[b] != kNoTile) len[j] = last[b] - first[b] + 1u;
+        if (b < nbins && first[b] != kNoTile) len[j] = last[b] - first[b] + 1u;
         sum += len[j];
     }
-    s_part[t] = sum;
+    // exclusive scan of the threads' sums: within each wavefront, then over the 16 wavefronts
+    const uint32_t incl = wave_incl_scan(sum);
+    if ((t & 63) == 63) s_part[t >> 6] = incl;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = t >= off ? s_part[t - off] : 0u;
-        __syncthreads();
-        s_part[t] += v;
-        __syncthreads();
-    }
-    uint32_t run = s_part[t] - sum;
+    uint32_t run = incl - sum;
+    for (int w = 0; w < (t >> 6); ++w) run += s_part[w];
     for (int j = 0; j < per; ++j) {
         const int b = b0 + j;
+        if (b >= nbins) break;
         if (len[j]) shift[b] = run - first[b];
         run += len[j];
         first[b] = kNoTile;
