@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# BDM_ORACLE_LIB selects another build of the same source (the sanitizer run of the pins)
+LIB_PATH = os.environ.get("BDM_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 OK, EINVAL, ENOMEM, ENONFINITE, ETOOMANYBOXES = 0, -1, -2, -3, -4
 RNG_INIT, RNG_MOVE, RNG_REC, RNG_INF, RNG_DIV = 1, 2, 3, 4, 5
