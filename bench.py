@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -135,14 +137,25 @@ def serving(args):
     torch.cuda.empty_cache()
     rate = 0.8 * c["requests"] / c["wall_s"]
     trace = serve.make_trace(args.serve_requests, seed=0, rate=rate)
-    srv = serve.Server(cap, boxes, slots, box=plan)
+    # a seeded sample of the requests is kept from both forms and compared bit for bit
+    sample = set(int(i) for i in np.random.default_rng(7).choice(len(trace), 16, replace=False))
+    srv = serve.Server(cap, boxes, slots, box=plan, keep_results=sample)
     b = srv.run(trace).summary()
+    served = srv.results
     del srv
     torch.cuda.empty_cache()
-    p_stats, _ = serve.run_plain(trace, box=plan)
+    p_stats, alone = serve.run_plain(trace, box=plan, keep_results=sample)
     p = p_stats.summary()
     pc_stats, _ = serve.run_plain(calib, box=plan)  # plain capacity: the same closed system
     pc = pc_stats.summary()
+    failed = {"batched_stream": b["failed"], "plain_stream": p["failed"], "batched_closed": c["failed"],
+              "plain_closed": pc["failed"]}
+    if any(failed.values()):
+        raise SystemExit(f"served requests failed on the device: {failed}")
+    equal = sum(all(np.array_equal(served[r][k].view(np.uint64), alone[r][k].view(np.uint64)) for k in "xyz")
+                for r in sample)
+    if equal != len(sample):
+        raise SystemExit(f"served results differ from plain launches: {equal}/{len(sample)} bit-equal")
     return {
         "requests": args.serve_requests, "arrival_rate_per_s": rate, "slots": slots,
         "box_plan": plan.summary(),
@@ -157,6 +170,8 @@ def serving(args):
             "batched_over_plain": c["agent_updates_per_s"] / pc["agent_updates_per_s"],
         },
         "agent_updates": b["agent_updates"],
+        "failed_requests": failed,
+        "served_equal_to_plain": {"sampled_requests": len(sample), "bit_equal": equal},
     }
 
 
@@ -222,11 +237,37 @@ def workloads():
     def sir(step):
         bdm.sim_step(pop.soa, bdm.MODEL_SIR, p, step, pop.ws)
     t = timed_steps(torch, sir, steps)
+    nboxes = bdm.grid_info(pop.ws)["nboxes"]
+    # algorithmic bytes of one SIR step per agent: keys (read x, y, z 24, write key 4), sort
+    # (read key, x, y, z, state, id 33; write the sorted record x, y, z, state, id 29), the
+    # step (read the record 29, write x, y, z, state, id 29) and the box starts 4 (B + 1) / N
+    sir_bytes = n * (24 + 4 + 33 + 29 + 29 + 29) + 4.0 * (nboxes + 1)
+    gbps = sir_bytes * steps / t / 1e9
     out["sir"] = dict(agents=n, steps=steps, seconds=t, agent_updates_per_s=n * steps / t,
-                      final_SIR=bdm.sir_counts(pop.ws), flags=bdm.status(pop.ws))
+                      final_SIR=bdm.sir_counts(pop.ws), flags=bdm.status(pop.ws),
+                      roofline=dict(bound="hbm", achieved=round(gbps, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
+                                    frac=round(gbps / HBM_PEAK_GBPS, 4),
+                                    algorithmic_bytes_per_step=int(sir_bytes),
+                                    scope="whole step: periodic grid build + SIR kernels"))
     del pop
     torch.cuda.empty_cache()
     return out
+
+
+def host_cpu():
+    """Model, clock and core counts of the host this runs on (from /proc/cpuinfo)."""
+    model, mhz = "unknown", None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name") and model == "unknown":
+                    model = line.split(":", 1)[1].strip()
+                elif line.startswith("cpu MHz") and mhz is None:
+                    mhz = float(line.split(":", 1)[1])
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return dict(model=model, mhz=mhz, nproc=usable, logical_cpus=os.cpu_count())
 
 
 def cpu_baseline(n_sample):
@@ -239,6 +280,7 @@ def cpu_baseline(n_sample):
     orc.mech_step(s, k=2.0, gamma=1.0, dt=0.01, max_disp=3.0)
     dt = time.perf_counter() - t0
     return dict(value=n_sample / dt, unit="agent-updates/s", cores=1, kind="oracle",
+                host=host_cpu(),
                 sample=f"one mechanical step (grid build + forces + move, binary64) of "
                        f"{n_sample} agents at the benchmark's density (cube edge {L:.1f} um), "
                        f"single thread, {dt:.1f} s")

@@ -228,6 +228,18 @@ int bdm_grid_export(const bdm_workspace *ws, uint32_t *key, uint32_t *order, uin
 int bdm_contacts(const bdm_workspace *ws, const bdm_params *params, uint32_t *counts,
                  const int64_t *offsets, uint32_t *ids, void *stream);
 
+/* Test hook: bdm_sim_step of model BDM_MODEL_MECH or BDM_MODEL_SPHEROID (same arguments, same
+ * results) through the traced instantiation of the same kernels, which also records the contact
+ * decisions the step's own walk takes [paper Sec. 2.1: the neighbours found in the 27 boxes].
+ * For each agent s in the step's output order (box-sorted slots), counts[s] = the number of
+ * contacts whose terms the step added to F_s and hashes[s] = h over those contacts in the order
+ * they were added, h = h*0x9E3779B1 + p + 1 (mod 2^32, from h = 0) with p the partner's
+ * box-sorted position (the index into bdm_grid_export's order[]).  counts and hashes are device
+ * arrays of soa->capacity elements; entries of slots >= n are not written.  Errors: as
+ * bdm_sim_step; BDM_EINVAL for another model or a NULL counts/hashes. */
+int bdm_sim_step_traced(const bdm_soa *soa, int32_t model, const bdm_params *params, int64_t step,
+                        const bdm_workspace *ws, uint32_t *counts, uint32_t *hashes, void *stream);
+
 /* ---- batched form --------------------------------------------------------------------------
  * Callers: many independent simulations of uneven sizes stepped together (one launch per
  * phase for all of them, capturable in a graph).  The per-slot work is the plain mechanical
@@ -258,6 +270,12 @@ int bdm_batch_clear_slot(const bdm_batch *b, int32_t slot, int64_t agent_off, in
  * launch geometry: the same call sequence is replayable as a graph.  Device conditions set the
  * slot's status bits (bdm_batch_slot_status).  Errors: BDM_EINVAL, BDM_ENOWS. */
 int bdm_batch_step(const bdm_soa *packed, const bdm_batch *b, void *stream);
+
+/* Test hook: bdm_batch_step through the traced instantiation of its kernels (see
+ * bdm_sim_step_traced); counts/hashes are indexed like the packed arrays (b->capacity
+ * elements), positions p are box-sorted positions within the agent's own slot. */
+int bdm_batch_step_traced(const bdm_soa *packed, const bdm_batch *b, uint32_t *counts, uint32_t *hashes,
+                          void *stream);
 
 /* Status bits and remaining steps of one slot (host).  Synchronises the stream. */
 int bdm_batch_slot_status(const bdm_batch *b, int32_t slot, uint32_t *flags, int64_t *steps_left,

@@ -28,9 +28,10 @@ GEN_CUBE, GEN_BALL, GEN_SIR = 0, 1, 2
 SYMBOLS = (
     "bdm_workspace_bytes", "bdm_workspace_init", "bdm_generate", "bdm_grid_build",
     "bdm_mech_step", "bdm_sim_step", "bdm_read_agents", "bdm_status", "bdm_sir_counts",
-    "bdm_grid_info", "bdm_grid_export", "bdm_contacts", "bdm_batch_workspace_bytes",
-    "bdm_batch_init", "bdm_batch_set_slot", "bdm_batch_clear_slot", "bdm_batch_step",
-    "bdm_batch_slot_status", "bdm_fp_probe", "bdm_strerror", "bdm_last_error",
+    "bdm_grid_info", "bdm_grid_export", "bdm_contacts", "bdm_sim_step_traced",
+    "bdm_batch_workspace_bytes", "bdm_batch_init", "bdm_batch_set_slot", "bdm_batch_clear_slot",
+    "bdm_batch_step", "bdm_batch_step_traced", "bdm_batch_slot_status", "bdm_fp_probe",
+    "bdm_strerror", "bdm_last_error",
 )
 MAX_SLOTS, SLOT_ALIGN, BOX_ALIGN = 4096, 1024, 64
 
@@ -101,6 +102,8 @@ def _load():
         "bdm_grid_info": ([P, P, P], C.c_int),
         "bdm_grid_export": ([P, P, P, P, P], C.c_int),
         "bdm_contacts": ([P, P, P, P, P, P], C.c_int),
+        "bdm_sim_step_traced": ([P, C.c_int32, P, C.c_int64, P, P, P, P], C.c_int),
+        "bdm_batch_step_traced": ([P, P, P, P, P], C.c_int),
         "bdm_fp_probe": ([P, P, C.c_int64, P, P, P, P, P], C.c_int),
         "bdm_batch_workspace_bytes": ([C.c_int64, C.c_int64, C.c_int32], C.c_size_t),
         "bdm_batch_init": ([P, P], C.c_int),
@@ -310,6 +313,13 @@ def contacts(ws: Workspace, p: Params, n: int = None, stream=None):
     return u32(counts)[:n], offsets[:n].cpu().numpy(), u32(ids)[:total]
 
 
+def sim_step_traced(soa: Soa, model: int, p: Params, step: int, ws: Workspace, counts, hashes,
+                    stream=None):
+    """sim_step through the traced kernels; counts/hashes: device int32 tensors of capacity."""
+    _check(_lib.bdm_sim_step_traced(_ref(soa), model, _ref(p), step, _ref(ws), _ptr(counts),
+                                    _ptr(hashes), _stream(stream)), "sim_step_traced")
+
+
 def fp_probe(a: torch.Tensor, b: torch.Tensor, stream=None):
     n = a.numel()
     outs = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(2)] + \
@@ -343,6 +353,11 @@ def batch_clear_slot(b: BatchRec, slot: int, agent_off: int, capacity: int, stre
 
 def batch_step(soa: Soa, b: BatchRec, stream=None):
     _check(_lib.bdm_batch_step(_ref(soa), _ref(b), _stream(stream)), "batch_step")
+
+
+def batch_step_traced(soa: Soa, b: BatchRec, counts, hashes, stream=None):
+    _check(_lib.bdm_batch_step_traced(_ref(soa), _ref(b), _ptr(counts), _ptr(hashes),
+                                      _stream(stream)), "batch_step_traced")
 
 
 def batch_slot_status(b: BatchRec, slot: int, stream=None):
@@ -391,6 +406,9 @@ class Batch:
 
     def step(self, stream=None):
         batch_step(self.soa, self.rec, stream)
+
+    def step_traced(self, counts, hashes, stream=None):
+        batch_step_traced(self.soa, self.rec, counts, hashes, stream)
 
     def slot_status(self, slot, stream=None):
         return batch_slot_status(self.rec, slot, stream)

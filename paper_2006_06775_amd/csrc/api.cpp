@@ -253,8 +253,12 @@ int bdm_mech_step(const bdm_soa *soa, const bdm_params *params, const bdm_worksp
     return hip_check("mech_step launch");
 }
 
-int bdm_sim_step(const bdm_soa *soa, int32_t model, const bdm_params *params, int64_t step,
-                 const bdm_workspace *ws, void *stream) {
+}  // extern "C"
+
+namespace {
+
+int sim_step(const bdm_soa *soa, int32_t model, const bdm_params *params, int64_t step, const bdm_workspace *ws,
+             const bdm::TraceOut *trace, void *stream) {
     g_last_error.clear();
     bdm::Ws w;
     int rc = get_ws(ws, &w);
@@ -282,10 +286,11 @@ int bdm_sim_step(const bdm_soa *soa, int32_t model, const bdm_params *params, in
         rc = hip_check("grid_build launch");
         if (rc) return rc;
         bdm::launch_mech(*soa, plain_slots(w, rec), soa->capacity, params->force_bits, model == BDM_MODEL_SPHEROID, w,
-                         st);
+                         st, trace);
         return hip_check("mech_step launch");
     }
     case BDM_MODEL_SIR: {
+        if (trace) return fail(BDM_EINVAL, "a traced step is a mechanical one (MECH or SPHEROID)");
         rc = check_soa(soa, w.lay.capacity, false, true);
         if (rc) return rc;
         rc = check_sir_params(params);
@@ -309,6 +314,23 @@ int bdm_sim_step(const bdm_soa *soa, int32_t model, const bdm_params *params, in
     default:
         return fail(BDM_EINVAL, "unknown model %d", model);
     }
+}
+
+}  // namespace
+
+extern "C" {
+
+int bdm_sim_step(const bdm_soa *soa, int32_t model, const bdm_params *params, int64_t step,
+                 const bdm_workspace *ws, void *stream) {
+    return sim_step(soa, model, params, step, ws, nullptr, stream);
+}
+
+int bdm_sim_step_traced(const bdm_soa *soa, int32_t model, const bdm_params *params, int64_t step,
+                        const bdm_workspace *ws, uint32_t *counts, uint32_t *hashes, void *stream) {
+    g_last_error.clear();
+    if (!counts || !hashes) return fail(BDM_EINVAL, "counts and hashes are required");
+    const bdm::TraceOut t{counts, hashes};
+    return sim_step(soa, model, params, step, ws, &t, stream);
 }
 
 int bdm_read_agents(const bdm_soa *soa, double *out_x, double *out_y, double *out_z, double *out_diam,
@@ -486,7 +508,11 @@ int bdm_batch_clear_slot(const bdm_batch *b, int32_t slot, int64_t agent_off, in
     return hip_check("batch_clear_slot launch");
 }
 
-int bdm_batch_step(const bdm_soa *packed, const bdm_batch *b, void *stream) {
+}  // extern "C"
+
+namespace {
+
+int batch_step(const bdm_soa *packed, const bdm_batch *b, const bdm::TraceOut *trace, void *stream) {
     g_last_error.clear();
     bdm::Ws w;
     int rc = get_batch(b, &w);
@@ -502,9 +528,25 @@ int bdm_batch_step(const bdm_soa *packed, const bdm_batch *b, void *stream) {
     sl.grids = w.grid;
     sl.nslots = b->slots;
     bdm::launch_grid_build(*packed, sl, b->capacity, false, w, st);
-    bdm::launch_mech(*packed, sl, b->capacity, 0, false, w, st);
+    bdm::launch_mech(*packed, sl, b->capacity, 0, false, w, st, trace);
     bdm::launch_batch_advance(w, st);
     return hip_check("batch_step launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+int bdm_batch_step(const bdm_soa *packed, const bdm_batch *b, void *stream) {
+    return batch_step(packed, b, nullptr, stream);
+}
+
+int bdm_batch_step_traced(const bdm_soa *packed, const bdm_batch *b, uint32_t *counts, uint32_t *hashes,
+                          void *stream) {
+    g_last_error.clear();
+    if (!counts || !hashes) return fail(BDM_EINVAL, "counts and hashes are required");
+    const bdm::TraceOut t{counts, hashes};
+    return batch_step(packed, b, &t, stream);
 }
 
 int bdm_batch_slot_status(const bdm_batch *b, int32_t slot, uint32_t *flags, int64_t *steps_left, void *stream) {

@@ -66,8 +66,15 @@ struct GridDev {
     unsigned long long sir_counts[3];
     int64_t sorted_base;            // first sorted position of this slot (start[box_off])
     double inv_b;                   // 1 / b, rounded (the pre-test records' scale)
+    int32_t kind;                   // what the last build wrote (kGrid*)
+    int32_t consumed;               // 1 once a plain mechanical step has used the build
 };
 static_assert(sizeof(GridDev) <= 256, "grid record must fit its slot");
+
+// What a grid build wrote, so that a step can refuse a build it cannot use: open space with the
+// 8-byte pre-test records, the same plus the binary32 copies (spheroid steps), or the periodic
+// (SIR) lattice, which writes no pre-test records.
+enum : int32_t { kGridNone = 0, kGridOpen = 1, kGridOpenF32 = 2, kGridPeriodic = 3 };
 
 // Parameters and placement of one slot.
 struct SlotDev {

@@ -110,7 +110,8 @@ __global__ __launch_bounds__(kBlock) void k_bounds(Slots sl, int64_t nbtiles, co
 }
 
 // One workgroup per slot: reduce the slot's bounds partials, then box edge, lattice, box count.
-__global__ __launch_bounds__(kBlock) void k_finalize(Slots sl, const int64_t *n_ptr, const double *partials) {
+__global__ __launch_bounds__(kBlock) void k_finalize(Slots sl, const int64_t *n_ptr, const double *partials,
+                                                     int32_t kind) {
     const int slot = int(blockIdx.x);
     if (slot >= sl.nslots) return;
     const SlotDev a = slot_record(sl, slot);
@@ -158,6 +159,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Slots sl, const int64_t *n_
     const bool bad = s_red[0][7] != 0.0;
     g->sir_counts[0] = g->sir_counts[1] = g->sir_counts[2] = 0ull;
     g->valid = 0;
+    g->kind = kind;
+    g->consumed = 0;
     g->n = 0;
     g->nboxes = 0;
     if (idle) return;  // idle batch slot
@@ -205,16 +208,30 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Slots sl, const int64_t *n_
             g->n = 0;
             return;
         }
+        // The span of each axis is formed in binary64 (exact for these integers) and checked
+        // against max_boxes before anything is narrowed to int32: coordinates in [-2^30,
+        // 2^30 - 1] can span 2^31 boxes, one more than int32 holds.
+        double c0[3], span[3];
         for (int i = 0; i < 3; ++i) {
             // floor is monotone, so min/max of floor(x/b) are floor(min x / b), floor(max x / b)
-            const double c0 = floor(lo[i] / b), c1 = floor(hi[i] / b);
-            if (!(c0 >= -1073741824.0 && c1 <= 1073741823.0)) {
+            c0[i] = floor(lo[i] / b);
+            const double c1 = floor(hi[i] / b);
+            if (!(c0[i] >= -1073741824.0 && c1 <= 1073741823.0)) {
                 g->flags |= BDM_FLAG_NONFINITE;
                 g->n = 0;
                 return;
             }
-            g->cmin[i] = int32_t(c0);
-            g->dims[i] = int32_t(c1) - int32_t(c0) + 1;
+            span[i] = c1 - c0[i] + 1.0;
+        }
+        if (span[0] * span[1] * span[2] > double(a.max_boxes) || span[0] > 2147483647.0 ||
+            span[1] > 2147483647.0 || span[2] > 2147483647.0) {
+            g->flags |= BDM_FLAG_BOXES;
+            g->n = 0;
+            return;
+        }
+        for (int i = 0; i < 3; ++i) {
+            g->cmin[i] = int32_t(c0[i]);
+            g->dims[i] = int32_t(span[i]);
         }
     }
     g->b = b;
@@ -929,7 +946,8 @@ void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, bool
     const int64_t nbt = (capacity + kBoundsTile - 1) / kBoundsTile;
     hipLaunchKernelGGL(k_bounds, dim3(tile_grid(sl, nbt)), dim3(kBlock), 0, st, sl, nbt, s.n, s.x, s.y, s.z, d,
                        w.partials, w.tiles, w.lay.max_tiles);
-    hipLaunchKernelGGL(k_finalize, dim3(unsigned(sl.nslots)), dim3(kBlock), 0, st, sl, s.n, w.partials);
+    const int32_t kind = (!sl.table && sl.one.periodic) ? kGridPeriodic : (f32_copy ? kGridOpenF32 : kGridOpen);
+    hipLaunchKernelGGL(k_finalize, dim3(unsigned(sl.nslots)), dim3(kBlock), 0, st, sl, s.n, w.partials, kind);
     const int64_t nt = (capacity + kBlock - 1) / kBlock;
     const unsigned nb = tile_grid(sl, nt);
     // keys and bucket ranks (rank array), bucket starts, agent indices by bucket

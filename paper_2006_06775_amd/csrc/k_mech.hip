@@ -34,8 +34,10 @@ constexpr uint32_t kCullMaxBox = 8;  // agents in a box up to which its agents d
 
 // The pair law for agent i with record p and a candidate j at offset (dx, dy, dz) = p - q with
 // radius rj: whether the spheres overlap and, if so, the term (tx, ty, tz) that j adds to the
-// force on i.  A non-contact adds nothing.
-template <bool F32>
+// force on i.  A non-contact adds nothing.  Coincident centres add nothing either; kCoincident
+// (the traced kernels) reports them as the contact they are, with a term of +0 (a running sum
+// that starts at +0 never becomes -0, so adding +0 changes no bit).
+template <bool F32, bool kCoincident = false>
 __device__ __forceinline__ bool pair_term(const double4 &p, double dx, double dy, double dz, double rj, float rif,
                                           const SlotDev &a, double &tx, double &ty, double &tz) {
     const double ri = p.w;
@@ -43,6 +45,12 @@ __device__ __forceinline__ bool pair_term(const double4 &p, double dx, double dy
         const double s = ri + rj;
         const double dist = __builtin_sqrt((dx * dx + dy * dy) + dz * dz);
         const double delta = s - dist;
+        if constexpr (kCoincident) {
+            if (delta > 0.0 && dist == 0.0) {
+                tx = ty = tz = 0.0;
+                return true;
+            }
+        }
         if (!(delta > 0.0) || dist == 0.0) return false;
         const double rhat = (ri * rj) / s;
         const double F = a.k * delta - a.gamma * __builtin_sqrt(rhat * delta);
@@ -56,6 +64,12 @@ __device__ __forceinline__ bool pair_term(const double4 &p, double dx, double dy
         const float rjf = float(rj);
         const float sf = rif + rjf;
         const float delta = sf - dist;
+        if constexpr (kCoincident) {
+            if (delta > 0.0f && dist == 0.0f) {
+                tx = ty = tz = 0.0;
+                return true;
+            }
+        }
         if (!(delta > 0.0f) || dist == 0.0f) return false;
         const float rhat = (rif * rjf) / sf;
         const float F = a.kf * delta - a.gf * __builtin_sqrtf(rhat * delta);
@@ -67,16 +81,36 @@ __device__ __forceinline__ bool pair_term(const double4 &p, double dx, double dy
     return true;
 }
 
-template <bool F32>
-__device__ __forceinline__ void exact_pair(const double4 &p, double dx, double dy, double dz, double rj, float rif,
+template <bool F32, bool kCoincident>
+__device__ __forceinline__ bool exact_pair(const double4 &p, double dx, double dy, double dz, double rj, float rif,
                                            const SlotDev &a, double &fx, double &fy, double &fz) {
     double tx, ty, tz;
-    if (pair_term<F32>(p, dx, dy, dz, rj, rif, a, tx, ty, tz)) {
+    if (pair_term<F32, kCoincident>(p, dx, dy, dz, rj, rif, a, tx, ty, tz)) {
         fx = fx + tx;
         fy = fy + ty;
         fz = fz + tz;
+        return true;
     }
+    return false;
 }
+
+// Contact record of a traced step (a test hook): every contact the step adds, in the order it
+// is added, as a count and an order-sensitive hash of the partners' sorted positions within the
+// slot (h = h * 0x9E3779B1 + position + 1, modulo 2^32).  NoTrace compiles to nothing; the
+// traced kernels are separate instantiations of the same code, so their contact decisions are
+// the step's own.
+struct NoTrace {
+    static constexpr bool kOn = false;
+    __device__ __forceinline__ void hit(uint32_t) {}
+};
+struct Trace {
+    static constexpr bool kOn = true;
+    uint32_t unit, base, n, h;  // candidate offsets are unit * (base + position)
+    __device__ __forceinline__ void hit(uint32_t u) {
+        n += 1u;
+        h = h * 0x9E3779B1u + (u / unit - base + 1u);
+    }
+};
 
 // Key range [lo, hi) of row r (dz = r / 3 - 1, dy = r % 3 - 1) of the 27 boxes around the box
 // (cx, cy, cz): boxes x0..x1 of that row, clipped to the lattice; an empty range off it.
@@ -346,10 +380,10 @@ __device__ __forceinline__ void wave_lds_sync() {
 // rows 0-2 hold a round's terms, rows 3 and 6-8 every lane's own record (r, x, y, z), rows 4-5
 // the layout (lane | slot << 6 per pair, at most 512; bit 15 set once the pair is a contact).
 // Every lane of the wavefront must take part.
-template <bool F32, int kQ, class Rec>
+template <bool F32, int kQ, class Rec, class Tr>
 __device__ __forceinline__ void exact_packed(const SlotDev &S, const double4 &p, const Rec &rec, uint32_t qn,
                                              uint2 (*s_run)[kBlock], const uint32_t (*s_q)[kBlock], int t,
-                                             double &fx, double &fy, double &fz) {
+                                             double &fx, double &fy, double &fz, Tr &tr) {
     static_assert(kQ <= 8, "the layout holds 64 lanes x 8 slots");
     const int lane = t & 63, w0 = t - lane;
     const uint32_t incl = wave_incl_scan(qn), excl = incl - qn;
@@ -374,7 +408,7 @@ __device__ __forceinline__ void exact_packed(const SlotDev &S, const double4 &p,
                 __builtin_bit_cast(double, s_run[6][w0 + o]), __builtin_bit_cast(double, s_run[7][w0 + o]),
                 __builtin_bit_cast(double, s_run[8][w0 + o]), __builtin_bit_cast(double, s_run[3][w0 + o]));
             const double4 r = rec.full(s_q[m >> 6][w0 + o]);
-            if (pair_term<F32>(po, po.x - r.x, po.y - r.y, po.z - r.z, r.w, float(po.w), S, tx, ty, tz))
+            if (pair_term<F32, Tr::kOn>(po, po.x - r.x, po.y - r.y, po.z - r.z, r.w, float(po.w), S, tx, ty, tz))
                 *le = uint16_t(m | 0x8000u);
         }
         s_run[0][t] = __builtin_bit_cast(uint2, tx);
@@ -383,11 +417,13 @@ __device__ __forceinline__ void exact_packed(const SlotDev &S, const double4 &p,
         wave_lds_sync();
         const uint32_t lo = excl > base ? excl : base, hi = incl < base + 64u ? incl : base + 64u;
         for (uint32_t f = lo; f < hi; ++f) {
-            if (*layout(f) & 0x8000u) {
+            const uint32_t m = *layout(f);
+            if (m & 0x8000u) {
                 const int col = w0 + int(f - base);
                 fx = fx + __builtin_bit_cast(double, s_run[0][col]);
                 fy = fy + __builtin_bit_cast(double, s_run[1][col]);
                 fz = fz + __builtin_bit_cast(double, s_run[2][col]);
+                if constexpr (Tr::kOn) tr.hit(s_q[(m >> 6) & 7u][t]);
             }
         }
     }
@@ -403,12 +439,12 @@ __device__ __forceinline__ void exact_packed(const SlotDev &S, const double4 &p,
 // for the others instead of running its own exact pass alone), and the last pass is the
 // packed one.  In crowded populations nearly every lane fills its longer queue within a few
 // candidates of the others, and each lane empties it where it fills (measured faster there).
-template <bool F32, int kQ, class Rec, class Pre>
+template <bool F32, int kQ, class Rec, class Pre, class Tr>
 __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const double4 &p,
                                             const Rec &rec, float slack, uint2 (*s_run)[kBlock], uint32_t cnt,
                                             uint32_t (*s_q)[kBlock], int t, const Pre &pre_final,
                                             const RowUnion &un, typename Rec::Pre *s_stage, double &fx, double &fy,
-                                            double &fz) {
+                                            double &fz, Tr &tr) {
     constexpr uint32_t U = Rec::kUnit;
     constexpr bool kSync = kQ == kQueue;
     const uint32_t qu = q * U;
@@ -427,7 +463,10 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
                 for (uint32_t k = 0; k < qn; ++k) {
                     const double dx = p.x - r.x, dy = p.y - r.y, dz = p.z - r.z, rj = r.w;
                     r = rec.full(s_q[k + 1u < qn ? k + 1u : k][t]);
-                    exact_pair<F32>(p, dx, dy, dz, rj, rif, S, fx, fy, fz);
+                    const bool hit = exact_pair<F32, Tr::kOn>(p, dx, dy, dz, rj, rif, S, fx, fy, fz);
+                    if constexpr (Tr::kOn) {
+                        if (hit) tr.hit(s_q[k][t]);
+                    }
                 }
             } else {  // the longer queue's kernel has registers to spare: two records ahead
                 const uint32_t last = qn - 1u;
@@ -437,7 +476,10 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
                     const double dx = p.x - r.x, dy = p.y - r.y, dz = p.z - r.z, rj = r.w;
                     r = r1;
                     r1 = rec.full(s_q[min(k + 2u, last)][t]);
-                    exact_pair<F32>(p, dx, dy, dz, rj, rif, S, fx, fy, fz);
+                    const bool hit = exact_pair<F32, Tr::kOn>(p, dx, dy, dz, rj, rif, S, fx, fy, fz);
+                    if constexpr (Tr::kOn) {
+                        if (hit) tr.hit(s_q[k][t]);
+                    }
                 }
             }
         }
@@ -471,7 +513,8 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
                 // four records per step, read from LDS together; the queues are emptied first
                 // when one of them could fill within the step.  [a, b) is the lane's own run
                 // within the chunk (entries past the chunk's end are valid LDS and outside it).
-                // The agent itself may enter its queue: the law adds nothing at zero distance.
+                // The agent itself may enter its queue: the law adds nothing at zero distance
+                // (the traced kernels, which count coincident centres as contacts, skip it).
                 const uint32_t kn = min(64u, uhi - base);
                 const uint32_t a = own.x > base ? min(own.x - base, kn) : 0u;
                 const uint32_t b = own.y > base ? min(own.y - base, kn) : 0u;
@@ -483,8 +526,9 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const uint32_t e = k + uint32_t(i);
-                        s_q[qn][t] = (base + e) * U;
-                        qn += ((e >= a) & (e < b) & Rec::touch(pf, cand[i], slack)) ? 1u : 0u;
+                        const uint32_t u = (base + e) * U;
+                        s_q[qn][t] = u;
+                        qn += ((e >= a) & (e < b) & (!Tr::kOn || u != qu) & Rec::touch(pf, cand[i], slack)) ? 1u : 0u;
                     }
                 }
             }
@@ -522,19 +566,20 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
     }
     pre_final();
     if constexpr (kSync)
-        exact_packed<F32, kQ>(S, p, rec, qn, s_run, s_q, t, fx, fy, fz);
+        exact_packed<F32, kQ>(S, p, rec, qn, s_run, s_q, t, fx, fy, fz, tr);
     else
         flush();
 }
 
 // One tile: 256 agents of one slot, one lane per agent.  precision: 64 or 32 for a plain call;
 // 0 = per slot.
-template <int kPrec, int kQ, class Rec>
+template <int kPrec, int kQ, class Tr, class Rec>
 __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const Rec &rec,
                                           const double *__restrict__ adh_s, const uint32_t *__restrict__ id_s,
                                           const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
                                           const uint32_t *__restrict__ start_all, const bdm_soa &out,
-                                          uint2 (*s_run)[kBlock], uint32_t (*s_q)[kBlock], typename Rec::Pre *s_stage) {
+                                          uint2 (*s_run)[kBlock], uint32_t (*s_q)[kBlock], typename Rec::Pre *s_stage,
+                                          const TraceOut &tout) {
     const int t = threadIdx.x;
     const int slot = slot_of_tile(sl, tile);
     if (slot < 0) return;
@@ -564,11 +609,17 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
         id = id_s[q];
         if (out.state) state = state_s[q];
     };
+    Tr tr{};
+    if constexpr (Tr::kOn) tr = Tr{Rec::kUnit, uint32_t(g->sorted_base), 0u, 0u};
     if (f32)
-        mech_forces<true, kQ>(S, q, p, rec, pretest_slack(g), s_run, cnt, s_q, t, pre, un, s_stage, fx, fy, fz);
+        mech_forces<true, kQ>(S, q, p, rec, pretest_slack(g), s_run, cnt, s_q, t, pre, un, s_stage, fx, fy, fz, tr);
     else
-        mech_forces<false, kQ>(S, q, p, rec, pretest_slack(g), s_run, cnt, s_q, t, pre, un, s_stage, fx, fy, fz);
+        mech_forces<false, kQ>(S, q, p, rec, pretest_slack(g), s_run, cnt, s_q, t, pre, un, s_stage, fx, fy, fz, tr);
     if (!live) return;
+    if constexpr (Tr::kOn) {
+        tout.counts[S.agent_off + l] = tr.n;
+        tout.hashes[S.agent_off + l] = tr.h;
+    }
 
     // adherence gate, clamp, integrate (binary64)
     double nxp = p.x, nyp = p.y, nzp = p.z;
@@ -600,59 +651,64 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
 }
 
 // Plain call: the tiles in the pencil order, one contiguous part of it per XCD.
-template <int kPrec, int kQ, class Rec>
+template <int kPrec, int kQ, class Tr, class Rec>
 __device__ __forceinline__ void mech_plain(const Slots &sl, const uint32_t *__restrict__ order, const Rec &rec,
                                            const double *__restrict__ adh_s, const uint32_t *__restrict__ id_s,
                                            const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
-                                           const uint32_t *__restrict__ start, const bdm_soa &out) {
+                                           const uint32_t *__restrict__ start, const bdm_soa &out,
+                                           const TraceOut &tout) {
     __shared__ uint2 s_run[9][kBlock];
     __shared__ uint32_t s_q[kQ][kBlock];
     __shared__ typename Rec::Pre s_stage[kQ == kQueueCrowded ? kBlock : 1];  // records of a cooperative walk
     GridDev *g0 = &sl.grids[0];
-    if (!g0->valid) {  // no grid of these agents (never built, or its build failed): report it
+    // no usable grid of these agents: never built, its build failed, already used by a step,
+    // or built for another model (the periodic lattice has no pre-test records; the crowded
+    // kernel reads the binary32 copies only spheroid builds write)
+    const bool usable = g0->valid && !g0->consumed &&
+                        (kQ == kQueueCrowded ? g0->kind == kGridOpenF32 : (g0->kind == kGridOpen || g0->kind == kGridOpenF32));
+    if (!usable) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&g0->flags, BDM_FLAG_NOGRID);
         return;
     }
     const uint32_t live_tiles = uint32_t((g0->n + kBlock - 1) / kBlock);
     if (blockIdx.x >= live_tiles) return;
-    mech_tile<kPrec, kQ>(sl, order[xcd_tile(blockIdx.x, live_tiles)], rec, adh_s, id_s, state_s, key_s, start, out,
-                         s_run, s_q, s_stage);
+    mech_tile<kPrec, kQ, Tr>(sl, order[xcd_tile(blockIdx.x, live_tiles)], rec, adh_s, id_s, state_s, key_s, start,
+                             out, s_run, s_q, s_stage, tout);
 }
 
 // The normal queue: six wavefronts per SIMD (80 registers), which is also what the LDS of a
 // workgroup allows.
-template <int kPrec, class Rec>
+template <int kPrec, class Tr, class Rec>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_mech(
     Slots sl, const uint32_t *__restrict__ order, Rec rec, const double *__restrict__ adh_s,
     const uint32_t *__restrict__ id_s, const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
-    const uint32_t *__restrict__ start, bdm_soa out) {
-    mech_plain<kPrec, kQueue>(sl, order, rec, adh_s, id_s, state_s, key_s, start, out);
+    const uint32_t *__restrict__ start, bdm_soa out, TraceOut tout) {
+    mech_plain<kPrec, kQueue, Tr>(sl, order, rec, adh_s, id_s, state_s, key_s, start, out, tout);
 }
 
 // The crowded queue (its LDS allows four wavefronts per SIMD).
-template <int kPrec, class Rec>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_mech_crowded(Slots sl, const uint32_t *__restrict__ order, Rec rec,
-                                                         const double *__restrict__ adh_s,
-                                                         const uint32_t *__restrict__ id_s,
-                                                         const uint8_t *__restrict__ state_s,
-                                                         const uint32_t *__restrict__ key_s,
-                                                         const uint32_t *__restrict__ start, bdm_soa out) {
-    mech_plain<kPrec, kQueueCrowded>(sl, order, rec, adh_s, id_s, state_s, key_s, start, out);
+template <int kPrec, class Tr, class Rec>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_mech_crowded(
+    Slots sl, const uint32_t *__restrict__ order, Rec rec, const double *__restrict__ adh_s,
+    const uint32_t *__restrict__ id_s, const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
+    const uint32_t *__restrict__ start, bdm_soa out, TraceOut tout) {
+    mech_plain<kPrec, kQueueCrowded, Tr>(sl, order, rec, adh_s, id_s, state_s, key_s, start, out, tout);
 }
 
 // Batch (precision per slot): the workgroups stride over the tiles (a simulation's tiles spread
 // over all of them), neighbouring tiles of a round going to workgroups of one XCD.
-template <class Rec>
+template <class Tr, class Rec>
 __global__ __launch_bounds__(kBlock) void k_mech_batch(Slots sl, int64_t ntiles, Rec rec,
                                                        const double *__restrict__ adh_s,
                                                        const uint32_t *__restrict__ id_s,
                                                        const uint8_t *__restrict__ state_s,
                                                        const uint32_t *__restrict__ key_s,
-                                                       const uint32_t *__restrict__ start, bdm_soa out) {
+                                                       const uint32_t *__restrict__ start, bdm_soa out,
+                                                       TraceOut tout) {
     __shared__ uint2 s_run[9][kBlock];
     __shared__ uint32_t s_q[kQueue][kBlock];
     for (int64_t tile = xcd_tile(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x)
-        mech_tile<0, kQueue>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q, nullptr);
+        mech_tile<0, kQueue, Tr>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q, nullptr, tout);
 }
 
 // Test hook: contact lists per sorted slot in force-sum order (mechanical contact, plain calls).
@@ -696,12 +752,12 @@ __global__ __launch_bounds__(kBlock) void k_contacts_mech(Slots sl, const double
     counts[s] = c;
 }
 
-template <class Rec>
+template <class Tr, class Rec>
 static void launch_mech_rec(const bdm_soa &s, const Slots &sl, int64_t ntiles, unsigned nb, int precision,
-                            const uint32_t *order, const Rec &rec, const Ws &w, hipStream_t st) {
+                            const uint32_t *order, const Rec &rec, const Ws &w, const TraceOut &tout, hipStream_t st) {
 #define BDM_MECH(K, P)                                                                                     \
-    hipLaunchKernelGGL((K<P, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, order, rec, w.adh, w.ids, w.state, w.rank, \
-                       w.start, s)
+    hipLaunchKernelGGL((K<P, Tr, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, order, rec, w.adh, w.ids, w.state, \
+                       w.rank, w.start, s, tout)
     if constexpr (Rec::kF32Copy) {  // the crowded kernel
         if (precision == 32)
             BDM_MECH(k_mech_crowded, 32);
@@ -712,32 +768,50 @@ static void launch_mech_rec(const bdm_soa &s, const Slots &sl, int64_t ntiles, u
     } else if (precision == 64) {
         BDM_MECH(k_mech, 64);
     } else {
-        hipLaunchKernelGGL((k_mech_batch<Rec>), dim3(nb), dim3(kBlock), 0, st, sl, ntiles, rec, w.adh, w.ids,
-                           w.state, w.rank, w.start, s);
+        hipLaunchKernelGGL((k_mech_batch<Tr, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, ntiles, rec, w.adh, w.ids,
+                           w.state, w.rank, w.start, s, tout);
     }
 #undef BDM_MECH
+}
+
+template <class Rec>
+static void launch_mech_traced(const bdm_soa &s, const Slots &sl, int64_t ntiles, unsigned nb, int precision,
+                               const uint32_t *order, const Rec &rec, const Ws &w, const TraceOut *trace,
+                               hipStream_t st) {
+    if (trace)
+        launch_mech_rec<Trace>(s, sl, ntiles, nb, precision, order, rec, w, *trace, st);
+    else
+        launch_mech_rec<NoTrace>(s, sl, ntiles, nb, precision, order, rec, w, TraceOut{nullptr, nullptr}, st);
+}
+
+// A plain mechanical step has used its grid build: the next step needs a new one.
+__global__ void k_grid_consume(GridDev *g) {
+    if (threadIdx.x == 0) g->consumed = 1;
 }
 
 // crowded: a population packed so densely that agents have tens of contacts (the growing
 // spheroid); a longer queue then saves exact-law rounds, at the cost of LDS (occupancy).
 void launch_mech(const bdm_soa &s, const Slots &sl, int64_t capacity, int precision, bool crowded, const Ws &w,
-                 hipStream_t st) {
+                 hipStream_t st, const TraceOut *trace) {
     const int64_t ntiles = (capacity + kBlock - 1) / kBlock;
     const unsigned nb = tile_grid(sl, ntiles);
     const uint32_t *order = sl.table ? nullptr : w.flagid;  // plain: order built with the grid
     const uint64_t bytes = uint64_t(w.lay.capacity) * 32u;
     if (bytes <= 0xFFFFFFE0ull) {
         if (crowded)
-            launch_mech_rec(s, sl, ntiles, nb, precision, order,
-                            RecBuf4{static_cast<void *>(w.pos4), static_cast<void *>(w.pos4f), uint32_t(bytes)}, w, st);
+            launch_mech_traced(s, sl, ntiles, nb, precision, order,
+                               RecBuf4{static_cast<void *>(w.pos4), static_cast<void *>(w.pos4f), uint32_t(bytes)}, w,
+                               trace, st);
         else
-            launch_mech_rec(s, sl, ntiles, nb, precision, order,
-                            RecBuf{static_cast<void *>(w.pos4), static_cast<void *>(w.pos8), uint32_t(bytes)}, w, st);
+            launch_mech_traced(s, sl, ntiles, nb, precision, order,
+                               RecBuf{static_cast<void *>(w.pos4), static_cast<void *>(w.pos8), uint32_t(bytes)}, w,
+                               trace, st);
     } else if (crowded) {
-        launch_mech_rec(s, sl, ntiles, nb, precision, order, RecGlobal4{w.pos4, w.pos4f}, w, st);
+        launch_mech_traced(s, sl, ntiles, nb, precision, order, RecGlobal4{w.pos4, w.pos4f}, w, trace, st);
     } else {
-        launch_mech_rec(s, sl, ntiles, nb, precision, order, RecGlobal{w.pos4, w.pos8}, w, st);
+        launch_mech_traced(s, sl, ntiles, nb, precision, order, RecGlobal{w.pos4, w.pos8}, w, trace, st);
     }
+    if (!sl.table) hipLaunchKernelGGL(k_grid_consume, dim3(1), dim3(64), 0, st, w.grid);
 }
 
 void launch_contacts_mech(int f32, const Slots &sl, const Ws &w, uint32_t *counts, const int64_t *offsets,

@@ -39,6 +39,12 @@ struct GenArgs {
     uint64_t seed, salt;
 };
 
+// Per-agent contact record of a traced mechanical step (test hook): count and order-sensitive
+// hash of the contacts the step adds, indexed like the step's outputs.
+struct TraceOut {
+    uint32_t *counts, *hashes;
+};
+
 struct ContactArgs {
     int32_t mode;       // 0: mechanical FP64, 1: mechanical FP32, 2: periodic radius
     double L, half, r2;
@@ -53,8 +59,9 @@ void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, bool
 // Exclusive scan of in[0, len) into out[0, len] (len read on the device).
 void launch_scan(uint32_t *in, uint32_t *out, const int64_t *len_ptr, int64_t max_len, const Ws &w,
                  int zero_in, bool prepare, hipStream_t st);
+// trace: NULL for the step itself; else the traced instantiation of the same kernels.
 void launch_mech(const bdm_soa &s, const Slots &sl, int64_t capacity, int precision, bool crowded, const Ws &w,
-                 hipStream_t st);
+                 hipStream_t st, const TraceOut *trace = nullptr);
 void launch_sir(const bdm_soa &s, const Slots &sl, int64_t capacity, const SirArgs &a, const Ws &w,
                 hipStream_t st);
 void launch_grow_divide(const bdm_soa &s, const Slots &sl, int64_t capacity, const DivArgs &a, const Ws &w,

@@ -123,10 +123,11 @@ class ServeStats:
     wall: float = 0.0
     batch_steps: int = 0
     max_concurrent: int = 0
+    failed: list = field(default_factory=list)  # (request id, status bits) of failed requests
 
     def summary(self):
         lat = np.array(self.latencies) if self.latencies else np.zeros(1)
-        return dict(requests=len(self.latencies), agent_updates=self.agent_updates,
+        return dict(requests=len(self.latencies), failed=len(self.failed), agent_updates=self.agent_updates,
                     wall_s=self.wall, agent_updates_per_s=self.agent_updates / max(self.wall, 1e-12),
                     p50_latency_s=float(np.percentile(lat, 50)), p99_latency_s=float(np.percentile(lat, 99)),
                     batch_steps=self.batch_steps, max_concurrent=self.max_concurrent)
@@ -136,7 +137,7 @@ class Server:
     """Packed population of `slots` simulation slots with `capacity` agents in total."""
 
     def __init__(self, capacity: int, max_boxes: int, slots: int = 64, box=D_HI,
-                 use_graph: bool = True, keep_results: bool = False):
+                 use_graph: bool = True, keep_results=False):
         import torch
 
         from . import bdm
@@ -152,6 +153,7 @@ class Server:
         self.stream = torch.cuda.Stream()
         self.graph = None
         self.use_graph = use_graph
+        # True keeps every result on the host; a set of request ids keeps only those
         self.keep_results = keep_results
         self.results: dict[int, dict] = {}
 
@@ -205,16 +207,21 @@ class Server:
             self.batch.step(stream=self.stream)
 
     def retire(self, slot: int):
+        """Read a finished request back and free its slot.  Returns (request, status bits): a
+        slot whose grid build or step met a device condition (bits != 0) did not do its work,
+        and its result must not count."""
         r = self.running.pop(slot)
         with self.torch.cuda.stream(self.stream):
             out = self.batch.read_slot(slot, r.agent_off, r.req.n, keys=("x", "y", "z"))
+            flags, _ = self.batch.slot_status(slot, stream=self.stream)
             self.batch.clear_slot(slot, r.agent_off, r.req.n, stream=self.stream)
         self.agents.release(r.agent_off, r.agent_len)
         self.boxes.release(r.box_off, r.box_len)
         self.free_slots.append(slot)
-        if self.keep_results:
+        keep = self.keep_results
+        if keep is True or (keep and r.req.rid in keep):
             self.results[r.req.rid] = out
-        return r
+        return r, flags
 
     def run(self, trace, time_scale: float = 1.0) -> ServeStats:
         """Serve `trace` in real time (arrival times multiplied by time_scale)."""
@@ -248,7 +255,10 @@ class Server:
                 if r.left == 0:
                     done.append(slot)
             for slot in done:
-                r = self.retire(slot)  # reads results back: synchronises the stream
+                r, flags = self.retire(slot)  # reads results back: synchronises the stream
+                if flags:
+                    stats.failed.append((r.req.rid, flags))
+                    continue
                 stats.latencies.append(time.perf_counter() - t0 - r.req.arrival * time_scale)
                 stats.agent_updates += r.req.n * r.req.steps
         self.stream.synchronize()
@@ -256,9 +266,9 @@ class Server:
         return stats
 
 
-def run_plain(trace, time_scale: float = 1.0, box=D_HI, keep_results: bool = False):
-    """Serve the trace one request at a time with plain launches (FIFO, no batching); `box` as
-    for Server."""
+def run_plain(trace, time_scale: float = 1.0, box=D_HI, keep_results=False):
+    """Serve the trace one request at a time with plain launches (FIFO, no batching); `box` and
+    `keep_results` as for Server."""
     import torch
 
     from . import bdm
@@ -282,7 +292,11 @@ def run_plain(trace, time_scale: float = 1.0, box=D_HI, keep_results: bool = Fal
         dev = {k: torch.empty(r.n, dtype=torch.float64, device="cuda") for k in ("x", "y", "z")}
         bdm.read_agents(view, dev["x"], dev["y"], dev["z"])
         out = {k: v.cpu().numpy() for k, v in dev.items()}
-        if keep_results:
+        flags = bdm.status(pop.ws, clear=True)
+        if flags:
+            stats.failed.append((r.rid, flags))
+            continue
+        if keep_results is True or (keep_results and r.rid in keep_results):
             results[r.rid] = out
         stats.latencies.append(time.perf_counter() - t0 - r.arrival * time_scale)
         stats.agent_updates += r.n * r.steps

@@ -89,3 +89,22 @@ def reach_adversarial(pairs, b=12.0, seed=0):
     pos = np.array(xs)
     return dict(x=pos[:, 0].copy(), y=pos[:, 1].copy(), z=pos[:, 2].copy(), d=np.array(ds),
                 adh=np.full(len(ds), 0.4))
+
+
+def separated_pairs(npairs, d, separation, spacing=40.0, coincident=0, seed=0):
+    """Pairs of equal spheres (diameter d) whose centres lie exactly `separation` apart along x,
+    y or z (axis-aligned, so the separation is exact in binary64), the pairs `spacing` apart on a
+    jittered lattice; then `coincident` pairs of spheres at one and the same centre."""
+    r = np.random.default_rng(seed)
+    k = int(np.ceil((npairs + coincident) ** (1.0 / 3.0)))
+    cells = np.stack(np.meshgrid(np.arange(k), np.arange(k), np.arange(k), indexing="ij"), -1)
+    cells = cells.reshape(-1, 3)[: npairs + coincident].astype(np.float64)
+    base = cells * spacing + np.round(r.uniform(0.0, 4.0, cells.shape) * 64.0) / 64.0
+    axis = r.integers(0, 3, npairs + coincident)
+    off = np.zeros_like(base)
+    off[np.arange(npairs), axis[:npairs]] = separation
+    a, b = base, base + off
+    pos = np.concatenate([a, b])
+    n = len(pos)
+    return dict(x=pos[:, 0].copy(), y=pos[:, 1].copy(), z=pos[:, 2].copy(), d=np.full(n, float(d)),
+                adh=np.full(n, 0.4))

@@ -175,6 +175,47 @@ def test_grid_explicit_box_and_flags():
     assert bdm.status(bad.ws) & bdm.FLAG_NONFINITE
 
 
+def test_grid_lattice_span_beyond_int32():
+    """Two agents 2^31 boxes apart along x (lattice coordinates -2^30 and 2^30 - 1, both inside
+    the device's coordinate range): the span does not fit int32 and far exceeds max_boxes, so
+    the build must fail with BDM_FLAG_BOXES and leave no valid grid, as the oracle refuses it."""
+    say("case: grid lattice span 2^31")
+    b = 10.0
+    s = dict(x=np.array([-(2.0 ** 30) * b + 5.0, (2.0 ** 30 - 1.0) * b + 5.0]), y=np.array([5.0, 5.0]),
+             z=np.array([5.0, 5.0]), d=np.array([b, b]), adh=np.array([0.4, 0.4]))
+    with pytest.raises(orc.OracleError) as e:
+        orc.grid(s["x"], s["y"], s["z"], s["d"], max_boxes=1 << 16)
+    assert e.value.rc == orc.ETOOMANYBOXES
+    pop = population(s, max_boxes=1 << 16)
+    bdm.grid_build(pop.soa, mech_p(), pop.ws)
+    assert bdm.status(pop.ws) & bdm.FLAG_BOXES
+    info = bdm.grid_info(pop.ws)
+    assert info["valid"] == 0 and info["n"] == 0
+
+
+def test_mech_step_refuses_a_foreign_or_used_grid():
+    """A mechanical step needs an open-space build of the same agents that no step has used:
+    after a periodic (SIR) build, or a second time after one build, it moves nothing and sets
+    BDM_FLAG_NOGRID."""
+    say("case: mech step after a periodic build / twice on one build")
+    s = inputs.uniform_cube(1000, 100.0, seed=9)
+    pop = population(s, state=True, max_boxes=1 << 16)
+    bdm.grid_build(pop.soa, bdm.params(box=20.0, periodic=1, L=100.0), pop.ws)
+    x0 = pop.t["x"][:1000].clone()
+    bdm.mech_step(pop.soa, mech_p(), pop.ws)
+    assert torch.equal(pop.t["x"][:1000], x0)
+    assert bdm.status(pop.ws, clear=True) == bdm.FLAG_NOGRID
+    bdm.grid_build(pop.soa, mech_p(), pop.ws)
+    bdm.mech_step(pop.soa, mech_p(), pop.ws)
+    assert bdm.status(pop.ws, clear=True) == 0
+    x1 = pop.t["x"][:1000].clone()
+    bdm.mech_step(pop.soa, mech_p(), pop.ws)
+    assert torch.equal(pop.t["x"][:1000], x1)
+    assert bdm.status(pop.ws, clear=True) == bdm.FLAG_NOGRID
+    bdm.sim_step(pop.soa, bdm.MODEL_MECH, mech_p(), 0, pop.ws)  # a build and a step: fine again
+    assert bdm.status(pop.ws) == 0
+
+
 def test_argument_validation():
     say("case: validation")
     pop = population(inputs.uniform_cube(100, 50.0, seed=1))

@@ -140,3 +140,19 @@ def test_grid_validation(orc):
 def test_grid_single_agent(orc):
     info, key, order, start = orc.grid([5.0], [-3.0], [1e6], [10.0])
     assert info["nboxes"] == 1 and key.tolist() == [0] and start.tolist() == [0, 1]
+
+
+def test_lattice_span_beyond_max_boxes_is_refused(orc):
+    """Two agents 2^31 boxes apart (lattice coordinates -2^30 and 2^30 - 1 at b = 10): the
+    lattice has 2^31 boxes along x, more than max_boxes, and the grid is refused."""
+    b = 10.0
+    x = np.array([-(2.0 ** 30) * b + 5.0, (2.0 ** 30 - 1.0) * b + 5.0])
+    yz = np.array([5.0, 5.0])
+    assert np.floor(x / b).tolist() == [-(2.0 ** 30), 2.0 ** 30 - 1.0]
+    with pytest.raises(orc.OracleError) as e:
+        orc.grid(x, yz, yz, np.array([b, b]), max_boxes=1 << 16)
+    assert e.value.rc == orc.ETOOMANYBOXES
+    # the same pair 2^16 - 1 boxes apart still fits exactly
+    x2 = np.array([5.0, (2.0 ** 16 - 1.0) * b + 5.0])
+    info, key, order, start = orc.grid(x2, yz, yz, np.array([b, b]), max_boxes=1 << 16)
+    assert info["dims"] == (1 << 16, 1, 1) and key.tolist() == [0, (1 << 16) - 1]
