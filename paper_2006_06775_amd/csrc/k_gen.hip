@@ -72,6 +72,8 @@ __device__ void clear_grid(GridDev *g) {
     g->scan_ticket = 0u;
     g->crowd_n = 0u;
     g->sorted_base = 0;
+    g->kind = kGridNone;
+    g->consumed = 0;
 }
 
 // Zero the grid records, the histogram and the scan tiles; empty the batch slot table.

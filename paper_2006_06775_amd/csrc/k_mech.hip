@@ -233,20 +233,33 @@ __device__ __forceinline__ bool maybe_touch(const float4 &a, const float4 &c, fl
     return d2 < __builtin_fmaf(s, s, slack);
 }
 
-// Conservative contact pre-test on the 8-byte records (units of b / 2^14, see pre8_axis).  Each
-// coordinate difference is within 1 + 2^-6 units of the true one and each stored radius at
-// least one unit above the true one, so a pair the exact law counts as a contact has a decoded
-// distance below r_i + r_j + 1.76 < R_i + R_j; binary32 holds the integer differences exactly,
-// and the one unit of slack covers the rounding of the squares and of either law's contact
-// test (binary32: about 2^-21 of r_i + r_j <= b, under 2^-7 units).
-__device__ __forceinline__ bool touch8(const uint2 &a, const uint2 &c) {
-    const int dx = int(int16_t(uint16_t(c.x - a.x)));
-    const int dy = int(c.x - (a.x & 0xFFFF0000u)) >> 16;
-    const int dz = int(int16_t(uint16_t(c.y - a.y)));
-    const float fx = float(dx), fy = float(dy), fz = float(dz);
-    const float d2 = __builtin_fmaf(fz, fz, __builtin_fmaf(fy, fy, fx * fx));
-    const float sr = float((a.y >> 16) + (c.y >> 16) + 1u);
-    return d2 < sr * sr;
+// The own pre-test record arranged for touch8i: the x|y word as stored, and the z field negated
+// modulo 2^16 beside the own radius, so that one packed 16-bit add gives (z_j - z_i, R_i + R_j).
+struct Own8 {
+    uint32_t xy, zr;
+};
+__device__ __forceinline__ Own8 own8(uint2 a) {
+    return Own8{a.x, ((0x10000u - (a.y & 0xFFFFu)) & 0xFFFFu) | (a.y & 0xFFFF0000u)};
+}
+
+// Conservative contact pre-test on the 8-byte records (units of b / 2^14, see pre8_axis), in
+// exact integer arithmetic.  Per axis the 16-bit fields
+// differ, modulo 2^16 and read as signed, by the offset in units (boxes within one of each other;
+// see pre8_axis), which is below 2^15 in magnitude; so the packed 16-bit differences, a signed
+// dot product of the (x, y) pair (below 2^31) and the z square (the sum below 3 * 2^30, exact as
+// an unsigned word) give the squared decoded distance exactly.  A pair the exact law counts as a
+// contact has a decoded distance below r_i + r_j + 1.76 units and each stored radius is at least
+// one unit above the true one, so the decoded distance is below R_i + R_j: no contact fails.
+typedef short bdm_s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short bdm_u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ bool touch8i(const Own8 &a, uint2 c) {
+    const bdm_s16x2 d = __builtin_bit_cast(bdm_s16x2, c.x) - __builtin_bit_cast(bdm_s16x2, a.xy);
+    const int dxy = __builtin_amdgcn_sdot2(d, d, 0, false);
+    const uint32_t zr = __builtin_bit_cast(uint32_t, __builtin_bit_cast(bdm_u16x2, c.y) + __builtin_bit_cast(bdm_u16x2, a.zr));
+    const int dz = int(int16_t(uint16_t(zr)));
+    const uint32_t d2 = uint32_t(dxy) + uint32_t(dz * dz);
+    const uint32_t R = zr >> 16;
+    return d2 < R * R;
 }
 
 // Packed-record loads by candidate offset u in units of kUnit.  RecBuf: raw buffer resources
@@ -272,7 +285,7 @@ struct RecBuf {
         const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base8, 0, bytes / 4u, 0x00020000);
         return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, u / 2u, 0, 0));
     }
-    static __device__ __forceinline__ bool touch(const uint2 &a, const uint2 &c, float) { return touch8(a, c); }
+    static __device__ __forceinline__ bool touch(const uint2 &a, const uint2 &c, float) { return touch8i(own8(a), c); }
 };
 // The binary32 copies instead (the crowded kernel: its walk is bound by VALU, not by memory).
 struct RecBuf4 {
@@ -305,7 +318,7 @@ struct RecGlobal {
     const uint2 *__restrict__ p8;
     __device__ __forceinline__ double4 full(uint32_t u) const { return p[u]; }
     __device__ __forceinline__ uint2 pre(uint32_t u) const { return p8[u]; }
-    static __device__ __forceinline__ bool touch(const uint2 &a, const uint2 &c, float) { return touch8(a, c); }
+    static __device__ __forceinline__ bool touch(const uint2 &a, const uint2 &c, float) { return touch8i(own8(a), c); }
 };
 struct RecGlobal4 {
     static constexpr uint32_t kUnit = 1;
@@ -377,25 +390,27 @@ __device__ __forceinline__ void wave_lds_sync() {
 // per lane, instead of each lane walking its own queue while the lanes with shorter queues idle.
 // Each lane then adds the terms of its own pairs in its queue order, so its sum is the one its
 // own walk would give.  The run table is no longer needed here; in the wavefront's columns,
-// rows 0-2 hold a round's terms, rows 3 and 6-8 every lane's own record (r, x, y, z), rows 4-5
-// the layout (lane | slot << 6 per pair, at most 512; bit 15 set once the pair is a contact).
-// Every lane of the wavefront must take part.
+// The scratch is 9 rows of 64 8-byte entries, one per lane of the wavefront: entry (row, lane)
+// at scr[row * stride + cbase + lane]; rows 0-2 hold a round's terms, rows 3 and 6-8 every
+// lane's own record (r, x, y, z), rows 4-5 the layout (lane | slot << 6 per pair, at most 512;
+// bit 15 set once the pair is a contact).  Every lane of the wavefront must take part.
 template <bool F32, int kQ, class Rec, class Tr>
 __device__ __forceinline__ void exact_packed(const SlotDev &S, const double4 &p, const Rec &rec, uint32_t qn,
-                                             uint2 (*s_run)[kBlock], const uint32_t (*s_q)[kBlock], int t,
-                                             double &fx, double &fy, double &fz, Tr &tr) {
+                                             uint2 *scr, int stride, int cbase, const uint32_t (*s_q)[kBlock],
+                                             int t, double &fx, double &fy, double &fz, Tr &tr) {
     static_assert(kQ <= 8, "the layout holds 64 lanes x 8 slots");
     const int lane = t & 63, w0 = t - lane;
     const uint32_t incl = wave_incl_scan(qn), excl = incl - qn;
     const uint32_t total = uint32_t(__shfl(int(incl), 63, 64));
     if (total == 0) return;
+    auto at = [&](int row, int c) -> uint2 & { return scr[row * stride + cbase + c]; };
     auto layout = [&](uint32_t e) -> uint16_t * {
-        return reinterpret_cast<uint16_t *>(&s_run[4 + (e >> 8)][w0]) + (e & 255u);
+        return reinterpret_cast<uint16_t *>(&at(4 + int(e >> 8), 0)) + (e & 255u);
     };
-    s_run[3][t] = __builtin_bit_cast(uint2, p.w);
-    s_run[6][t] = __builtin_bit_cast(uint2, p.x);
-    s_run[7][t] = __builtin_bit_cast(uint2, p.y);
-    s_run[8][t] = __builtin_bit_cast(uint2, p.z);
+    at(3, lane) = __builtin_bit_cast(uint2, p.w);
+    at(6, lane) = __builtin_bit_cast(uint2, p.x);
+    at(7, lane) = __builtin_bit_cast(uint2, p.y);
+    at(8, lane) = __builtin_bit_cast(uint2, p.z);
     for (uint32_t k = 0; k < qn; ++k) *layout(excl + k) = uint16_t(uint32_t(lane) | (k << 6));
     for (uint32_t base = 0; base < total; base += 64) {
         wave_lds_sync();
@@ -405,24 +420,24 @@ __device__ __forceinline__ void exact_packed(const SlotDev &S, const double4 &p,
             uint16_t *le = layout(e);
             const uint32_t m = *le, o = m & 63u;
             const double4 po = make_double4(
-                __builtin_bit_cast(double, s_run[6][w0 + o]), __builtin_bit_cast(double, s_run[7][w0 + o]),
-                __builtin_bit_cast(double, s_run[8][w0 + o]), __builtin_bit_cast(double, s_run[3][w0 + o]));
+                __builtin_bit_cast(double, at(6, int(o))), __builtin_bit_cast(double, at(7, int(o))),
+                __builtin_bit_cast(double, at(8, int(o))), __builtin_bit_cast(double, at(3, int(o))));
             const double4 r = rec.full(s_q[m >> 6][w0 + o]);
             if (pair_term<F32, Tr::kOn>(po, po.x - r.x, po.y - r.y, po.z - r.z, r.w, float(po.w), S, tx, ty, tz))
                 *le = uint16_t(m | 0x8000u);
         }
-        s_run[0][t] = __builtin_bit_cast(uint2, tx);
-        s_run[1][t] = __builtin_bit_cast(uint2, ty);
-        s_run[2][t] = __builtin_bit_cast(uint2, tz);
+        at(0, lane) = __builtin_bit_cast(uint2, tx);
+        at(1, lane) = __builtin_bit_cast(uint2, ty);
+        at(2, lane) = __builtin_bit_cast(uint2, tz);
         wave_lds_sync();
         const uint32_t lo = excl > base ? excl : base, hi = incl < base + 64u ? incl : base + 64u;
         for (uint32_t f = lo; f < hi; ++f) {
             const uint32_t m = *layout(f);
             if (m & 0x8000u) {
-                const int col = w0 + int(f - base);
-                fx = fx + __builtin_bit_cast(double, s_run[0][col]);
-                fy = fy + __builtin_bit_cast(double, s_run[1][col]);
-                fz = fz + __builtin_bit_cast(double, s_run[2][col]);
+                const int c = int(f - base);
+                fx = fx + __builtin_bit_cast(double, at(0, c));
+                fy = fy + __builtin_bit_cast(double, at(1, c));
+                fz = fz + __builtin_bit_cast(double, at(2, c));
                 if constexpr (Tr::kOn) tr.hit(s_q[(m >> 6) & 7u][t]);
             }
         }
@@ -566,7 +581,7 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
     }
     pre_final();
     if constexpr (kSync)
-        exact_packed<F32, kQ>(S, p, rec, qn, s_run, s_q, t, fx, fy, fz, tr);
+        exact_packed<F32, kQ>(S, p, rec, qn, &s_run[0][0], kBlock, t - (t & 63), s_q, t, fx, fy, fz, tr);
     else
         flush();
 }

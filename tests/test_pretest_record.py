@@ -7,9 +7,8 @@ The record, per axis: the box index c (floor of the coordinate over the box edge
 rounds it) mod 4 in the top 2 of 16 bits, above the offset within the box in units of b / 2^14,
 floor((v * fl(1/b) - c) * 2^14) clamped to [0, 2^14 - 1]; the radius in the same units, rounded
 up plus one.  The test reads each axis difference modulo 2^16 as a signed 16-bit value and
-compares the binary32 squared distance (one product, two fused multiply-adds) with
-(R_i + R_j + 1)^2.  This is a model of the definition, not the kernel's code; the GPU parity
-tests check the kernel bit for bit.
+compares the exact integer squared distance with (R_i + R_j)^2.  This is a model of the
+definition, not the kernel's code; the GPU parity tests check the kernel bit for bit.
 
 Pairs sit at the edge of contact (distance (r_i + r_j)(1 + e), |e| <= 1e-6 and a few at 0),
 in boxes at lattice coordinates up to 2^30, with box edges from the largest diameter to five
@@ -44,13 +43,14 @@ def record_test(vi, vj, ri, rj, b):
     assert np.all(np.abs(cj - ci) <= 1), "a candidate's box is within one of the agent's"
     ai = encode_axis(vi, ci, inv_b[:, None])
     aj = encode_axis(vj, cj, inv_b[:, None])
-    d = signed16(aj - ai).astype(np.float32)
-    f32 = np.float32
-    t = (d[:, 0].astype(np.float64) ** 2).astype(f32)
-    t = (d[:, 1].astype(np.float64) ** 2 + t.astype(np.float64)).astype(f32)
-    t = (d[:, 2].astype(np.float64) ** 2 + t.astype(np.float64)).astype(f32)
-    sr = (encode_radius(ri, inv_b) + encode_radius(rj, inv_b) + 1).astype(f32)
-    return t < sr * sr
+    d = signed16(aj - ai)
+    # every field difference is below 2^15 in magnitude, so the kernel's packed 16-bit
+    # arithmetic (x, y as a signed dot product below 2^31, z added as an unsigned word) is exact
+    assert np.all(np.abs(d) < (1 << 15))
+    d2 = (d * d).sum(axis=1)
+    assert np.all(d2 < (3 << 30))
+    sr = encode_radius(ri, inv_b) + encode_radius(rj, inv_b)
+    return d2 < sr * sr
 
 
 def edge_pairs(n, rng, rel, gap=0.0):
