@@ -240,6 +240,23 @@ int bdm_contacts(const bdm_workspace *ws, const bdm_params *params, uint32_t *co
 int bdm_sim_step_traced(const bdm_soa *soa, int32_t model, const bdm_params *params, int64_t step,
                         const bdm_workspace *ws, uint32_t *counts, uint32_t *hashes, void *stream);
 
+/* For callers that cannot allocate device memory: code under stream or graph capture, tight
+ * serving loops, harnesses that forbid allocation.  The same step as bdm_sim_step (any model,
+ * same arguments, same results bit for bit) with the library's own static device array of
+ * BDM_NOALLOC_SCRATCH_BYTES as the workspace, one copy per device that runs it, held until the
+ * process ends; no memory is allocated or freed in the call.  soa->capacity and max_boxes (the
+ * grid boxes the workspace must hold, as for bdm_workspace_bytes) must fit the array:
+ * bdm_workspace_bytes(capacity, max_boxes) <= BDM_NOALLOC_SCRATCH_BYTES, else BDM_ENOWS
+ * (synchronous, nothing launched).  The array is cleared at the start of every call, so nothing
+ * carries over between calls (no grid for a later bdm_mech_step, no S/I/R counts to read).
+ * flags (device, one uint32, may be NULL) receives the step's sticky status bits (BDM_FLAG_*)
+ * when the step completes on the stream.  Calls on one device share its array: calls that
+ * overlap in time on one device (other streams, other threads) race and are not allowed.
+ * Errors: as bdm_sim_step; BDM_ENOWS as above; BDM_ENODEV, BDM_EHIP from the device lookup. */
+#define BDM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int bdm_sim_step_noalloc(const bdm_soa *soa, int32_t model, const bdm_params *params, int64_t step,
+                         int64_t max_boxes, uint32_t *flags, void *stream);
+
 /* ---- batched form --------------------------------------------------------------------------
  * Callers: many independent simulations of uneven sizes stepped together (one launch per
  * phase for all of them, capturable in a graph).  The per-slot work is the plain mechanical

@@ -28,7 +28,7 @@ GEN_CUBE, GEN_BALL, GEN_SIR = 0, 1, 2
 SYMBOLS = (
     "bdm_workspace_bytes", "bdm_workspace_init", "bdm_generate", "bdm_grid_build",
     "bdm_mech_step", "bdm_sim_step", "bdm_read_agents", "bdm_status", "bdm_sir_counts",
-    "bdm_grid_info", "bdm_grid_export", "bdm_contacts", "bdm_sim_step_traced",
+    "bdm_grid_info", "bdm_grid_export", "bdm_contacts", "bdm_sim_step_traced", "bdm_sim_step_noalloc",
     "bdm_batch_workspace_bytes", "bdm_batch_init", "bdm_batch_set_slot", "bdm_batch_clear_slot",
     "bdm_batch_step", "bdm_batch_step_traced", "bdm_batch_slot_status", "bdm_fp_probe",
     "bdm_strerror", "bdm_last_error",
@@ -103,6 +103,7 @@ def _load():
         "bdm_grid_export": ([P, P, P, P, P], C.c_int),
         "bdm_contacts": ([P, P, P, P, P, P], C.c_int),
         "bdm_sim_step_traced": ([P, C.c_int32, P, C.c_int64, P, P, P, P], C.c_int),
+        "bdm_sim_step_noalloc": ([P, C.c_int32, P, C.c_int64, C.c_int64, P, P], C.c_int),
         "bdm_batch_step_traced": ([P, P, P, P, P], C.c_int),
         "bdm_fp_probe": ([P, P, C.c_int64, P, P, P, P, P], C.c_int),
         "bdm_batch_workspace_bytes": ([C.c_int64, C.c_int64, C.c_int32], C.c_size_t),
@@ -318,6 +319,17 @@ def sim_step_traced(soa: Soa, model: int, p: Params, step: int, ws: Workspace, c
     """sim_step through the traced kernels; counts/hashes: device int32 tensors of capacity."""
     _check(_lib.bdm_sim_step_traced(_ref(soa), model, _ref(p), step, _ref(ws), _ptr(counts),
                                     _ptr(hashes), _stream(stream)), "sim_step_traced")
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def sim_step_noalloc(soa: Soa, model: int, p: Params, step: int, max_boxes: int, flags=None,
+                     stream=None):
+    """sim_step with the library's static device scratch as the workspace; flags: optional device
+    int32 tensor of one element that receives the status bits."""
+    _check(_lib.bdm_sim_step_noalloc(_ref(soa), model, _ref(p), step, max_boxes, _ptr(flags),
+                                     _stream(stream)), "sim_step_noalloc")
 
 
 def fp_probe(a: torch.Tensor, b: torch.Tensor, stream=None):

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "kernels.hpp"
@@ -331,6 +332,80 @@ int bdm_sim_step_traced(const bdm_soa *soa, int32_t model, const bdm_params *par
     if (!counts || !hashes) return fail(BDM_EINVAL, "counts and hashes are required");
     const bdm::TraceOut t{counts, hashes};
     return sim_step(soa, model, params, step, ws, &t, stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// Step without a caller workspace
+// ---------------------------------------------------------------------------------------------
+// The workspace of bdm_sim_step_noalloc: a static device array, one copy on every device that
+// runs the entry point, held until the process ends.  In host code `scratch` only names the
+// symbol; its device address on the current device comes from hipGetSymbolAddress, looked up
+// once per device and kept in g_scratch_ptr, and only that address is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[BDM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the device's first call).
+int scratch_address(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(BDM_ENODEV, "no HIP device");
+    if (dev < 0 || dev >= kMaxDevices) return fail(BDM_ENODEV, "device index %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int rc = check_device();
+        if (rc) return rc;
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(BDM_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return BDM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bdm_sim_step_noalloc(const bdm_soa *soa, int32_t model, const bdm_params *params, int64_t step,
+                         int64_t max_boxes, uint32_t *flags, void *stream) {
+    g_last_error.clear();
+    if (!soa) return fail(BDM_EINVAL, "soa is NULL");
+    bdm::WsLayout lay;
+    if (!bdm::ws_layout(soa->capacity, max_boxes, 0, &lay))
+        return fail(BDM_EINVAL, "capacity %lld / max_boxes %lld out of range", (long long)soa->capacity,
+                    (long long)max_boxes);
+    if (lay.total > size_t(BDM_NOALLOC_SCRATCH_BYTES))
+        return fail(BDM_ENOWS, "capacity %lld and max_boxes %lld need %zu bytes of workspace; the static scratch "
+                    "holds %zu", (long long)soa->capacity, (long long)max_boxes, lay.total,
+                    size_t(BDM_NOALLOC_SCRATCH_BYTES));
+    void *ptr = nullptr;
+    int rc = scratch_address(&ptr);
+    if (rc) return rc;
+    const bdm_workspace ws{ptr, size_t(BDM_NOALLOC_SCRATCH_BYTES), soa->capacity, max_boxes};
+    bdm::Ws w;
+    rc = get_ws(&ws, &w);
+    if (rc) return rc;
+    hipStream_t st = as_stream(stream);
+    // the previous call's contents stay in the array: start from a cleared grid, histogram and
+    // tile order, as bdm_workspace_init leaves a workspace
+    bdm::launch_ws_init(w, st);
+    rc = hip_check("noalloc workspace init launch");
+    if (rc) return rc;
+    rc = sim_step(soa, model, params, step, &ws, nullptr, stream);
+    if (rc) return rc;
+    if (flags) {
+        bdm::launch_copy_flags(w, flags, st);
+        return hip_check("noalloc flags launch");
+    }
+    return BDM_OK;
 }
 
 int bdm_read_agents(const bdm_soa *soa, double *out_x, double *out_y, double *out_z, double *out_diam,

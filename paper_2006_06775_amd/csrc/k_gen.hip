@@ -174,6 +174,15 @@ void launch_set_slot(const Ws &w, int32_t slot, const SlotDev &rec, int64_t firs
                        w.grid, slot, rec, first_tile, ntile, first_bucket, nbucket, value);
 }
 
+// The status bits of a plain workspace's grid record into a caller's device word.
+__global__ void k_copy_flags(const GridDev *g, uint32_t *out) {
+    if (threadIdx.x == 0) out[0] = g->flags;
+}
+
+void launch_copy_flags(const Ws &w, uint32_t *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy_flags, dim3(1), dim3(64), 0, st, w.grid, out);
+}
+
 void launch_batch_advance(const Ws &w, hipStream_t st) {
     hipLaunchKernelGGL(k_batch_advance, dim3(nblocks(w.lay.nslots, 0)), dim3(kBlock), 0, st, w.slots,
                        w.lay.nslots);

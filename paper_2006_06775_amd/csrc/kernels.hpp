@@ -78,5 +78,6 @@ void launch_generate(const bdm_soa &s, const GenArgs &a, hipStream_t st);
 void launch_fp_probe(const double *a, const double *b, int64_t n, double *os, double *od, float *osf,
                      float *odf, hipStream_t st);
 void launch_ws_init(const Ws &w, hipStream_t st);
+void launch_copy_flags(const Ws &w, uint32_t *out, hipStream_t st);
 
 }  // namespace bdm

@@ -69,3 +69,9 @@ def test_validation_without_gpu():
     assert lib.bdm_generate(C.byref(soa), C.byref(g), None) == bdm.EINVAL
     assert lib.bdm_strerror(bdm.ENOWS) == b"workspace missing or too small"
     assert lib.bdm_fp_probe(None, None, -1, None, None, None, None, None) == bdm.EINVAL
+    # the static-scratch step refuses a population beyond its array before touching a device
+    big = bdm.Soa(1 << 22, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 0)
+    p = bdm.params()
+    assert lib.bdm_sim_step_noalloc(C.byref(big), 0, C.byref(p), 0, 1 << 20, None, None) == bdm.ENOWS
+    assert b"static scratch" in lib.bdm_last_error()
+    assert bdm.workspace_bytes(1 << 22, 1 << 20) > bdm.NOALLOC_SCRATCH_BYTES
