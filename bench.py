@@ -86,6 +86,35 @@ def run_variant(bdm, torch, n, L, steps, warmup, force_bits):
     return dict(wall=wall, grid_ms=grid_ms, mech_ms=mech_ms, flags=flags, info=info, pop=pop)
 
 
+def stationary_skip(bdm, torch, n, L, relax=24, steps=20, dt=0.3):
+    """The stationary-region skip (paper Sec. 2.3 (iv)) on the mechanics workload as it relaxes:
+    dt 0.3 (30 times the benchmark's), `relax` steps, then `steps` timed steps, once without and
+    once with the skip, from the same seed; the two end states must be bit-identical."""
+    out, ends = {}, {}
+    for skip in (0, 1):
+        pop = bdm.Population(n, bdm.box_count_hint(L, 11.9, 3))
+        bdm.generate(pop.soa, bdm.gen(bdm.GEN_CUBE, n, L, 8.0, 12.0, 0.4, seed=0))
+        p = bdm.params(k=2.0, gamma=1.0, dt=dt, max_disp=3.0, box=0.0, force_bits=64, skip_static=skip)
+        for step in range(relax):
+            bdm.sim_step(pop.soa, bdm.MODEL_MECH, p, step, pop.ws)
+
+        def one(step):
+            bdm.sim_step(pop.soa, bdm.MODEL_MECH, p, relax + step, pop.ws)
+        t = timed_steps(torch, one, steps)
+        info = bdm.grid_info(pop.ws)
+        out["skip" if skip else "plain"] = dict(ms_per_step=round(t * 1e3 / steps, 4),
+                                                agent_updates_per_s=n * steps / t,
+                                                skipped_last_step=info["skipped"], flags=info["flags"])
+        ends[skip] = pop.read(("x", "y", "z", "fx", "fy", "fz"))
+        del pop
+        torch.cuda.empty_cache()
+    same = all(np.array_equal(ends[0][k].view(np.uint64), ends[1][k].view(np.uint64)) for k in ends[0])
+    out.update(dt=dt, relax_steps=relax, timed_steps=steps, bit_identical=same,
+               speedup=out["plain"]["ms_per_step"] / out["skip"]["ms_per_step"],
+               skipped_fraction_last_step=out["skip"]["skipped_last_step"] / n)
+    return out
+
+
 def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
@@ -125,8 +154,8 @@ def serving(args):
 
     from paper_2006_06775_amd import serve, tune
     plan = tune.plan()  # box edge per request size, measured on this device
-    per_agent = 68 + 93 + 4
-    cap = int(args.serve_budget_gib * (1 << 30) / (per_agent + (4 + 12 / 64) * 1.6))
+    per_agent = 68 + 118 + 4
+    cap = int(args.serve_budget_gib * (1 << 30) / (per_agent + (5 + 12 / 64) * 1.6))
     boxes = int(cap * 1.6)
     slots = 64
     # closed-system calibration: every request present at t = 0
@@ -332,6 +361,7 @@ def main():
     del r64["pop"]
     torch.cuda.empty_cache()
 
+    skip = stationary_skip(bdm, torch, n, L)
     served = None if args.no_serve else serving(args)
     other = None if args.no_workloads else workloads()
     copy_gbps = copy_bandwidth(torch)
@@ -357,6 +387,7 @@ def main():
         "mech_step_only_agent_updates_per_s": n / (r64["mech_ms"] * 1e-3),
         "roofline": roofline,
         "fp32_forces": fp32,
+        "stationary_skip": skip,
         "served_stream": served,
         "other_workloads": other,
         "copy_kernel_GBps": round(copy_gbps, 1),

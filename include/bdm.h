@@ -91,7 +91,20 @@ typedef struct bdm_params {
     double div_d;          /* spheroid: division threshold diameter */
     double half_cbrt;      /* spheroid: daughter diameter factor (cube root of 1/2) */
     uint64_t seed, salt;   /* Philox4x64-10 key */
+    int32_t skip_static;   /* 1: skip agents in stationary regions (mechanical steps; see below) */
 } bdm_params;
+
+/* Stationary regions [paper Sec. 2.3 (iv): detect stationary regions and skip their expensive
+ * collision detection].  With skip_static = 1 a plain mechanical step (bdm_grid_build +
+ * bdm_mech_step, or bdm_sim_step with BDM_MODEL_MECH) skips the neighbour walk of every agent
+ * whose result is known to equal the previous step's: the previous step was also a skip_static
+ * step of the same agents on the same workspace, the lattice (box edge, origin, dims) is
+ * unchanged, the agent did not move in it, and no agent moved out of or into any box of its
+ * neighbourhood that can hold a sphere touching it.  Such an agent keeps its previous force
+ * (so it is gated again) and its position, bit for bit: results are identical with and without
+ * skipping.  Precondition: between two skip_static steps the agents change only through the
+ * library's mechanical steps (after bdm_generate or any other change, take one step with
+ * skip_static = 0, or re-initialise the workspace).  The batched and spheroid steps ignore it. */
 
 /* Seeded initial state. */
 typedef struct bdm_gen {
@@ -123,6 +136,7 @@ typedef struct bdm_grid_desc {
     int64_t n;             /* agents binned */
     int32_t valid;         /* 1 when the last build succeeded */
     uint32_t flags;        /* sticky BDM_FLAG_* bits */
+    int64_t skipped;       /* agents whose walk the last skip_static mechanical step skipped */
 } bdm_grid_desc;
 
 /* A batch: many independent mechanical simulations packed into one population.  Slot s owns

@@ -59,7 +59,7 @@ class Params(C.Structure):
                 ("periodic", C.c_int32), ("L", C.c_double), ("r_inf", C.c_double),
                 ("p_inf", C.c_double), ("p_rec", C.c_double), ("walk", C.c_double),
                 ("grow", C.c_double), ("div_d", C.c_double), ("half_cbrt", C.c_double),
-                ("seed", C.c_uint64), ("salt", C.c_uint64)]
+                ("seed", C.c_uint64), ("salt", C.c_uint64), ("skip_static", C.c_int32)]
 
 
 class Gen(C.Structure):
@@ -81,7 +81,7 @@ class BatchRec(C.Structure):
 class GridDesc(C.Structure):
     _fields_ = [("b", C.c_double), ("cmin", C.c_int32 * 3), ("dims", C.c_int32 * 3),
                 ("nboxes", C.c_int64), ("n", C.c_int64), ("valid", C.c_int32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("skipped", C.c_int64)]
 
 
 def _load():
@@ -153,9 +153,9 @@ def _ref(s):
 # ---------------------------------------------------------------------------------------------
 def params(k=2.0, gamma=1.0, dt=0.01, max_disp=3.0, box=0.0, force_bits=64, periodic=0, L=0.0,
            r_inf=0.0, p_inf=0.0, p_rec=0.0, walk=0.0, grow=1.05 ** (1.0 / 3.0), div_d=14.0,
-           half_cbrt=0.5 ** (1.0 / 3.0), seed=0, salt=0) -> Params:
+           half_cbrt=0.5 ** (1.0 / 3.0), seed=0, salt=0, skip_static=0) -> Params:
     return Params(k, gamma, dt, max_disp, box, force_bits, periodic, L, r_inf, p_inf, p_rec,
-                  walk, grow, div_d, half_cbrt, seed, salt)
+                  walk, grow, div_d, half_cbrt, seed, salt, skip_static)
 
 
 def gen(kind=GEN_CUBE, n=0, L=200.0, dlo=10.0, dhi=15.0, adh=0.4, n_infected=0, seed=0,
@@ -280,7 +280,7 @@ def grid_info(ws: Workspace, stream=None) -> dict:
     d = GridDesc()
     _check(_lib.bdm_grid_info(_ref(ws), C.byref(d), _stream(stream)), "grid_info")
     return dict(b=d.b, cmin=tuple(d.cmin), dims=tuple(d.dims), nboxes=d.nboxes, n=d.n,
-                valid=d.valid, flags=d.flags)
+                valid=d.valid, flags=d.flags, skipped=d.skipped)
 
 
 def grid_export(ws: Workspace, stream=None):

@@ -84,6 +84,13 @@ int check_soa(const bdm_soa *s, int64_t ws_capacity, bool need_sphere, bool need
     return BDM_OK;
 }
 
+// The stationary skip carries each agent's last force, so the steps that use it need them.
+int check_skip(const bdm_soa *s, const bdm_params *p) {
+    if (p->skip_static == 1 && !p->periodic && (!s->fx || !s->fy || !s->fz))
+        return fail(BDM_EINVAL, "skip_static needs the force arrays fx, fy, fz");
+    return BDM_OK;
+}
+
 int check_mech_params(const bdm_params *p) {
     if (!p) return fail(BDM_EINVAL, "params is NULL");
     if (!(p->dt > 0.0) || !is_fin(p->dt)) return fail(BDM_EINVAL, "dt must be > 0");
@@ -92,6 +99,7 @@ int check_mech_params(const bdm_params *p) {
     if (p->force_bits != 64 && p->force_bits != 32) return fail(BDM_EINVAL, "force_bits must be 32 or 64");
     if (!is_fin(p->box)) return fail(BDM_EINVAL, "box must be finite");
     if (p->periodic) return fail(BDM_EINVAL, "the mechanical step runs in open space (periodic = 0)");
+    if (p->skip_static != 0 && p->skip_static != 1) return fail(BDM_EINVAL, "skip_static must be 0 or 1");
     return BDM_OK;
 }
 
@@ -127,6 +135,7 @@ bdm::SlotDev slot_record(const bdm_params *p, int64_t agent_off, int64_t capacit
     r.periodic = p->periodic ? 1 : 0;
     r.nb = 0;
     r.has_d = has_d ? 1 : 0;
+    r.skip = p->skip_static == 1 ? 1 : 0;
     return r;
 }
 
@@ -237,6 +246,9 @@ int bdm_grid_build(const bdm_soa *soa, const bdm_params *params, const bdm_works
     rc = check_soa(soa, w.lay.capacity, false, false);
     if (rc) return rc;
     if (!is_fin(params->box)) return fail(BDM_EINVAL, "box must be finite");
+    if (params->skip_static != 0 && params->skip_static != 1) return fail(BDM_EINVAL, "skip_static must be 0 or 1");
+    rc = check_skip(soa, params);
+    if (rc) return rc;
     return plain_grid(soa, params, params->periodic != 0, w, as_stream(stream), nullptr);
 }
 
@@ -248,6 +260,8 @@ int bdm_mech_step(const bdm_soa *soa, const bdm_params *params, const bdm_worksp
     rc = check_soa(soa, w.lay.capacity, true, false);
     if (rc) return rc;
     rc = check_mech_params(params);
+    if (rc) return rc;
+    rc = check_skip(soa, params);
     if (rc) return rc;
     const bdm::SlotDev rec = slot_record(params, 0, soa->capacity, 0, w.lay.max_boxes, 1, true);
     bdm::launch_mech(*soa, plain_slots(w, rec), soa->capacity, params->force_bits, false, w, as_stream(stream));
@@ -274,7 +288,10 @@ int sim_step(const bdm_soa *soa, int32_t model, const bdm_params *params, int64_
         if (rc) return rc;
         rc = check_mech_params(params);
         if (rc) return rc;
-        const bdm::SlotDev rec = slot_record(params, 0, soa->capacity, 0, w.lay.max_boxes, 1, true);
+        bdm::SlotDev rec = slot_record(params, 0, soa->capacity, 0, w.lay.max_boxes, 1, true);
+        if (model == BDM_MODEL_SPHEROID) rec.skip = 0;  // (diameters change every step)
+        rc = check_skip(soa, params);
+        if (rc && rec.skip) return rc;
         if (model == BDM_MODEL_SPHEROID) {
             rc = check_spheroid_params(params);
             if (rc) return rc;
@@ -467,6 +484,7 @@ int bdm_grid_info(const bdm_workspace *ws, bdm_grid_desc *desc, void *stream) {
     desc->n = g.n;
     desc->valid = g.valid;
     desc->flags = g.flags;
+    desc->skipped = g.skipped;
     return BDM_OK;
 }
 
@@ -483,8 +501,11 @@ int bdm_grid_export(const bdm_workspace *ws, uint32_t *key, uint32_t *order, uin
         return hip_check("grid_export key");
     if (order && n && hipMemcpyAsync(order, w.ids, 4 * n, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return hip_check("grid_export order");
-    if (start && hipMemcpyAsync(start, w.start, 4 * (size_t(d.nboxes) + 1), hipMemcpyDeviceToDevice, st) != hipSuccess)
-        return hip_check("grid_export start");
+    if (start) {
+        if (hipMemcpyAsync(start, w.start, 4 * (size_t(d.nboxes) + 1), hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return hip_check("grid_export start");
+        bdm::launch_mask_starts(start, d.nboxes + 1, st);  // (the stationary-skip marks)
+    }
     if (hipStreamSynchronize(st) != hipSuccess) return hip_check("grid_export sync");
     return BDM_OK;
 }
@@ -561,7 +582,8 @@ int bdm_batch_set_slot(const bdm_batch *b, int32_t slot, int64_t agent_off, int6
     if (steps < 0) return fail(BDM_EINVAL, "steps must be >= 0");
     rc = check_mech_params(p);
     if (rc) return rc;
-    const bdm::SlotDev rec = slot_record(p, agent_off, capacity, box_off, max_boxes, steps, true);
+    bdm::SlotDev rec = slot_record(p, agent_off, capacity, box_off, max_boxes, steps, true);
+    rec.skip = 0;  // (the batched step does not skip stationary agents)
     const int64_t first = agent_off / bdm::kBlock;
     const int64_t ntile = (agent_off + capacity + bdm::kBlock - 1) / bdm::kBlock - first;
     bdm::launch_set_slot(w, slot, rec, first, ntile, slot, as_stream(stream));

@@ -47,6 +47,11 @@ __device__ __forceinline__ uint32_t pre8_radius(double r, double inv_b) {
 }
 constexpr uint32_t kScanSpinLimit = 1u << 22;  // polls before a look-back gives up
 
+// Bit 31 of a box start in builds that may skip stationary agents: an agent that moved in the
+// last step left or entered the box.  Starts are below 2^31 (capacity), so the bit is free; every
+// reader of such a build masks it off (kStartMask).
+constexpr uint32_t kStartDirty = 0x80000000u, kStartMask = 0x7FFFFFFFu;
+
 // Philox draw purposes: counter word 0 = purpose + (attempt << 8).
 enum : uint64_t { kRngInit = 1, kRngMove = 2, kRngRec = 3, kRngInf = 4, kRngDiv = 5 };
 
@@ -68,13 +73,16 @@ struct GridDev {
     double inv_b;                   // 1 / b, rounded (the pre-test records' scale)
     int32_t kind;                   // what the last build wrote (kGrid*)
     int32_t consumed;               // 1 once a plain mechanical step has used the build
+    int32_t mark_ready;             // the last plain step skipped stationary agents and marked its movers
+    int32_t skip_ok;                // this build may skip stationary agents (same lattice, marks ready)
+    int64_t skipped;                // agents the last skipping step skipped
 };
 static_assert(sizeof(GridDev) <= 256, "grid record must fit its slot");
 
 // What a grid build wrote, so that a step can refuse a build it cannot use: open space with the
 // 8-byte pre-test records, the same plus the binary32 copies (spheroid steps), or the periodic
 // (SIR) lattice, which writes no pre-test records.
-enum : int32_t { kGridNone = 0, kGridOpen = 1, kGridOpenF32 = 2, kGridPeriodic = 3 };
+enum : int32_t { kGridNone = 0, kGridOpen = 1, kGridOpenF32 = 2, kGridPeriodic = 3, kGridOpenSkip = 4 };
 
 // Parameters and placement of one slot.
 struct SlotDev {
@@ -91,13 +99,14 @@ struct SlotDev {
     int32_t periodic;
     int32_t nb;          // periodic boxes per axis
     int32_t has_d;       // spheres (diameters present) or points
+    int32_t skip;        // plain mechanics: skip agents in stationary regions
 };
 
 // Byte offsets of every workspace region (256-byte aligned).  `slots` = 0 is a plain
 // workspace (one grid record, slot passed by value); > 0 is a batch of that many slots.
 struct WsLayout {
     size_t grid, slots, tilemap, bucketmap, partials, count, bstart, start, tiles, key, rank, item, tmpid, pos4, pos4f, pos8,
-        adh, ids, state, flagid, rankid, order_bins, crowd;
+        adh, ids, state, flagid, rankid, order_bins, crowd, dirty, moved, fprev, tileskip;
     size_t total;
     int64_t capacity, max_boxes, max_tiles, nslots, ntiles, nbuckets;
 };
@@ -143,6 +152,10 @@ inline bool ws_layout(int64_t capacity, int64_t max_boxes, int64_t slots, WsLayo
     L->rankid = take(4 * (cap + 1));
     L->order_bins = take(3 * 4 * size_t(kOrderBins));
     L->crowd = take(4 * (nbk + 1));  // buckets the bucket sort hands to the crowded-box ranking
+    L->dirty = take(mb + 1);         // stationary skip: boxes a mover left or entered
+    L->moved = take(cap);            // stationary skip: agents that moved in the last step
+    L->fprev = take(24 * cap);       // stationary skip: the last step's force, in the new sorted order
+    L->tileskip = take(4 * (kBlock / 64) * ntile);  // stationary skip: agents skipped per wavefront of a tile
     L->total = off;
     L->capacity = capacity;
     L->max_boxes = max_boxes;
@@ -174,6 +187,10 @@ struct Ws {
     uint32_t *flagid, *rankid;
     uint32_t *order_first, *order_last, *order_shift;  // tile-order runs per bin (plain calls)
     uint32_t *crowd;     // crowded buckets of the running build (bucket sort -> crowded-box ranking)
+    uint8_t *dirty;      // stationary skip: per box, a mover left or entered it since the last build
+    uint8_t *moved;      // stationary skip: per agent (sorted order of the last build), it moved
+    double *fprev;       // stationary skip: fx, fy, fz of the last step, in this build's sorted order
+    uint32_t *tileskip;  // stationary skip: agents skipped per tile of the last step
     WsLayout lay;
 };
 
@@ -202,6 +219,10 @@ inline Ws ws_view(void *base, const WsLayout &L) {
     w.flagid = reinterpret_cast<uint32_t *>(p + L.flagid);
     w.rankid = reinterpret_cast<uint32_t *>(p + L.rankid);
     w.crowd = reinterpret_cast<uint32_t *>(p + L.crowd);
+    w.dirty = reinterpret_cast<uint8_t *>(p + L.dirty);
+    w.moved = reinterpret_cast<uint8_t *>(p + L.moved);
+    w.fprev = reinterpret_cast<double *>(p + L.fprev);
+    w.tileskip = reinterpret_cast<uint32_t *>(p + L.tileskip);
     w.order_first = reinterpret_cast<uint32_t *>(p + L.order_bins);
     w.order_last = w.order_first + kOrderBins;
     w.order_shift = w.order_last + kOrderBins;

@@ -74,6 +74,9 @@ __device__ void clear_grid(GridDev *g) {
     g->sorted_base = 0;
     g->kind = kGridNone;
     g->consumed = 0;
+    g->mark_ready = 0;
+    g->skip_ok = 0;
+    g->skipped = 0;
 }
 
 // Zero the grid records, the histogram and the scan tiles; empty the batch slot table.
@@ -172,6 +175,16 @@ void launch_set_slot(const Ws &w, int32_t slot, const SlotDev &rec, int64_t firs
     const int64_t most = ntile > nbucket ? ntile : nbucket;
     hipLaunchKernelGGL(k_set_slot, dim3(nblocks(most, 0)), dim3(kBlock), 0, st, w.slots, w.tilemap, w.bucketmap,
                        w.grid, slot, rec, first_tile, ntile, first_bucket, nbucket, value);
+}
+
+// Box starts as a reader sees them: without the stationary-skip marks of bit 31.
+__global__ __launch_bounds__(kBlock) void k_mask_starts(uint32_t *p, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] &= kStartMask;
+}
+
+void launch_mask_starts(uint32_t *p, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_mask_starts, dim3(nblocks(n, 0)), dim3(kBlock), 0, st, p, n);
 }
 
 // The status bits of a plain workspace's grid record into a caller's device word.

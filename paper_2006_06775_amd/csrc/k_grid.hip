@@ -157,6 +157,13 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Slots sl, const int64_t *n_
     const double hi[3] = {s_red[0][3], s_red[0][4], s_red[0][5]};
     const double dmax = a.has_d ? s_red[0][6] : 0.0;
     const bool bad = s_red[0][7] != 0.0;
+    // the last build's lattice and whether the step after it marked its movers (stationary skip)
+    const double prev_b = g->b;
+    const int32_t prev_cmin[3] = {g->cmin[0], g->cmin[1], g->cmin[2]};
+    const int32_t prev_dims[3] = {g->dims[0], g->dims[1], g->dims[2]};
+    const bool marks = kind == kGridOpenSkip && g->mark_ready && g->valid && g->consumed && g->kind == kGridOpenSkip;
+    g->mark_ready = 0;
+    g->skip_ok = 0;
     g->sir_counts[0] = g->sir_counts[1] = g->sir_counts[2] = 0ull;
     g->valid = 0;
     g->kind = kind;
@@ -245,6 +252,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Slots sl, const int64_t *n_
     g->inv_b = 1.0 / g->b;
     g->div_nx = fastdiv_magic(uint32_t(g->dims[0]));
     g->div_ny = fastdiv_magic(uint32_t(g->dims[1]));
+    // keys index the same boxes as in the last build only on the same lattice
+    g->skip_ok = marks && g->b == prev_b && g->cmin[0] == prev_cmin[0] && g->cmin[1] == prev_cmin[1] &&
+                 g->cmin[2] == prev_cmin[2] && g->dims[0] == prev_dims[0] && g->dims[1] == prev_dims[1] &&
+                 g->dims[2] == prev_dims[2];
     g->valid = 1;
 }
 
@@ -311,12 +322,16 @@ __device__ __forceinline__ KeyGrid key_grid(const Slots &sl, int slot) {
 // coordinates, then the keys, then the atomics), so that their memory accesses are in flight
 // together rather than one tile's chain of dependent accesses after another's.  A plain call
 // reads its one grid record once per group.
+// dirty / moved (plain calls that skip stationary agents, else NULL): the box of every agent
+// that moved in the last step is marked (the box it entered; the step marked the one it left).
 __global__ __launch_bounds__(kBlock) void k_key_bucket(Slots sl, int64_t ntiles, const double *__restrict__ x,
                                                        const double *__restrict__ y,
                                                        const double *__restrict__ z, uint32_t *count,
                                                        uint32_t *__restrict__ key,
-                                                       uint32_t *__restrict__ brank) {
+                                                       uint32_t *__restrict__ brank, uint8_t *dirty,
+                                                       const uint8_t *__restrict__ moved) {
     const int lane = threadIdx.x & 63;
+    const bool mark = dirty && sl.grids[0].skip_ok;
     const int64_t ngroups = (ntiles + kKeyTiles - 1) / kKeyTiles;
     for (int64_t grp = xcd_tile(blockIdx.x, gridDim.x); grp < ngroups; grp += gridDim.x) {
         const int64_t tile = grp * kKeyTiles;
@@ -358,6 +373,7 @@ __global__ __launch_bounds__(kBlock) void k_key_bucket(Slots sl, int64_t ntiles,
             if (!r[u].live) continue;
             key[r[u].i] = r[u].k;
             brank[r[u].i] = base + uint32_t(lane - r[u].head);
+            if (mark && moved[r[u].i]) dirty[r[u].k] = 1;
         }
     }
 }
@@ -556,6 +572,8 @@ struct SortOut {
     uint8_t *state;
     uint32_t *key;       // box key of each sorted agent
     uint32_t *tile_key;  // key of every tile's first agent (plain calls only)
+    uint8_t *dirty;      // stationary skip (plain calls): box marks, folded into the starts
+    double *fprev;       // stationary skip: the agents' last forces in the new sorted order
 };
 
 // One sorted agent as the bucket sort carries it.
@@ -617,6 +635,7 @@ struct SortCtx {
     int periodic;
     int64_t capacity;
     PreGrid pg;  // the bucket's grid (open lattices only)
+    bool fold;   // this build may skip stationary agents: carry the forces, mark the starts
 };
 
 // The agent at input index i, for a bucket whose first box is box0 (kl >= 64 marks an entry to
@@ -664,6 +683,11 @@ __device__ __forceinline__ void sort_write(const SortCtx &c, const BucketAgent &
     c.o.key[dst] = a.k;
     if (c.s.state) c.o.state[dst] = a.st;
     if (c.o.tile_key && (dst & (kBlock - 1)) == 0) c.o.tile_key[dst / kBlock] = a.k;
+    if (c.fold) {
+        c.o.fprev[3 * size_t(dst)] = c.s.fx[a.i];
+        c.o.fprev[3 * size_t(dst) + 1] = c.s.fy[a.i];
+        c.o.fprev[3 * size_t(dst) + 2] = c.s.fz[a.i];
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbuckets, int64_t max_boxes,
@@ -690,8 +714,9 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbucke
     const int64_t box0 = bk << kBucketShift;
     hist[lane] = 0u;
 
+    const bool fold = o.dirty && sl.grids[0].skip_ok;  // (plain calls only)
     const SortCtx ctx{sl, s, key, o, periodic, capacity,
-                      pre_grid(&sl.grids[sl.bucketmap ? sl.bucketmap[bk] : 0])};
+                      pre_grid(&sl.grids[sl.bucketmap ? sl.bucketmap[bk] : 0]), fold};
     auto from_index = [&](int64_t i, bool full) { return sort_agent(ctx, box0, i, full); };
     // the agent of item slot c
     auto fetch = [&](uint32_t c, bool full) {
@@ -729,11 +754,20 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbucke
         __builtin_amdgcn_wave_barrier();
         const uint32_t h = hist[lane];
         const uint32_t ls = wave_incl_scan(h) - h;
-        if (box0 + lane <= max_boxes) start[box0 + lane] = b0 + ls;
-    // the first box start of the next bucket is this bucket's end: written here too, so that a
-    // simulation whose box range ends at this bucket's end finds it even when no simulation
-    // owns the next bucket (both writers write the same value)
-    if (lane == 0 && box0 + kBucketBoxes <= max_boxes) start[box0 + kBucketBoxes] = b1;
+        if (box0 + lane <= max_boxes) {
+            uint32_t v = b0 + ls;
+            if (o.dirty) {  // stationary skip: fold the box's mark into its start, clear the mark
+                const int64_t bx = box0 + lane;
+                if (fold && o.dirty[bx]) v |= kStartDirty;
+                o.dirty[bx] = 0;
+            }
+            start[box0 + lane] = v;
+        }
+        // the first box start of the next bucket is this bucket's end: written here too, so that
+        // a simulation whose box range ends at this bucket's end finds it even when no simulation
+        // owns the next bucket (both writers write the same value).  Plain calls own every
+        // bucket, and when they mark their starts only the owner may write one.
+        if (!o.dirty && lane == 0 && box0 + kBucketBoxes <= max_boxes) start[box0 + kBucketBoxes] = b1;
         lst[lane] = ls;
         cur[lane] = ls;
         __builtin_amdgcn_wave_barrier();
@@ -782,14 +816,14 @@ __global__ __launch_bounds__(kBlock) void k_bucket_crowded(Slots sl, int64_t max
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (uniform)
     uint32_t *grp = s_grp[wave];
     const uint32_t nc = sl.grids[0].crowd_n;
-    SortCtx ctx{sl, s, key, o, periodic, capacity, {}};
+    SortCtx ctx{sl, s, key, o, periodic, capacity, {}, o.dirty && sl.grids[0].skip_ok};
     const int64_t nwaves = int64_t(gridDim.x) * (kBlock / 64);
     for (int64_t w = int64_t(blockIdx.x) * (kBlock / 64) + wave; w < int64_t(nc) * kBucketBoxes; w += nwaves) {
         const int64_t bk = crowd[w / kBucketBoxes];
         const int kl = int(w % kBucketBoxes);
         const int64_t box0 = bk << kBucketShift;
         if (box0 + kl + 1 > max_boxes) continue;
-        const uint32_t b0 = bstart[bk], s0 = start[box0 + kl], s1 = start[box0 + kl + 1];
+        const uint32_t b0 = bstart[bk], s0 = start[box0 + kl] & kStartMask, s1 = start[box0 + kl + 1] & kStartMask;
         if (s1 <= s0 || s0 < b0) continue;
         const uint32_t l0 = s0 - b0, gn = s1 - s0;
         ctx.pg = pre_grid(&sl.grids[sl.bucketmap ? sl.bucketmap[bk] : 0]);
@@ -946,13 +980,19 @@ void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, bool
     const int64_t nbt = (capacity + kBoundsTile - 1) / kBoundsTile;
     hipLaunchKernelGGL(k_bounds, dim3(tile_grid(sl, nbt)), dim3(kBlock), 0, st, sl, nbt, s.n, s.x, s.y, s.z, d,
                        w.partials, w.tiles, w.lay.max_tiles);
-    const int32_t kind = (!sl.table && sl.one.periodic) ? kGridPeriodic : (f32_copy ? kGridOpenF32 : kGridOpen);
+    // plain open-space mechanics that skips stationary agents (needs the forces of the last step)
+    const bool skip = !sl.table && !sl.one.periodic && sl.one.skip && !f32_copy && s.fx && s.fy && s.fz;
+    const int32_t kind = (!sl.table && sl.one.periodic) ? kGridPeriodic
+                         : f32_copy                     ? kGridOpenF32
+                         : skip                         ? kGridOpenSkip
+                                                        : kGridOpen;
     hipLaunchKernelGGL(k_finalize, dim3(unsigned(sl.nslots)), dim3(kBlock), 0, st, sl, s.n, w.partials, kind);
     const int64_t nt = (capacity + kBlock - 1) / kBlock;
     const unsigned nb = tile_grid(sl, nt);
     // keys and bucket ranks (rank array), bucket starts, agent indices by bucket
     const unsigned nbk = tile_grid(sl, (nt + kKeyTiles - 1) / kKeyTiles);
-    hipLaunchKernelGGL(k_key_bucket, dim3(nbk), dim3(kBlock), 0, st, sl, nt, s.x, s.y, s.z, w.count, w.key, w.rank);
+    hipLaunchKernelGGL(k_key_bucket, dim3(nbk), dim3(kBlock), 0, st, sl, nt, s.x, s.y, s.z, w.count, w.key, w.rank,
+                       skip ? w.dirty : nullptr, w.moved);
     launch_scan(w.count, w.bstart, nullptr, w.lay.nbuckets, w, 1, false, st);
     hipLaunchKernelGGL(k_bucket_scatter, dim3(nbk), dim3(kBlock), 0, st, sl, nt, w.key, w.rank, w.bstart, w.item,
                        capacity);
@@ -962,8 +1002,9 @@ void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, bool
     // (free during the build: the tile order is written there afterwards)
     uint32_t *tile_key = sl.table ? nullptr : w.rankid;
     const int periodic = sl.table ? 0 : sl.one.periodic;
-    SoaIn in{s.x, s.y, s.z, d, s.adh, s.id, s.state};
-    SortOut o{w.pos4, f32_copy ? w.pos4f : nullptr, w.pos8, w.adh, w.ids, w.state, w.rank, tile_key};
+    SoaIn in{s.x, s.y, s.z, d, s.adh, s.id, s.state, s.fx, s.fy, s.fz};
+    SortOut o{w.pos4, f32_copy ? w.pos4f : nullptr, w.pos8, w.adh, w.ids, w.state, w.rank, tile_key,
+              skip ? w.dirty : nullptr, w.fprev};
     const int64_t nwg = (w.lay.nbuckets + kBlock / 64 - 1) / (kBlock / 64);
     hipLaunchKernelGGL(k_bucket_sort, dim3(unsigned(nwg)), dim3(kBlock), 0, st, sl, w.lay.nbuckets,
                        w.lay.max_boxes, in, w.key, w.bstart, w.item, w.tmpid, w.flagid, w.start, o, periodic,

@@ -122,8 +122,8 @@ __device__ __forceinline__ void row_range(const GridDev *__restrict__ g, const u
     if (zz < 0 || zz >= nz || yy < 0 || yy >= ny) return;
     const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < nx - 1 ? cx + 1 : nx - 1;
     const uint32_t kb = uint32_t(x0) + uint32_t(nx) * (uint32_t(yy) + uint32_t(ny) * uint32_t(zz));
-    lo = start[kb];
-    hi = start[kb + uint32_t(x1 - x0) + 1u];
+    lo = start[kb] & kStartMask;
+    hi = start[kb + uint32_t(x1 - x0) + 1u] & kStartMask;
 }
 
 // The candidate runs of the agent with record p in box (cx, cy, cz), in canonical order, into
@@ -147,10 +147,13 @@ struct RowUnion {
     bool coop;
 };
 
-template <uint32_t kUnit, bool kCoop>
+// kSkip (a build that skips stationary agents): the starts carry the boxes' marks in bit 31
+// (kStartDirty); they are masked off, and `dirty` says whether any box the agent keeps (any box
+// that can hold a sphere touching it) is marked.
+template <uint32_t kUnit, bool kCoop, bool kSkip = false>
 __device__ __forceinline__ uint32_t load_runs(const GridDev *__restrict__ g, const uint32_t *__restrict__ start,
                                               int cx, int cy, int cz, const double4 &p, bool live,
-                                              uint2 (*s_run)[kBlock], int t, RowUnion &un) {
+                                              uint2 (*s_run)[kBlock], int t, RowUnion &un, bool *dirty = nullptr) {
     const int nx = g->dims[0], ny = g->dims[1], nz = g->dims[2];
     const double b = g->b;
     const double ox = double(g->cmin[0]) + double(cx), oy = double(g->cmin[1]) + double(cy),
@@ -172,6 +175,15 @@ __device__ __forceinline__ uint32_t load_runs(const GridDev *__restrict__ g, con
         const uint32_t kb = uint32_t(cx) + uint32_t(nx) * (uint32_t(yc) + uint32_t(ny) * uint32_t(zc));
         v[r] = __builtin_amdgcn_raw_buffer_load_b128(srs, kb * 4u, 0, 0);  // kb - 1 .. kb + 2
     }
+    uint32_t marks[9];  // (kSkip) row r: bit 0, 1, 2 = box kb - 1, kb, kb + 1 marked
+    if constexpr (kSkip) {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            marks[r] = (v[r][0] >> 31) | (v[r][1] >> 31) << 1 | (v[r][2] >> 31) << 2;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[r][e] &= kStartMask;
+        }
+    }
     // Dropping boxes pays where an agent shares its box with few others.  Agents of one box walk
     // the same runs in step when none are dropped, so a wavefront's lanes read the same records
     // together; dropping boxes per agent breaks that, which costs more than it saves in crowded
@@ -180,6 +192,7 @@ __device__ __forceinline__ uint32_t load_runs(const GridDev *__restrict__ g, con
     const double reach = p.w + 0.5 * b;
     const double T = v[4][2] - v[4][1] <= kCullMaxBox ? (reach * reach) * 1.001 : __builtin_inf();
     uint32_t lo[9], hi[9];
+    bool any_mark = false;
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
         const int dz = r / 3 - 1, dy = r % 3 - 1;
@@ -190,7 +203,12 @@ __device__ __forceinline__ uint32_t load_runs(const GridDev *__restrict__ g, con
         const bool left = cx > 0 && gyz + gx2l < T, right = cx < nx - 1 && gyz + gx2r < T;
         lo[r] = in && live ? (left ? v[r][0] : v[r][1]) : 0u;
         hi[r] = in && live ? (right ? v[r][3] : v[r][2]) : 0u;
+        if constexpr (kSkip) {
+            const uint32_t kept = in ? (2u | (left ? 1u : 0u) | (right ? 4u : 0u)) : 0u;
+            any_mark |= (marks[r] & kept) != 0u;
+        }
     }
+    if constexpr (kSkip) *dirty = any_mark;
     un.coop = false;
     if constexpr (kCoop) {
         // every lane takes part (the wavefront's lanes are all active here)
@@ -588,13 +606,26 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
 
 // One tile: 256 agents of one slot, one lane per agent.  precision: 64 or 32 for a plain call;
 // 0 = per slot.
-template <int kPrec, int kQ, class Tr, class Rec>
+// Stationary skip (paper Sec. 2.3 (iv)), plain calls: an agent whose kept boxes (every box that
+// can hold a sphere touching it, its own included) are unmarked -- no agent left or entered them
+// in the last step, so it did not move either -- on an unchanged lattice has the same candidates,
+// contacts and force as in the last step, where it was gated: it keeps that force (carried by the
+// sort into fprev) and its position, without a walk.  Every agent records whether it moves and
+// marks the box it leaves; the next build marks the box it enters.
+struct SkipIO {
+    const double *fprev;  // the last step's force of each sorted agent
+    uint8_t *moved;       // per output slot: the agent moves in this step
+    uint8_t *dirty;       // per box: a mover leaves it
+    uint32_t *tileskip;   // per wavefront of each tile: agents skipped
+};
+
+template <int kPrec, int kQ, class Tr, bool kSkip = false, class Rec>
 __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const Rec &rec,
                                           const double *__restrict__ adh_s, const uint32_t *__restrict__ id_s,
                                           const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
                                           const uint32_t *__restrict__ start_all, const bdm_soa &out,
                                           uint2 (*s_run)[kBlock], uint32_t (*s_q)[kBlock], typename Rec::Pre *s_stage,
-                                          const TraceOut &tout) {
+                                          const TraceOut &tout, const SkipIO &sk = SkipIO{}) {
     const int t = threadIdx.x;
     const int slot = slot_of_tile(sl, tile);
     if (slot < 0) return;
@@ -609,11 +640,20 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
     const bool f32 = kPrec == 32 || (kPrec == 0 && S.force_bits == 32);
     const uint32_t q = uint32_t(g->sorted_base + (l < g->n ? l : g->n - 1));
     const double4 p = rec.full(q * Rec::kUnit);
+    const uint32_t key = key_s[q];
     int cx, cy, cz;
-    key_coords(g, key_s[q], cx, cy, cz);
+    key_coords(g, key, cx, cy, cz);
     RowUnion un;
-    const uint32_t cnt = load_runs<Rec::kUnit, kQ == kQueueCrowded>(g, start_all + S.box_off, cx, cy, cz, p, live,
-                                                                  s_run, t, un);
+    bool marked = false;
+    uint32_t cnt = load_runs<Rec::kUnit, kQ == kQueueCrowded, kSkip>(g, start_all + S.box_off, cx, cy, cz, p, live,
+                                                                    s_run, t, un, &marked);
+    bool skip = false;
+    if constexpr (kSkip) {
+        skip = g->skip_ok && live && !marked;
+        if (skip) cnt = 0;
+        const unsigned long long m = __ballot(skip);
+        if ((t & 63) == 0) sk.tileskip[tile * (kBlock / 64) + (t >> 6)] = uint32_t(__popcll(m));
+    }
     double fx, fy, fz;
     // the agent's remaining inputs are loaded before the last exact pass, which hides their latency
     double adh;
@@ -635,6 +675,13 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
         tout.counts[S.agent_off + l] = tr.n;
         tout.hashes[S.agent_off + l] = tr.h;
     }
+    if constexpr (kSkip) {
+        if (skip) {
+            fx = sk.fprev[3 * size_t(q)];
+            fy = sk.fprev[3 * size_t(q) + 1];
+            fz = sk.fprev[3 * size_t(q) + 2];
+        }
+    }
 
     // adherence gate, clamp, integrate (binary64)
     double nxp = p.x, nyp = p.y, nzp = p.z;
@@ -653,6 +700,11 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
         nzp = p.z + uz;
     }
     const int64_t o = S.agent_off + l;
+    if constexpr (kSkip) {
+        const bool moves = !(fn < adh);
+        sk.moved[o] = moves ? 1 : 0;
+        if (moves) sk.dirty[key] = 1;
+    }
     __builtin_nontemporal_store(nxp, &out.x[o]);
     __builtin_nontemporal_store(nyp, &out.y[o]);
     __builtin_nontemporal_store(nzp, &out.z[o]);
@@ -666,12 +718,12 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
 }
 
 // Plain call: the tiles in the pencil order, one contiguous part of it per XCD.
-template <int kPrec, int kQ, class Tr, class Rec>
+template <int kPrec, int kQ, class Tr, bool kSkip = false, class Rec>
 __device__ __forceinline__ void mech_plain(const Slots &sl, const uint32_t *__restrict__ order, const Rec &rec,
                                            const double *__restrict__ adh_s, const uint32_t *__restrict__ id_s,
                                            const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
                                            const uint32_t *__restrict__ start, const bdm_soa &out,
-                                           const TraceOut &tout) {
+                                           const TraceOut &tout, const SkipIO &sk = SkipIO{}) {
     __shared__ uint2 s_run[9][kBlock];
     __shared__ uint32_t s_q[kQ][kBlock];
     __shared__ typename Rec::Pre s_stage[kQ == kQueueCrowded ? kBlock : 1];  // records of a cooperative walk
@@ -679,16 +731,19 @@ __device__ __forceinline__ void mech_plain(const Slots &sl, const uint32_t *__re
     // no usable grid of these agents: never built, its build failed, already used by a step,
     // or built for another model (the periodic lattice has no pre-test records; the crowded
     // kernel reads the binary32 copies only spheroid builds write)
+    // (a build that skips stationary agents marks its starts: only the skipping kernel reads it)
     const bool usable = g0->valid && !g0->consumed &&
-                        (kQ == kQueueCrowded ? g0->kind == kGridOpenF32 : (g0->kind == kGridOpen || g0->kind == kGridOpenF32));
+                        (kQ == kQueueCrowded ? g0->kind == kGridOpenF32
+                         : kSkip             ? g0->kind == kGridOpenSkip
+                                             : (g0->kind == kGridOpen || g0->kind == kGridOpenF32));
     if (!usable) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&g0->flags, BDM_FLAG_NOGRID);
         return;
     }
     const uint32_t live_tiles = uint32_t((g0->n + kBlock - 1) / kBlock);
     if (blockIdx.x >= live_tiles) return;
-    mech_tile<kPrec, kQ, Tr>(sl, order[xcd_tile(blockIdx.x, live_tiles)], rec, adh_s, id_s, state_s, key_s, start,
-                             out, s_run, s_q, s_stage, tout);
+    mech_tile<kPrec, kQ, Tr, kSkip>(sl, order[xcd_tile(blockIdx.x, live_tiles)], rec, adh_s, id_s, state_s, key_s,
+                                    start, out, s_run, s_q, s_stage, tout, sk);
 }
 
 // The normal queue: six wavefronts per SIMD (80 registers), which is also what the LDS of a
@@ -699,6 +754,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     const uint32_t *__restrict__ id_s, const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
     const uint32_t *__restrict__ start, bdm_soa out, TraceOut tout) {
     mech_plain<kPrec, kQueue, Tr>(sl, order, rec, adh_s, id_s, state_s, key_s, start, out, tout);
+}
+
+// The same with the stationary skip.
+template <int kPrec, class Tr, class Rec>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_mech_skip(
+    Slots sl, const uint32_t *__restrict__ order, Rec rec, const double *__restrict__ adh_s,
+    const uint32_t *__restrict__ id_s, const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
+    const uint32_t *__restrict__ start, bdm_soa out, TraceOut tout, SkipIO sk) {
+    mech_plain<kPrec, kQueue, Tr, true>(sl, order, rec, adh_s, id_s, state_s, key_s, start, out, tout, sk);
 }
 
 // The crowded queue (its LDS allows four wavefronts per SIMD).
@@ -778,6 +842,14 @@ static void launch_mech_rec(const bdm_soa &s, const Slots &sl, int64_t ntiles, u
             BDM_MECH(k_mech_crowded, 32);
         else
             BDM_MECH(k_mech_crowded, 64);
+    } else if (!sl.table && sl.one.skip) {
+        const SkipIO sk{w.fprev, w.moved, w.dirty, w.tileskip};
+        if (precision == 32)
+            hipLaunchKernelGGL((k_mech_skip<32, Tr, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, order, rec, w.adh, w.ids,
+                               w.state, w.rank, w.start, s, tout, sk);
+        else
+            hipLaunchKernelGGL((k_mech_skip<64, Tr, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, order, rec, w.adh, w.ids,
+                               w.state, w.rank, w.start, s, tout, sk);
     } else if (precision == 32) {
         BDM_MECH(k_mech, 32);
     } else if (precision == 64) {
@@ -799,8 +871,29 @@ static void launch_mech_traced(const bdm_soa &s, const Slots &sl, int64_t ntiles
         launch_mech_rec<NoTrace>(s, sl, ntiles, nb, precision, order, rec, w, TraceOut{nullptr, nullptr}, st);
 }
 
-// A plain mechanical step has used its grid build: the next step needs a new one.
-__global__ void k_grid_consume(GridDev *g) {
+// A plain mechanical step has used its grid build: the next step needs a new one.  After a step
+// that skips stationary agents, its marks are ready for the next build, and the agents skipped
+// are summed from the per-wavefront counts of the tiles it ran.
+__global__ __launch_bounds__(1024) void k_grid_consume(GridDev *g, const uint32_t *tileskip, int32_t skip) {
+    __shared__ unsigned long long s_part[1024 / 64];
+    if (skip) {
+        const bool ran = g->valid && g->kind == kGridOpenSkip && !g->consumed;
+        const int64_t nw = ran ? (g->n + kBlock - 1) / kBlock * (kBlock / 64) : 0;
+        unsigned long long c = 0;
+        if (g->skip_ok)
+            for (int64_t i = threadIdx.x; i < nw; i += blockDim.x) c += tileskip[i];
+        for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+        if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long sum = 0;
+            for (int k = 0; k < 1024 / 64; ++k) sum += s_part[k];
+            if (ran) {
+                g->skipped = int64_t(sum);
+                g->mark_ready = 1;
+            }
+        }
+    }
     if (threadIdx.x == 0) g->consumed = 1;
 }
 
@@ -826,7 +919,8 @@ void launch_mech(const bdm_soa &s, const Slots &sl, int64_t capacity, int precis
     } else {
         launch_mech_traced(s, sl, ntiles, nb, precision, order, RecGlobal{w.pos4, w.pos8}, w, trace, st);
     }
-    if (!sl.table) hipLaunchKernelGGL(k_grid_consume, dim3(1), dim3(64), 0, st, w.grid);
+    if (!sl.table)
+        hipLaunchKernelGGL(k_grid_consume, dim3(1), dim3(1024), 0, st, w.grid, w.tileskip, int32_t(sl.one.skip));
 }
 
 void launch_contacts_mech(int f32, const Slots &sl, const Ws &w, uint32_t *counts, const int64_t *offsets,

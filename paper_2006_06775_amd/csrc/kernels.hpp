@@ -13,6 +13,7 @@ struct SoaIn {
     const double *x, *y, *z, *d, *adh;
     const uint32_t *id;
     const uint8_t *state;
+    const double *fx, *fy, *fz;  // the last step's forces (stationary skip only)
 };
 
 struct ReadOut {
@@ -79,5 +80,6 @@ void launch_fp_probe(const double *a, const double *b, int64_t n, double *os, do
                      float *odf, hipStream_t st);
 void launch_ws_init(const Ws &w, hipStream_t st);
 void launch_copy_flags(const Ws &w, uint32_t *out, hipStream_t st);
+void launch_mask_starts(uint32_t *p, int64_t n, hipStream_t st);
 
 }  // namespace bdm

@@ -46,12 +46,13 @@ def test_workspace_bytes_host_only():
     assert 0 < a < b and a % 256 == 0
     # per agent: packed double4 record 32 B, its binary32 copy 16 and 8-byte pre-test record,
     # adherence 8, id 4, key 4, rank 4, bucket item 4, scratch id 4, state 1, division flag and
-    # rank 4 + 4 = 93 B
-    assert b - a == 4096 * 93 + 4 * 64  # plus one 64-byte bounds partial per 1024 agents
-    # per box: start 4 B, plus bucket count, bucket start and crowded-bucket entry 4 + 4 + 4 per
-    # 64 boxes
+    # rank 4 + 4 = 93 B; for the stationary skip the moved flag 1 and the last force 24 = 118 B
+    # plus one 64-byte bounds partial per 1024 agents and 16 B of skip counts per 256
+    assert b - a == 4096 * 118 + 4 * 64 + 16 * 16
+    # per box: start 4 B and the stationary-skip mark 1 B, plus bucket count, bucket start and
+    # crowded-bucket entry 4 + 4 + 4 per 64 boxes
     c = bdm.workspace_bytes(4096, 3000 + 64 * 1000)
-    assert abs((c - a) - 64 * 1000 * (4 + 12 / 64)) <= 3 * 256
+    assert abs((c - a) - 64 * 1000 * (5 + 12 / 64)) <= 4 * 256
 
 
 def test_validation_without_gpu():
