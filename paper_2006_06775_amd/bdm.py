@@ -75,7 +75,7 @@ class Workspace(C.Structure):
 
 class BatchRec(C.Structure):
     _fields_ = [("ptr", C.c_void_p), ("bytes", C.c_size_t), ("capacity", C.c_int64),
-                ("max_boxes", C.c_int64), ("slots", C.c_int32)]
+                ("max_boxes", C.c_int64), ("slots", C.c_int32), ("grid_cap", C.c_int32)]
 
 
 class GridDesc(C.Structure):
@@ -386,7 +386,7 @@ class Batch:
 
     FIELDS = ("x", "y", "z", "diam", "adh", "fx", "fy", "fz")
 
-    def __init__(self, capacity: int, max_boxes: int, slots: int, device: str = "cuda"):
+    def __init__(self, capacity: int, max_boxes: int, slots: int, device: str = "cuda", grid_cap: int = 0):
         self.capacity, self.max_boxes, self.slots = int(capacity), int(max_boxes), int(slots)
         self.t = {k: torch.zeros(self.capacity, dtype=torch.float64, device=device)
                   for k in self.FIELDS}
@@ -398,7 +398,7 @@ class Batch:
                            f"capacity={capacity} max_boxes={max_boxes} slots={slots}")
         self.ws_tensor = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.rec = BatchRec(self.ws_tensor.data_ptr(), nbytes, self.capacity, self.max_boxes,
-                            self.slots)
+                            self.slots, int(grid_cap))
         self.soa = Soa(self.capacity, _ptr(self.n), *(_ptr(self.t[k]) for k in self.FIELDS),
                        _ptr(self.t["id"]), None)
         batch_init(self.rec)

@@ -69,6 +69,8 @@ int get_ws(const bdm_workspace *ws, bdm::Ws *out) {
 int get_batch(const bdm_batch *b, bdm::Ws *out) {
     if (!b) return fail(BDM_ENOWS, "batch is NULL");
     if (b->slots < 1 || b->slots > BDM_MAX_SLOTS) return fail(BDM_EINVAL, "batch slots must be in [1, %d]", BDM_MAX_SLOTS);
+    if (b->grid_cap != 0 && (b->grid_cap < 64 || b->grid_cap > 65536))
+        return fail(BDM_EINVAL, "batch grid_cap must be 0 or in [64, 65536]");
     return view(b->ptr, b->bytes, b->capacity, b->max_boxes, b->slots, out);
 }
 
@@ -624,6 +626,7 @@ int batch_step(const bdm_soa *packed, const bdm_batch *b, const bdm::TraceOut *t
     sl.bucketmap = w.bucketmap;
     sl.grids = w.grid;
     sl.nslots = b->slots;
+    sl.grid_cap = b->grid_cap;
     bdm::launch_grid_build(*packed, sl, b->capacity, false, w, st);
     bdm::launch_mech(*packed, sl, b->capacity, 0, false, w, st, trace);
     bdm::launch_batch_advance(w, st);

@@ -238,6 +238,7 @@ struct Slots {
     GridDev *grids;            // grid record per slot
     int64_t nslots;            // 1 for a plain call
     SlotDev one;               // the plain call's slot record
+    int32_t grid_cap;          // batch: workgroups of the per-tile launches (they stride over the tiles)
 };
 
 __device__ __forceinline__ int slot_of_tile(const Slots &sl, int64_t tile) {

@@ -968,7 +968,7 @@ static inline unsigned blocks_for(int64_t n, int64_t per = kBlock) {
 // Workgroups of a per-tile launch: one per tile for a plain call; a batch strides over its
 // tiles with at most kBatchGrid workgroups, so empty capacity costs a table read, not a dispatch.
 unsigned tile_grid(const Slots &sl, int64_t ntiles) {
-    const int64_t cap = 8192;
+    const int64_t cap = sl.grid_cap > 0 ? sl.grid_cap : 8192;
     if (ntiles < 1) return 1;
     return unsigned(sl.table && ntiles > cap ? cap : ntiles);
 }

@@ -145,7 +145,7 @@ class Server:
         self.capacity = (int(capacity) + ALIGN - 1) // ALIGN * ALIGN
         self.max_boxes, self.slots = int(max_boxes), int(slots)
         self.box = box  # one edge for every request, or a tune.BoxPlan (edge per request size)
-        self.batch = bdm.Batch(self.capacity, self.max_boxes, self.slots)
+        self.batch = bdm.Batch(self.capacity, self.max_boxes, self.slots, grid_cap=int(getattr(box, "grid_cap", 0)))
         self.agents = RangeAllocator(self.capacity, ALIGN)
         self.boxes = RangeAllocator(self.max_boxes, bdm.BOX_ALIGN)
         self.free_slots = list(range(self.slots))[::-1]

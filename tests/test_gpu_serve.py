@@ -57,6 +57,24 @@ def test_served_mixed_box_edges_equal_alone():
 def test_tune_plan_measures():
     print("case: tune plan", flush=True)
     from paper_2006_06775_amd import tune
-    plan = tune.plan(classes=(2000, 20000), factors=(1.0, 1.25), steps=2)
+    plan = tune.plan(classes=(2000, 20000), factors=(1.0, 1.25), caps=(1024, 8192), steps=2)
     assert set(plan.best) == {2000, 20000} and set(plan.best.values()) <= {1.0, 1.25}
     assert all(t > 0 for row in plan.table.values() for t in row.values())
+    assert set(plan.split_table) == {1024, 8192} and plan.grid_cap in (1024, 8192)
+
+
+def test_work_split_changes_no_result():
+    """The same requests served with different work splits (grid caps) give identical results."""
+    print("case: serve work splits", flush=True)
+    from paper_2006_06775_amd import tune
+    trace = serve.make_trace(6, seed=6, rate=5000.0, n_min=2000, n_max=60000, s_min=2, s_max=5)
+    res = []
+    for cap in (64, 1024, 0):
+        srv = serve.Server(capacity=200_000, max_boxes=600_000, slots=4, box=tune.fixed(1.0, cap),
+                           keep_results=True)
+        srv.run(trace)
+        res.append(srv.results)
+    for r in trace:
+        for k in ("x", "y", "z"):
+            assert np.array_equal(res[0][r.rid][k].view(np.uint64), res[1][r.rid][k].view(np.uint64))
+            assert np.array_equal(res[0][r.rid][k].view(np.uint64), res[2][r.rid][k].view(np.uint64))

@@ -71,3 +71,7 @@ def test_tune_pick_and_plan_lookup():
     assert plan.box_for(20_000) == 15.0 and plan.box_for(3_000_000) == 15.0
     assert serve.box_edge(plan, 900) == 18.0 and serve.box_edge(15.0, 900) == 15.0
     assert tune.fixed(1.0).box_for(123456) == 15.0
+    # the work split: the default unless another is faster by more than 2 %
+    assert tune.pick_cap({4096: 0.99e-9, 8192: 1.0e-9}) == 8192
+    assert tune.pick_cap({4096: 0.97e-9, 8192: 1.0e-9}) == 4096
+    assert tune.pick_cap({2048: 1.0e-9, 16384: 2e-9}) == 2048  # default not measured
