@@ -84,7 +84,7 @@ void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t ou
 }
 
 /* Purposes of random draws: word 0 of the counter is purpose + (attempt << 8). */
-enum { RNG_INIT = 1, RNG_MOVE = 2, RNG_REC = 3, RNG_INF = 4, RNG_DIV = 5 };
+enum { RNG_INIT = 1, RNG_MOVE = 2, RNG_REC = 3, RNG_INF = 4, RNG_DIV = 5, RNG_APO = 6, RNG_MIG = 7 };
 
 /* One Philox block keyed by (seed, salt) at counter (purpose + attempt*2^8, id, step, 0). */
 void orc_draw(uint64_t seed, uint64_t salt, uint64_t purpose, uint64_t attempt, uint64_t id,
@@ -617,6 +617,71 @@ int orc_spheroid_step(int64_t *n, int64_t capacity, double *x, double *y, double
     rc = orc_grow_divide(n, capacity, x, y, z, d, adh, p, step, overflow);
     if (rc) return rc;
     return orc_mech_step(*n, x, y, z, d, adh, &p->mech, fx, fy, fz, NULL, NULL);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Tumour spheroid with apoptosis and Brownian migration [Sec. 3.2]                            */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct {
+    orc_spheroid_params sph;  /* growth, division, mechanics, Philox key */
+    double p_apo;             /* probability per step that a cell dies */
+    double migrate;           /* bound of the Brownian displacement per axis and step */
+} orc_oncology_params;
+
+/* Apoptosis.  Cell `id` dies at `step` iff word 0 of the draw (APO, 0, id, step) is below
+ * floor(p_apo * 2^64).  The survivors keep their relative order by id and are renumbered
+ * 0 .. n'-1 in that order, so ids stay dense (the next daughter id is n').  *n is updated. */
+int orc_apoptosis(int64_t *n, double *x, double *y, double *z, double *d, double *adh,
+                  double p_apo, uint64_t seed, uint64_t salt, int64_t step)
+{
+    int64_t n0 = *n, kept = 0;
+    for (int64_t i = 0; i < n0; ++i) {
+        uint64_t w[4];
+        orc_draw(seed, salt, RNG_APO, 0, (uint64_t)i, (uint64_t)step, w);
+        if (orc_bernoulli(w[0], p_apo)) continue;
+        x[kept] = x[i]; y[kept] = y[i]; z[kept] = z[i];
+        d[kept] = d[i]; adh[kept] = adh[i];
+        ++kept;
+    }
+    *n = kept;
+    return ORC_OK;
+}
+
+/* Brownian migration: every cell moves by migrate * (2u - 1) per axis, with u from words 0..2
+ * of the draw (MIG, 0, id, step).  Open space: no wall, no wrap. */
+int orc_migrate(int64_t n, double *x, double *y, double *z, double migrate, uint64_t seed,
+                uint64_t salt, int64_t step)
+{
+    if (!(migrate >= 0.0) || !isfinite(migrate)) return ORC_EINVAL;
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t w[4];
+        orc_draw(seed, salt, RNG_MIG, 0, (uint64_t)i, (uint64_t)step, w);
+        x[i] = x[i] + migrate * (2.0 * orc_u01(w[0]) - 1.0);
+        y[i] = y[i] + migrate * (2.0 * orc_u01(w[1]) - 1.0);
+        z[i] = z[i] + migrate * (2.0 * orc_u01(w[2]) - 1.0);
+    }
+    return ORC_OK;
+}
+
+/* One step of the tumour-spheroid behaviour: apoptosis -> growth -> division -> migration ->
+ * grid -> mechanics.  Each part draws with the ids the cells hold when it runs (the division
+ * axis and the migration use the ids after the renumbering of this step's apoptosis; a daughter
+ * migrates with its own new id). */
+int orc_oncology_step(int64_t *n, int64_t capacity, double *x, double *y, double *z, double *d,
+                      double *adh, const orc_oncology_params *p, int64_t step, double *fx,
+                      double *fy, double *fz, int32_t *overflow)
+{
+    int rc = check_mech_params(&p->sph.mech);
+    if (rc) return rc;
+    if (!(p->p_apo >= 0.0) || !(p->p_apo <= 1.0) || !(p->migrate >= 0.0) || !isfinite(p->migrate))
+        return ORC_EINVAL;
+    rc = orc_apoptosis(n, x, y, z, d, adh, p->p_apo, p->sph.seed, p->sph.salt, step);
+    if (rc) return rc;
+    rc = orc_grow_divide(n, capacity, x, y, z, d, adh, &p->sph, step, overflow);
+    if (rc) return rc;
+    rc = orc_migrate(*n, x, y, z, p->migrate, p->sph.seed, p->sph.salt, step);
+    if (rc) return rc;
+    return orc_mech_step(*n, x, y, z, d, adh, &p->sph.mech, fx, fy, fz, NULL, NULL);
 }
 
 /* ------------------------------------------------------------------------------------------ */

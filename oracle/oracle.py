@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("BDM_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 OK, EINVAL, ENOMEM, ENONFINITE, ETOOMANYBOXES = 0, -1, -2, -3, -4
-RNG_INIT, RNG_MOVE, RNG_REC, RNG_INF, RNG_DIV = 1, 2, 3, 4, 5
+RNG_INIT, RNG_MOVE, RNG_REC, RNG_INF, RNG_DIV, RNG_APO, RNG_MIG = 1, 2, 3, 4, 5, 6, 7
 SIR_S, SIR_I, SIR_R = 0, 1, 2
 
 
@@ -41,6 +41,10 @@ class _MechParams(C.Structure):
 class _SpheroidParams(C.Structure):
     _fields_ = [("mech", _MechParams), ("grow", C.c_double), ("div_d", C.c_double),
                 ("half_cbrt", C.c_double), ("seed", C.c_uint64), ("salt", C.c_uint64)]
+
+
+class _OncologyParams(C.Structure):
+    _fields_ = [("sph", _SpheroidParams), ("p_apo", C.c_double), ("migrate", C.c_double)]
 
 
 class _SirParams(C.Structure):
@@ -109,11 +113,16 @@ def _declare(L):
                                   C.POINTER(_SpheroidParams), C.c_int64, _I32]
     L.orc_spheroid_step.argtypes = [_I64, C.c_int64, _D, _D, _D, _D, _D,
                                     C.POINTER(_SpheroidParams), C.c_int64, _D, _D, _D, _I32]
+    L.orc_apoptosis.argtypes = [_I64, _D, _D, _D, _D, _D, C.c_double, C.c_uint64, C.c_uint64,
+                                C.c_int64]
+    L.orc_migrate.argtypes = [C.c_int64, _D, _D, _D, C.c_double, C.c_uint64, C.c_uint64, C.c_int64]
+    L.orc_oncology_step.argtypes = [_I64, C.c_int64, _D, _D, _D, _D, _D,
+                                    C.POINTER(_OncologyParams), C.c_int64, _D, _D, _D, _I32]
     L.orc_sir_step.argtypes = [C.c_int64, _D, _D, _D, _U8, C.POINTER(_SirParams), C.c_int64, _I64]
     for name in ("orc_generate_cube", "orc_generate_ball", "orc_generate_sir", "orc_grid_setup",
                  "orc_grid_sort", "orc_pair_force_f64", "orc_pair_force_f32", "orc_displacement",
                  "orc_mech_step", "orc_mech_sample", "orc_contacts", "orc_grow_divide", "orc_spheroid_step",
-                 "orc_sir_step"):
+                 "orc_apoptosis", "orc_migrate", "orc_oncology_step", "orc_sir_step"):
         getattr(L, name).restype = C.c_int
 
 
@@ -295,6 +304,25 @@ def division_axis(seed, agent_id, step, salt=0):
     return out
 
 
+def oncology_params(grow, div_d, half_cbrt, seed, p_apo, migrate, salt=0, **mech):
+    return _OncologyParams(spheroid_params(grow, div_d, half_cbrt, seed, salt, **mech), p_apo, migrate)
+
+
+def hull_diameter(x, y, z) -> float:
+    """Spheroid diameter [Sec. 3.2]: the diameter of the sphere whose volume equals that of the
+    convex hull of the cell centres, (6 V / pi)^(1/3).  The hull volume is Qhull's (through
+    scipy).  Fewer than four points, or points in one plane, give 0."""
+    from scipy.spatial import ConvexHull, QhullError
+    pts = np.stack([_f64(x), _f64(y), _f64(z)], axis=1)
+    if len(pts) < 4:
+        return 0.0
+    try:
+        vol = ConvexHull(pts).volume
+    except QhullError:
+        return 0.0
+    return float((6.0 * vol / np.pi) ** (1.0 / 3.0))
+
+
 class SpheroidState:
     """Spheroid population with room for `capacity` agents (arrays sized to capacity)."""
 
@@ -333,6 +361,31 @@ class SpheroidState:
                                      _p(a["adh"], C.c_double), C.byref(params), step,
                                      _p(ov, C.c_int32)), "grow_divide")
         return bool(ov[0])
+
+
+    def oncology_step(self, params: _OncologyParams, step: int):
+        ov = np.zeros(1, dtype=np.int32)
+        a = self.arr
+        _check(lib().orc_oncology_step(_p(self.n, C.c_int64), self.capacity,
+                                       _p(a["x"], C.c_double), _p(a["y"], C.c_double),
+                                       _p(a["z"], C.c_double), _p(a["d"], C.c_double),
+                                       _p(a["adh"], C.c_double), C.byref(params), step,
+                                       _p(self.f[0], C.c_double), _p(self.f[1], C.c_double),
+                                       _p(self.f[2], C.c_double), _p(ov, C.c_int32)),
+               "oncology_step")
+        return bool(ov[0])
+
+    def apoptosis(self, p_apo: float, seed: int, step: int, salt: int = 0):
+        a = self.arr
+        _check(lib().orc_apoptosis(_p(self.n, C.c_int64), _p(a["x"], C.c_double),
+                                   _p(a["y"], C.c_double), _p(a["z"], C.c_double),
+                                   _p(a["d"], C.c_double), _p(a["adh"], C.c_double), p_apo, seed,
+                                   salt, step), "apoptosis")
+
+    def migrate(self, migrate: float, seed: int, step: int, salt: int = 0):
+        a = self.arr
+        _check(lib().orc_migrate(int(self.n[0]), _p(a["x"], C.c_double), _p(a["y"], C.c_double),
+                                 _p(a["z"], C.c_double), migrate, seed, salt, step), "migrate")
 
 
 # ---------------------------------------------------------------------------------------------
