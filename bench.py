@@ -256,6 +256,33 @@ def workloads():
                               flags=bdm.status(pop.ws), precision="fp64")
     del pop, counts
     torch.cuda.empty_cache()
+    # tumour spheroid with apoptosis and Brownian migration: the same 10^4 cells, 1 % death
+    # chance per step, migration up to 1 um per axis and step, 60 steps; the spheroid diameter
+    # (equal-volume sphere of the hull of the centres) before and after
+    from paper_2006_06775_amd import observe
+    steps = 60
+    pop = bdm.Population(300_000, 1 << 22)
+    bdm.generate(pop.soa, bdm.gen(bdm.GEN_BALL, 10_000, 60.0, 14.0 * h, 14.0, 0.4, seed=0))
+    p_onc = bdm.params(grow=g, div_d=14.0, half_cbrt=h, seed=0, p_apo=0.01, migrate=1.0)
+    d_start = observe.spheroid_diameter(pop)
+    counts = torch.zeros(steps, dtype=torch.int64, device="cuda")
+
+    def onc(step):
+        bdm.sim_step(pop.soa, bdm.MODEL_ONCOLOGY, p_onc, step, pop.ws)
+        counts[step:step + 1].copy_(pop.t["n"])
+    t = timed_steps(torch, onc, steps)
+    updates = int(counts.sum().item())
+    stats = {}
+    t0 = time.perf_counter()
+    d_end = observe.spheroid_diameter(pop, stats=stats)
+    t_obs = time.perf_counter() - t0
+    out["oncology"] = dict(cells_start=10_000, cells_end=pop.n, steps=steps, seconds=t, steps_per_s=steps / t,
+                           agent_updates_per_s=updates / t, p_apo=0.01, migrate_um=1.0,
+                           diameter_um_start=round(d_start, 3), diameter_um_end=round(d_end, 3),
+                           diameter_seconds=round(t_obs, 4), hull_candidates=stats.get("candidates"),
+                           flags=bdm.status(pop.ws), precision="fp64")
+    del pop, counts
+    torch.cuda.empty_cache()
     # SIR: 10^7 points in a periodic 5000^3 cube, box 20 (250^3 boxes), radius 2, p_inf 0.3,
     # p_rec 0.01, walk 1, 0.1 % infected, 200 steps
     n, L, steps = 10_000_000, 5000.0, 200

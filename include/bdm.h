@@ -53,6 +53,7 @@ extern "C" {
 #define BDM_MODEL_MECH 0      /* grid build + mechanical step (open space) */
 #define BDM_MODEL_SPHEROID 1  /* growth + division, then grid build + mechanical step */
 #define BDM_MODEL_SIR 2       /* periodic grid build + SIR infection/recovery/movement */
+#define BDM_MODEL_ONCOLOGY 3  /* apoptosis, growth + division, Brownian migration, grid + mechanics */
 
 /* ---- batched form ------------------------------------------------------------------------ */
 #define BDM_MAX_SLOTS 4096      /* slots of one batch */
@@ -92,6 +93,8 @@ typedef struct bdm_params {
     double half_cbrt;      /* spheroid: daughter diameter factor (cube root of 1/2) */
     uint64_t seed, salt;   /* Philox4x64-10 key */
     int32_t skip_static;   /* 1: skip agents in stationary regions (mechanical steps; see below) */
+    double p_apo;          /* oncology: probability per step that a cell dies, in [0, 1] */
+    double migrate;        /* oncology: bound of the Brownian displacement per axis and step (>= 0) */
 } bdm_params;
 
 /* Stationary regions [paper Sec. 2.3 (iv): detect stationary regions and skip their expensive
@@ -204,6 +207,14 @@ int bdm_mech_step(const bdm_soa *soa, const bdm_params *params, const bdm_worksp
  *                      x + (d'/4)u with id n + (rank of the mother among dividing mothers by
  *                      id) and the mother's adherence; divisions with no slot below capacity
  *                      are skipped and set BDM_FLAG_CAPACITY; then grid + mechanics.
+ *   BDM_MODEL_ONCOLOGY [paper Sec. 3.2: growth, duplication, Brownian migration, apoptosis]
+ *                      apoptosis: the cell with id i dies iff draw (6, i, step, 0) has word 0 <
+ *                      floor(p_apo*2^64); the survivors are renumbered 0 .. n'-1 in their old id
+ *                      order and packed into slots 0 .. n'-1 (slot = id); then growth and
+ *                      division as BDM_MODEL_SPHEROID (with the new ids); then every cell moves
+ *                      by migrate*(2u - 1) per axis, u from words 0..2 of draw (7, id, step, 0)
+ *                      (open space); then grid + mechanics.  BDM_EINVAL for p_apo outside
+ *                      [0, 1] or a negative or non-finite migrate.
  *   BDM_MODEL_SIR      [paper Sec. 3.3] on the periodic grid of positions at t: a susceptible
  *                      agent with m infected agents within r_inf (minimum image, inclusive)
  *                      becomes infected iff one of the draws (4 + c*2^8, id, step, 0), c < m,
@@ -220,6 +231,30 @@ int bdm_sim_step(const bdm_soa *soa, int32_t model, const bdm_params *params, in
 int bdm_read_agents(const bdm_soa *soa, double *out_x, double *out_y, double *out_z,
                     double *out_diam, double *out_fx, double *out_fy, double *out_fz,
                     uint8_t *out_state, void *stream);
+
+/* Spheroid diameter [paper Sec. 3.2: the diameter is derived from the volume of the convex hull
+ * that encloses all cells].  These two calls do the O(n) part on the device; the host builds
+ * the hull of the few agents they return.  Positions must be finite.
+ *
+ * bdm_extreme_points: for each direction k < ndir (dirs: device, row k = (ux, uy, uz), binary64),
+ * out_slot[k] (device int32) = the smallest slot s < n maximising (ux*x[s] + uy*y[s]) + uz*z[s]
+ * (binary64, no contraction).  work: device scratch of ndir uint64, overwritten.
+ * 1 <= ndir <= BDM_HULL_MAX_DIRS.  With n = 0 every out_slot is 0x7fffffff.  Errors: BDM_EINVAL.
+ *
+ * bdm_hull_candidates: every slot s < n whose centre is not strictly inside all nplane
+ * half-spaces, i.e. for which some plane k (planes: device, row k = (nx, ny, nz, c)) has
+ * (nx*x[s] + ny*y[s]) + nz*z[s] + c >= -tol, is a candidate.  *out_count (device int64) = the
+ * number of candidates; the first min(count, max_out) of them are written to out_slot (device
+ * int32), in no particular order.  When the planes bound a polytope spanned by agents (faces
+ * with outward normals, c the offset) and tol covers the rounding of the plane test, no agent
+ * left out is a vertex of the agents' hull.  1 <= nplane <= BDM_HULL_MAX_PLANES, tol >= 0.
+ * Errors: BDM_EINVAL. */
+#define BDM_HULL_MAX_DIRS 256
+#define BDM_HULL_MAX_PLANES 1024
+int bdm_extreme_points(const bdm_soa *soa, const double *dirs, int32_t ndir, uint64_t *work,
+                       int32_t *out_slot, void *stream);
+int bdm_hull_candidates(const bdm_soa *soa, const double *planes, int32_t nplane, double tol,
+                        int32_t *out_slot, int64_t max_out, int64_t *out_count, void *stream);
 
 /* Sticky status bits of the workspace into *flags (host); clears them when `clear` != 0.
  * Synchronises the stream.  Errors: BDM_ENOWS, BDM_EHIP. */
@@ -245,7 +280,7 @@ int bdm_grid_export(const bdm_workspace *ws, uint32_t *key, uint32_t *order, uin
 int bdm_contacts(const bdm_workspace *ws, const bdm_params *params, uint32_t *counts,
                  const int64_t *offsets, uint32_t *ids, void *stream);
 
-/* Test hook: bdm_sim_step of model BDM_MODEL_MECH or BDM_MODEL_SPHEROID (same arguments, same
+/* Test hook: bdm_sim_step of model BDM_MODEL_MECH, _SPHEROID or _ONCOLOGY (same arguments, same
  * results) through the traced instantiation of the same kernels, which also records the contact
  * decisions the step's own walk takes [paper Sec. 2.1: the neighbours found in the 27 boxes].
  * For each agent s in the step's output order (box-sorted slots), counts[s] = the number of

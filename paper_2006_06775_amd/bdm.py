@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libbdm.so")
 OK, EINVAL, ENOWS, EHIP, ENODEV = 0, -1, -2, -3, -4
 (FLAG_CAPACITY, FLAG_BOXES, FLAG_NONFINITE, FLAG_BOXSMALL, FLAG_NOGRID, FLAG_SCAN,
  FLAG_BADCOUNT, FLAG_BADID) = (0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40, 0x80)
-MODEL_MECH, MODEL_SPHEROID, MODEL_SIR = 0, 1, 2
+MODEL_MECH, MODEL_SPHEROID, MODEL_SIR, MODEL_ONCOLOGY = 0, 1, 2, 3
 GEN_CUBE, GEN_BALL, GEN_SIR = 0, 1, 2
 
 # Exported C symbols, in declaration order of include/bdm.h.
@@ -31,7 +31,7 @@ SYMBOLS = (
     "bdm_grid_info", "bdm_grid_export", "bdm_contacts", "bdm_sim_step_traced", "bdm_sim_step_noalloc",
     "bdm_batch_workspace_bytes", "bdm_batch_init", "bdm_batch_set_slot", "bdm_batch_clear_slot",
     "bdm_batch_step", "bdm_batch_step_traced", "bdm_batch_slot_status", "bdm_fp_probe",
-    "bdm_strerror", "bdm_last_error",
+    "bdm_extreme_points", "bdm_hull_candidates", "bdm_strerror", "bdm_last_error",
 )
 MAX_SLOTS, SLOT_ALIGN, BOX_ALIGN = 4096, 1024, 64
 
@@ -59,7 +59,8 @@ class Params(C.Structure):
                 ("periodic", C.c_int32), ("L", C.c_double), ("r_inf", C.c_double),
                 ("p_inf", C.c_double), ("p_rec", C.c_double), ("walk", C.c_double),
                 ("grow", C.c_double), ("div_d", C.c_double), ("half_cbrt", C.c_double),
-                ("seed", C.c_uint64), ("salt", C.c_uint64), ("skip_static", C.c_int32)]
+                ("seed", C.c_uint64), ("salt", C.c_uint64), ("skip_static", C.c_int32),
+                ("p_apo", C.c_double), ("migrate", C.c_double)]
 
 
 class Gen(C.Structure):
@@ -113,6 +114,8 @@ def _load():
         "bdm_batch_clear_slot": ([P, C.c_int32, C.c_int64, C.c_int64, P], C.c_int),
         "bdm_batch_step": ([P, P, P], C.c_int),
         "bdm_batch_slot_status": ([P, C.c_int32, P, P, P], C.c_int),
+        "bdm_extreme_points": ([P, P, C.c_int32, P, P, P], C.c_int),
+        "bdm_hull_candidates": ([P, P, C.c_int32, C.c_double, P, C.c_int64, P, P], C.c_int),
         "bdm_strerror": ([C.c_int], C.c_char_p),
         "bdm_last_error": ([], C.c_char_p),
     }
@@ -153,9 +156,10 @@ def _ref(s):
 # ---------------------------------------------------------------------------------------------
 def params(k=2.0, gamma=1.0, dt=0.01, max_disp=3.0, box=0.0, force_bits=64, periodic=0, L=0.0,
            r_inf=0.0, p_inf=0.0, p_rec=0.0, walk=0.0, grow=1.05 ** (1.0 / 3.0), div_d=14.0,
-           half_cbrt=0.5 ** (1.0 / 3.0), seed=0, salt=0, skip_static=0) -> Params:
+           half_cbrt=0.5 ** (1.0 / 3.0), seed=0, salt=0, skip_static=0, p_apo=0.0,
+           migrate=0.0) -> Params:
     return Params(k, gamma, dt, max_disp, box, force_bits, periodic, L, r_inf, p_inf, p_rec,
-                  walk, grow, div_d, half_cbrt, seed, salt, skip_static)
+                  walk, grow, div_d, half_cbrt, seed, salt, skip_static, p_apo, migrate)
 
 
 def gen(kind=GEN_CUBE, n=0, L=200.0, dlo=10.0, dhi=15.0, adh=0.4, n_infected=0, seed=0,
@@ -330,6 +334,30 @@ def sim_step_noalloc(soa: Soa, model: int, p: Params, step: int, max_boxes: int,
     int32 tensor of one element that receives the status bits."""
     _check(_lib.bdm_sim_step_noalloc(_ref(soa), model, _ref(p), step, max_boxes, _ptr(flags),
                                      _stream(stream)), "sim_step_noalloc")
+
+
+HULL_MAX_DIRS, HULL_MAX_PLANES = 256, 1024
+
+
+def extreme_points(soa: Soa, dirs: torch.Tensor, work: torch.Tensor, out_slot: torch.Tensor, stream=None):
+    """dirs: device float64 (ndir, 3); work: device 8-byte tensor of ndir; out_slot: device int32
+    of ndir (the smallest slot maximising each direction's support)."""
+    dirs = dirs.contiguous()
+    ndir = dirs.shape[0]
+    if work.numel() < ndir or out_slot.numel() < ndir or work.element_size() != 8:
+        raise BdmError(EINVAL, "extreme_points", "work and out_slot need ndir entries")
+    _check(_lib.bdm_extreme_points(_ref(soa), _ptr(dirs), ndir, _ptr(work), _ptr(out_slot),
+                                   _stream(stream)), "extreme_points")
+
+
+def hull_candidates(soa: Soa, planes: torch.Tensor, tol: float, out_slot: torch.Tensor,
+                    out_count: torch.Tensor, stream=None):
+    """planes: device float64 (nplane, 4) rows (nx, ny, nz, c); out_slot: device int32 (its length
+    is max_out); out_count: device int64 of one element (the number of candidates)."""
+    planes = planes.contiguous()
+    _check(_lib.bdm_hull_candidates(_ref(soa), _ptr(planes), planes.shape[0], tol,
+                                    _ptr(out_slot), out_slot.numel(), _ptr(out_count), _stream(stream)),
+           "hull_candidates")
 
 
 def fp_probe(a: torch.Tensor, b: torch.Tensor, stream=None):

@@ -194,6 +194,12 @@ int check_spheroid_params(const bdm_params *p) {
     return BDM_OK;
 }
 
+int check_oncology_params(const bdm_params *p) {
+    if (!(p->p_apo >= 0.0) || !(p->p_apo <= 1.0)) return fail(BDM_EINVAL, "p_apo must be in [0, 1]");
+    if (!(p->migrate >= 0.0) || !is_fin(p->migrate)) return fail(BDM_EINVAL, "migrate must be finite and >= 0");
+    return BDM_OK;
+}
+
 int read_grid(const bdm::GridDev *src, bdm::GridDev *dst, hipStream_t st) {
     if (hipMemcpyAsync(dst, src, sizeof *dst, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
@@ -285,32 +291,49 @@ int sim_step(const bdm_soa *soa, int32_t model, const bdm_params *params, int64_
     hipStream_t st = as_stream(stream);
     switch (model) {
     case BDM_MODEL_MECH:
-    case BDM_MODEL_SPHEROID: {
+    case BDM_MODEL_SPHEROID:
+    case BDM_MODEL_ONCOLOGY: {
+        const bool cells = model != BDM_MODEL_MECH;  // growing cells: the crowded mechanics path
         rc = check_soa(soa, w.lay.capacity, true, false);
         if (rc) return rc;
         rc = check_mech_params(params);
         if (rc) return rc;
         bdm::SlotDev rec = slot_record(params, 0, soa->capacity, 0, w.lay.max_boxes, 1, true);
-        if (model == BDM_MODEL_SPHEROID) rec.skip = 0;  // (diameters change every step)
+        if (cells) rec.skip = 0;  // (diameters change every step)
         rc = check_skip(soa, params);
         if (rc && rec.skip) return rc;
-        if (model == BDM_MODEL_SPHEROID) {
+        if (cells) {
             rc = check_spheroid_params(params);
             if (rc) return rc;
+        }
+        if (model == BDM_MODEL_ONCOLOGY) {
+            rc = check_oncology_params(params);
+            if (rc) return rc;
+            bdm::ApoArgs apo{threshold(params->p_apo), params->seed, params->salt, uint64_t(step)};
+            if (apo.tapo.mode != 0) bdm::launch_apoptosis(*soa, soa->capacity, apo, w, st);
+            rc = hip_check("apoptosis launch");
+            if (rc) return rc;
+        }
+        if (cells) {
             bdm::DivArgs a{params->grow, params->div_d, params->half_cbrt, params->seed, params->salt, uint64_t(step)};
             bdm::launch_grow_divide(*soa, plain_slots(w, rec), soa->capacity, a, w, st);
             rc = hip_check("grow_divide launch");
             if (rc) return rc;
         }
-        bdm::launch_grid_build(*soa, plain_slots(w, rec), soa->capacity, model == BDM_MODEL_SPHEROID, w, st);
+        if (model == BDM_MODEL_ONCOLOGY) {
+            bdm::MigArgs mig{params->migrate, params->seed, params->salt, uint64_t(step)};
+            bdm::launch_migrate(*soa, soa->capacity, mig, st);
+            rc = hip_check("migrate launch");
+            if (rc) return rc;
+        }
+        bdm::launch_grid_build(*soa, plain_slots(w, rec), soa->capacity, cells, w, st);
         rc = hip_check("grid_build launch");
         if (rc) return rc;
-        bdm::launch_mech(*soa, plain_slots(w, rec), soa->capacity, params->force_bits, model == BDM_MODEL_SPHEROID, w,
-                         st, trace);
+        bdm::launch_mech(*soa, plain_slots(w, rec), soa->capacity, params->force_bits, cells, w, st, trace);
         return hip_check("mech_step launch");
     }
     case BDM_MODEL_SIR: {
-        if (trace) return fail(BDM_EINVAL, "a traced step is a mechanical one (MECH or SPHEROID)");
+        if (trace) return fail(BDM_EINVAL, "a traced step is a mechanical one (MECH, SPHEROID or ONCOLOGY)");
         rc = check_soa(soa, w.lay.capacity, false, true);
         if (rc) return rc;
         rc = check_sir_params(params);
@@ -437,6 +460,36 @@ int bdm_read_agents(const bdm_soa *soa, double *out_x, double *out_y, double *ou
     bdm::ReadOut o{out_x, out_y, out_z, out_diam, out_fx, out_fy, out_fz, out_state};
     bdm::launch_read_agents(*soa, o, as_stream(stream));
     return hip_check("read_agents launch");
+}
+
+int bdm_extreme_points(const bdm_soa *soa, const double *dirs, int32_t ndir, uint64_t *work, int32_t *out_slot,
+                       void *stream) {
+    g_last_error.clear();
+    if (!soa || !soa->n || !soa->x || !soa->y || !soa->z) return fail(BDM_EINVAL, "soa positions are required");
+    if (soa->capacity < 0 || soa->capacity > INT32_MAX) return fail(BDM_EINVAL, "capacity must be in [0, 2^31)");
+    if (ndir < 1 || ndir > BDM_HULL_MAX_DIRS) return fail(BDM_EINVAL, "ndir must be in [1, %d]", BDM_HULL_MAX_DIRS);
+    if (!dirs || !work || !out_slot) return fail(BDM_EINVAL, "dirs, work and out_slot are required");
+    int rc = check_device();
+    if (rc) return rc;
+    bdm::launch_extreme_points(*soa, dirs, ndir, reinterpret_cast<unsigned long long *>(work), out_slot,
+                               as_stream(stream));
+    return hip_check("extreme_points launch");
+}
+
+int bdm_hull_candidates(const bdm_soa *soa, const double *planes, int32_t nplane, double tol, int32_t *out_slot,
+                        int64_t max_out, int64_t *out_count, void *stream) {
+    g_last_error.clear();
+    if (!soa || !soa->n || !soa->x || !soa->y || !soa->z) return fail(BDM_EINVAL, "soa positions are required");
+    if (soa->capacity < 0 || soa->capacity > INT32_MAX) return fail(BDM_EINVAL, "capacity must be in [0, 2^31)");
+    if (nplane < 1 || nplane > BDM_HULL_MAX_PLANES)
+        return fail(BDM_EINVAL, "nplane must be in [1, %d]", BDM_HULL_MAX_PLANES);
+    if (!(tol >= 0.0) || !is_fin(tol)) return fail(BDM_EINVAL, "tol must be finite and >= 0");
+    if (!planes || !out_count || max_out < 0 || (max_out > 0 && !out_slot))
+        return fail(BDM_EINVAL, "planes, out_count and (for max_out > 0) out_slot are required");
+    int rc = check_device();
+    if (rc) return rc;
+    bdm::launch_hull_keep(*soa, planes, nplane, tol, out_slot, max_out, out_count, as_stream(stream));
+    return hip_check("hull_candidates launch");
 }
 
 int bdm_status(const bdm_workspace *ws, uint32_t *flags, int32_t clear, void *stream) {

@@ -53,7 +53,7 @@ constexpr uint32_t kScanSpinLimit = 1u << 22;  // polls before a look-back gives
 constexpr uint32_t kStartDirty = 0x80000000u, kStartMask = 0x7FFFFFFFu;
 
 // Philox draw purposes: counter word 0 = purpose + (attempt << 8).
-enum : uint64_t { kRngInit = 1, kRngMove = 2, kRngRec = 3, kRngInf = 4, kRngDiv = 5 };
+enum : uint64_t { kRngInit = 1, kRngMove = 2, kRngRec = 3, kRngInf = 4, kRngDiv = 5, kRngApo = 6, kRngMig = 7 };
 
 // Grid description and step bookkeeping of one slot (device memory, 256 bytes).
 struct GridDev {

@@ -32,6 +32,16 @@ struct DivArgs {
     uint64_t seed, salt, step;
 };
 
+struct ApoArgs {
+    Threshold tapo;
+    uint64_t seed, salt, step;
+};
+
+struct MigArgs {
+    double walk;
+    uint64_t seed, salt, step;
+};
+
 struct GenArgs {
     int32_t kind;
     int64_t n;
@@ -67,6 +77,15 @@ void launch_sir(const bdm_soa &s, const Slots &sl, int64_t capacity, const SirAr
                 hipStream_t st);
 void launch_grow_divide(const bdm_soa &s, const Slots &sl, int64_t capacity, const DivArgs &a, const Ws &w,
                         hipStream_t st);
+// Apoptosis: survivors compacted and renumbered 0 .. n'-1 in id order; n updated on the device.
+void launch_apoptosis(const bdm_soa &s, int64_t capacity, const ApoArgs &a, const Ws &w, hipStream_t st);
+// Brownian migration of every live agent.
+void launch_migrate(const bdm_soa &s, int64_t capacity, const MigArgs &a, hipStream_t st);
+// Spheroid-diameter observable: extreme agents per direction; agents outside a set of planes.
+void launch_extreme_points(const bdm_soa &s, const double *dirs, int32_t ndir, unsigned long long *work,
+                           int32_t *out_slot, hipStream_t st);
+void launch_hull_keep(const bdm_soa &s, const double *planes, int32_t nplane, double tol, int32_t *out_slot,
+                      int64_t max_out, int64_t *out_count, hipStream_t st);
 void launch_batch_advance(const Ws &w, hipStream_t st);
 void launch_set_slot(const Ws &w, int32_t slot, const SlotDev &rec, int64_t first_tile, int64_t ntile,
                      int32_t value, hipStream_t st);

@@ -1,0 +1,198 @@
+"""GPU parity of the tumour-spheroid behaviour with apoptosis and Brownian migration (paper
+Sec. 3.2), and of the spheroid-diameter observable, against the CPU oracle.
+
+* Counts per step, ids, diameters and (binary64 law) positions are bit-exact over whole runs:
+  apoptosis renumbers survivors by id, division appends daughters by mother rank, migration
+  draws by the new ids, and the crowded mechanics kernel sums in canonical order.
+* The traced step's contact decisions equal the oracle's contact lists on the state the
+  mechanics sees (after apoptosis, division and migration).
+* The diameter from the device hull filter equals the oracle's hull of all centres.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2006_06775_amd import bdm, observe  # noqa: E402
+from oracle import oracle as orc  # noqa: E402
+
+from test_gpu_contacts import expected, u32  # noqa: E402
+
+G = 1.05 ** (1.0 / 3.0)
+H = 0.5 ** (1.0 / 3.0)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_params(seed, p_apo, migrate, bits=64):
+    return bdm.params(grow=G, div_d=14.0, half_cbrt=H, seed=seed, p_apo=p_apo, migrate=migrate,
+                      force_bits=bits)
+
+
+def ora_params(seed, p_apo, migrate, bits=64):
+    return orc.oncology_params(G, 14.0, H, seed, p_apo, migrate, k=2.0, gamma=1.0, dt=0.01,
+                               max_disp=3.0, force_bits=bits)
+
+
+def run_pair(n0, radius, seed, p_apo, migrate, steps, cap, bits=64):
+    pop = bdm.Population(cap, 1 << 18)
+    bdm.generate(pop.soa, bdm.gen(bdm.GEN_BALL, n0, radius, 14.0 * H, 14.0, 0.4, seed=seed))
+    st = orc.SpheroidState(orc.generate_ball(n0, seed, radius, 14.0 * H, 14.0, 0.4), cap)
+    p, op = gpu_params(seed, p_apo, migrate, bits), ora_params(seed, p_apo, migrate, bits)
+    counts = []
+    for t in range(steps):
+        bdm.sim_step(pop.soa, bdm.MODEL_ONCOLOGY, p, t, pop.ws)
+        st.oncology_step(op, t)
+        assert pop.n == int(st.n[0]), t
+        counts.append(pop.n)
+    return pop, st, counts
+
+
+def bit_equal(got, ref):
+    return all(np.array_equal(got[a].view(np.uint64), ref[b].view(np.uint64))
+               for a, b in (("x", "x"), ("y", "y"), ("z", "z"), ("diam", "d")))
+
+
+@pytest.mark.parametrize("bits", [64, 32])
+def test_oncology_trajectory_bit_exact(bits):
+    say(f"case: oncology 1000 cells, 25 steps, bits={bits}")
+    pop, st, counts = run_pair(1000, 28.0, 5, 0.02, 1.0, 25, 40000, bits)
+    say(f"counts {counts[0]} .. {counts[-1]}")
+    assert counts[-1] > 1000  # growth wins over death at these rates
+    got = pop.read()
+    assert bit_equal(got, {k: st.view(k) for k in ("x", "y", "z", "d")})
+    assert bdm.status(pop.ws) == 0
+
+
+def test_oncology_high_death_rate():
+    """Deaths outpace divisions: the population shrinks, still bit-exact."""
+    say("case: oncology p_apo 0.2")
+    pop, st, counts = run_pair(3000, 40.0, 9, 0.2, 2.0, 12, 6000)
+    assert counts[-1] < 3000
+    assert bit_equal(pop.read(), {k: st.view(k) for k in ("x", "y", "z", "d")})
+    assert bdm.status(pop.ws) == 0
+
+
+def test_all_cells_die_then_steps_on_empty():
+    say("case: oncology p_apo 1")
+    pop = bdm.Population(512, 1 << 16)
+    bdm.generate(pop.soa, bdm.gen(bdm.GEN_BALL, 300, 20.0, 9.0, 14.0, 0.4, seed=1))
+    p = gpu_params(1, 1.0, 1.0)
+    bdm.sim_step(pop.soa, bdm.MODEL_ONCOLOGY, p, 0, pop.ws)
+    assert pop.n == 0
+    bdm.sim_step(pop.soa, bdm.MODEL_ONCOLOGY, p, 1, pop.ws)
+    assert pop.n == 0
+    assert bdm.status(pop.ws) == 0
+
+
+def test_no_death_no_migration_is_the_spheroid_step():
+    say("case: oncology == spheroid")
+    outs = []
+    for model in (bdm.MODEL_SPHEROID, bdm.MODEL_ONCOLOGY):
+        pop = bdm.Population(20000, 1 << 18)
+        bdm.generate(pop.soa, bdm.gen(bdm.GEN_BALL, 800, 25.0, 14.0 * H, 14.0, 0.4, seed=4))
+        p = gpu_params(4, 0.0, 0.0)
+        for t in range(15):
+            bdm.sim_step(pop.soa, model, p, t, pop.ws)
+        outs.append(pop.read(("x", "y", "z", "diam", "fx", "fy", "fz")))
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k].view(np.uint64), outs[1][k].view(np.uint64)), k
+
+
+def test_parameter_checks():
+    pop = bdm.Population(64, 1 << 12)
+    for bad in (dict(p_apo=-0.5), dict(p_apo=1.5), dict(p_apo=math.nan), dict(migrate=-1.0),
+                dict(migrate=math.inf)):
+        p = gpu_params(0, bad.get("p_apo", 0.0), bad.get("migrate", 0.0))
+        with pytest.raises(bdm.BdmError) as e:
+            bdm.sim_step(pop.soa, bdm.MODEL_ONCOLOGY, p, 0, pop.ws)
+        assert e.value.rc == bdm.EINVAL
+
+
+@pytest.mark.parametrize("bits", [64, 32])
+def test_traced_oncology_contacts_match_oracle(bits):
+    """Contacts of the oncology step's mechanics, on the state after apoptosis, division and
+    migration (built by the oracle's separate parts)."""
+    say(f"case: traced oncology contacts bits={bits}")
+    seed, step, n0, cap = 6, 3, 2500, 8000
+    init = orc.generate_ball(n0, seed, 30.0, 14.0 * H, 14.0, 0.4)
+    pop = bdm.Population(cap, 1 << 18)
+    pop.load(init)
+    counts = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    hashes = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    bdm.sim_step_traced(pop.soa, bdm.MODEL_ONCOLOGY, gpu_params(seed, 0.05, 1.5, bits), step, pop.ws, counts,
+                        hashes)
+    assert bdm.status(pop.ws) == 0
+    st = orc.SpheroidState(init, cap)
+    st.apoptosis(0.05, seed, step)
+    st.grow_divide(orc.spheroid_params(G, 14.0, H, seed), step)
+    st.migrate(1.5, seed, step)
+    n = int(st.n[0])
+    assert pop.n == n
+    _, _, order, _ = bdm.grid_export(pop.ws)
+    pre = {k: st.view(k).copy() for k in ("x", "y", "z", "d")}
+    ec, eh = expected(pre, order, bits)
+    got_c, got_h = u32(counts, n), u32(hashes, n)
+    bad = np.nonzero((got_c != ec) | (got_h != eh))[0]
+    say(f"{n} cells, {int(ec.sum())} contacts, {len(bad)} differ")
+    assert len(bad) == 0
+
+
+# ---- spheroid diameter ------------------------------------------------------------------------
+def diameter_pair(arrays):
+    n = len(arrays["x"])
+    pop = bdm.Population(max(n, 1), 1 << 12)
+    pop.load(arrays)
+    stats = {}
+    d = observe.spheroid_diameter(pop, stats=stats)
+    ref = orc.hull_diameter(arrays["x"], arrays["y"], arrays["z"])
+    return d, ref, stats
+
+
+def test_diameter_of_grown_spheroid():
+    say("case: diameter after 20 oncology steps")
+    pop, st, _ = run_pair(2000, 35.0, 2, 0.01, 1.0, 20, 40000)
+    stats = {}
+    d = observe.spheroid_diameter(pop, stats=stats)
+    ref = orc.hull_diameter(st.view("x"), st.view("y"), st.view("z"))
+    say(f"diameter {d:.6f} (oracle {ref:.6f}); {stats['candidates']} of {pop.n} candidates")
+    assert d == pytest.approx(ref, rel=1e-12)
+    assert stats["candidates"] < pop.n // 2
+
+
+@pytest.mark.parametrize("n", [200_000, 4097])
+def test_diameter_of_generated_balls(n):
+    say(f"case: diameter of a ball of {n} centres")
+    s = orc.generate_ball(n, 12, 60.0, 10.0, 14.0, 0.4)
+    d, ref, stats = diameter_pair(s)
+    say(f"diameter {d:.6f} (oracle {ref:.6f}); {stats['candidates']} candidates")
+    assert d == pytest.approx(ref, rel=1e-12)
+    assert stats["candidates"] < 0.25 * n
+
+
+def test_diameter_special_sets():
+    say("case: diameter special sets")
+    a = 7.0
+    corners = np.array([[i, j, k] for i in (0, a) for j in (0, a) for k in (0, a)], dtype=float)
+    inner = np.random.default_rng(1).uniform(0.5, a - 0.5, size=(5000, 3))
+    pts = np.concatenate([inner, corners]) + np.array([1.0e6, -30.0, 5.0])
+    cube = dict(x=pts[:, 0], y=pts[:, 1], z=pts[:, 2], d=np.full(len(pts), 1.0), adh=np.full(len(pts), 0.4))
+    d, ref, stats = diameter_pair(cube)
+    assert d == pytest.approx(ref, rel=1e-12)
+    assert d == pytest.approx((6 * a ** 3 / math.pi) ** (1 / 3), rel=1e-9)
+    assert stats["candidates"] <= 64
+    three = dict(x=np.array([0.0, 1.0, 2.0]), y=np.zeros(3), z=np.zeros(3), d=np.ones(3), adh=np.ones(3))
+    assert diameter_pair(three)[0] == 0.0
+    x = np.random.default_rng(2).uniform(0, 10, 300)
+    flat = dict(x=x, y=2 * x + 1, z=np.full(300, 4.0), d=np.ones(300), adh=np.ones(300))
+    assert diameter_pair(flat)[0] == 0.0
