@@ -19,6 +19,11 @@
  *   - Tumour-spheroid growth and division [Sec. 3.2] and the SIR epidemic model [Sec. 3.3:
  *     infection within a radius with a probability, recovery with a probability each step,
  *     bounded random movement], both on the same grid.
+ *   - Tumour-spheroid apoptosis and Brownian migration, and the convex-hull diameter (in the
+ *     Python wrapper) [Sec. 3.2].
+ *   - Extracellular substances [Sec. 2.1]: an explicit diffusion step with decay on a voxel grid
+ *     (a standalone operation), secretion and chemotaxis (agent behaviours), and the soma-
+ *     clustering model built from them [Sec. 3.4 benchmark].
  *   - Counter-based Philox4x64-10 random numbers (Salmon, Moraes, Dror, Shaw, SC'11).
  *
  * Where the paper is silent the readings are fixed as follows (each one is restated at the
@@ -781,4 +786,160 @@ int orc_sir_step(int64_t n, double *x, double *y, double *z, uint8_t *state,
     }
     free(key); free(order); free(start); free(next);
     return rc;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Extracellular substances [Sec. 2.1: diffusion of substances as a standalone operation run   */
+/* once per step; secretion and chemotaxis as agent behaviours] and the soma-clustering        */
+/* benchmark [Sec. 3.4]                                                                        */
+/* ------------------------------------------------------------------------------------------ */
+/* A substance lives on a uniform grid of nx*ny*nz cubic voxels of edge h with lower corner
+ * (x0, y0, z0); voxel (i, j, k) is element i + nx*(j + ny*k) (x fastest).  The two substances of
+ * the soma-clustering model are stored one after the other (substance s at offset s*V). */
+typedef struct {
+    int64_t nx, ny, nz;
+    double x0, y0, z0, h;
+} orc_field;
+
+static int check_field(const orc_field *f)
+{
+    if (f->nx < 1 || f->ny < 1 || f->nz < 1) return ORC_EINVAL;
+    if (!(f->h > 0.0) || !isfinite(f->h) || !finite3(f->x0, f->y0, f->z0)) return ORC_EINVAL;
+    return ORC_OK;
+}
+
+static int64_t field_index(const orc_field *f, int64_t i, int64_t j, int64_t k)
+{
+    return i + f->nx * (j + f->ny * k);
+}
+
+/* Voxel coordinate of a position along one axis: floor((v - origin) / h), clamped into the grid
+ * (agents outside the grid use the nearest boundary voxel). */
+static int64_t voxel_coord(double v, double origin, double h, int64_t n)
+{
+    double c = floor((v - origin) / h);
+    if (c < 0.0) c = 0.0;
+    if (c > (double)(n - 1)) c = (double)(n - 1);
+    return (int64_t)c;
+}
+
+/* One explicit (forward-Euler, central-difference) diffusion step with decay:
+ *   out = c + (lam * L(c) - kdec * c),
+ *   L(c) = ((dx- + dx+) + (dy- + dy+)) + (dz- + dz+),  d = c_neighbour - c,
+ * lam = D*dt/h^2 and kdec = decay*dt.  The boundary is closed (no flux): a neighbour outside the
+ * grid takes the voxel's own value, so its difference is zero. */
+int orc_diffuse(const orc_field *f, const double *in, double *out, double lam, double kdec)
+{
+    int rc = check_field(f);
+    if (rc) return rc;
+    for (int64_t k = 0; k < f->nz; ++k)
+        for (int64_t j = 0; j < f->ny; ++j)
+            for (int64_t i = 0; i < f->nx; ++i) {
+                double c = in[field_index(f, i, j, k)];
+                double xm = i > 0 ? in[field_index(f, i - 1, j, k)] : c;
+                double xp = i < f->nx - 1 ? in[field_index(f, i + 1, j, k)] : c;
+                double ym = j > 0 ? in[field_index(f, i, j - 1, k)] : c;
+                double yp = j < f->ny - 1 ? in[field_index(f, i, j + 1, k)] : c;
+                double zm = k > 0 ? in[field_index(f, i, j, k - 1)] : c;
+                double zp = k < f->nz - 1 ? in[field_index(f, i, j, k + 1)] : c;
+                double lap = (((xm - c) + (xp - c)) + ((ym - c) + (yp - c))) + ((zm - c) + (zp - c));
+                out[field_index(f, i, j, k)] = c + (lam * lap - kdec * c);
+            }
+    return ORC_OK;
+}
+
+/* Coefficients of the diffusion step from the physical parameters (the same expressions on
+ * every side): lam = (D*dt)/(h*h), kdec = decay*dt. */
+void orc_diffusion_coefficients(double D, double decay, double dt, double h, double out[2])
+{
+    out[0] = (D * dt) / (h * h);
+    out[1] = decay * dt;
+}
+
+/* Secretion: every agent of type s (0 or 1) adds q to substance s in the voxel holding its
+ * centre; a voxel holding m such agents gains q*m at once: c = c + q*m.  Agents of any other
+ * type are inert. */
+int orc_secrete(const orc_field *f, int64_t n, const double *x, const double *y, const double *z,
+                const uint8_t *type, double q, double *c)
+{
+    int rc = check_field(f);
+    if (rc) return rc;
+    int64_t V = f->nx * f->ny * f->nz;
+    uint32_t *m = (uint32_t *)calloc((size_t)(2 * V), sizeof(uint32_t));
+    if (!m) return ORC_ENOMEM;
+    for (int64_t a = 0; a < n; ++a) {
+        if (type[a] > 1) continue;
+        int64_t v = field_index(f, voxel_coord(x[a], f->x0, f->h, f->nx),
+                                voxel_coord(y[a], f->y0, f->h, f->ny),
+                                voxel_coord(z[a], f->z0, f->h, f->nz));
+        m[type[a] * V + v] += 1;
+    }
+    for (int64_t v = 0; v < 2 * V; ++v)
+        if (m[v]) c[v] = c[v] + q * (double)m[v];
+    free(m);
+    return ORC_OK;
+}
+
+/* Chemotaxis: an agent of type s moves by `speed` along the gradient of substance s at its
+ * voxel, g = (c(i+1) - c(i-1), c(j+1) - c(j-1), c(k+1) - c(k-1)) with neighbours outside the grid
+ * taking the voxel's own value; x += (speed/|g|) * g with |g| = sqrt((gx*gx + gy*gy) + gz*gz);
+ * no move where g = 0.  Agents of any other type do not move. */
+int orc_chemotaxis(const orc_field *f, int64_t n, double *x, double *y, double *z,
+                   const uint8_t *type, const double *c, double speed)
+{
+    int rc = check_field(f);
+    if (rc) return rc;
+    int64_t V = f->nx * f->ny * f->nz;
+    for (int64_t a = 0; a < n; ++a) {
+        if (type[a] > 1) continue;
+        const double *cs = c + type[a] * V;
+        int64_t i = voxel_coord(x[a], f->x0, f->h, f->nx);
+        int64_t j = voxel_coord(y[a], f->y0, f->h, f->ny);
+        int64_t k = voxel_coord(z[a], f->z0, f->h, f->nz);
+        int64_t im = i > 0 ? i - 1 : i, ip = i < f->nx - 1 ? i + 1 : i;
+        int64_t jm = j > 0 ? j - 1 : j, jp = j < f->ny - 1 ? j + 1 : j;
+        int64_t km = k > 0 ? k - 1 : k, kp = k < f->nz - 1 ? k + 1 : k;
+        double gx = cs[field_index(f, ip, j, k)] - cs[field_index(f, im, j, k)];
+        double gy = cs[field_index(f, i, jp, k)] - cs[field_index(f, i, jm, k)];
+        double gz = cs[field_index(f, i, j, kp)] - cs[field_index(f, i, j, km)];
+        double g2 = (gx * gx + gy * gy) + gz * gz;
+        if (!(g2 > 0.0)) continue;
+        double s = speed / sqrt(g2);
+        x[a] = x[a] + s * gx;
+        y[a] = y[a] + s * gy;
+        z[a] = z[a] + s * gz;
+    }
+    return ORC_OK;
+}
+
+typedef struct {
+    orc_mech_params mech;  /* mechanics; mech.dt is also the diffusion time step */
+    double D;              /* diffusion coefficient */
+    double decay;          /* decay rate */
+    double secrete;        /* quantity an agent adds to its substance per step */
+    double speed;          /* chemotactic displacement per step */
+} orc_soma_params;
+
+/* One soma-clustering step: secretion into c (in place) -> one diffusion step of both substances
+ * c -> c_next -> chemotaxis on c_next -> grid -> mechanics.  type[] is the agent's cell type. */
+int orc_soma_step(int64_t n, double *x, double *y, double *z, const double *d, const double *adh,
+                  const uint8_t *type, const orc_field *f, double *c, double *c_next,
+                  const orc_soma_params *p, double *fx, double *fy, double *fz)
+{
+    int rc = check_mech_params(&p->mech);
+    if (rc) return rc;
+    rc = check_field(f);
+    if (rc) return rc;
+    double coef[2];
+    orc_diffusion_coefficients(p->D, p->decay, p->mech.dt, f->h, coef);
+    if (!(coef[0] >= 0.0) || coef[0] > 1.0 / 6.0 || !(coef[1] >= 0.0) || coef[1] > 1.0) return ORC_EINVAL;
+    if (!isfinite(p->secrete) || !(p->speed >= 0.0) || !isfinite(p->speed)) return ORC_EINVAL;
+    rc = orc_secrete(f, n, x, y, z, type, p->secrete, c);
+    if (rc) return rc;
+    int64_t V = f->nx * f->ny * f->nz;
+    for (int s = 0; s < 2 && !rc; ++s) rc = orc_diffuse(f, c + s * V, c_next + s * V, coef[0], coef[1]);
+    if (rc) return rc;
+    rc = orc_chemotaxis(f, n, x, y, z, type, c_next, p->speed);
+    if (rc) return rc;
+    return orc_mech_step(n, x, y, z, d, adh, &p->mech, fx, fy, fz, NULL, NULL);
 }

@@ -47,6 +47,16 @@ class _OncologyParams(C.Structure):
     _fields_ = [("sph", _SpheroidParams), ("p_apo", C.c_double), ("migrate", C.c_double)]
 
 
+class _Field(C.Structure):
+    _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64), ("x0", C.c_double),
+                ("y0", C.c_double), ("z0", C.c_double), ("h", C.c_double)]
+
+
+class _SomaParams(C.Structure):
+    _fields_ = [("mech", _MechParams), ("D", C.c_double), ("decay", C.c_double),
+                ("secrete", C.c_double), ("speed", C.c_double)]
+
+
 class _SirParams(C.Structure):
     _fields_ = [("L", C.c_double), ("box", C.c_double), ("r_inf", C.c_double),
                 ("p_inf", C.c_double), ("p_rec", C.c_double), ("walk", C.c_double),
@@ -118,11 +128,20 @@ def _declare(L):
     L.orc_migrate.argtypes = [C.c_int64, _D, _D, _D, C.c_double, C.c_uint64, C.c_uint64, C.c_int64]
     L.orc_oncology_step.argtypes = [_I64, C.c_int64, _D, _D, _D, _D, _D,
                                     C.POINTER(_OncologyParams), C.c_int64, _D, _D, _D, _I32]
+    _F = C.POINTER(_Field)
+    L.orc_diffuse.argtypes = [_F, _D, _D, C.c_double, C.c_double]
+    L.orc_diffusion_coefficients.argtypes = [C.c_double] * 4 + [_D]
+    L.orc_diffusion_coefficients.restype = None
+    L.orc_secrete.argtypes = [_F, C.c_int64, _D, _D, _D, _U8, C.c_double, _D]
+    L.orc_chemotaxis.argtypes = [_F, C.c_int64, _D, _D, _D, _U8, _D, C.c_double]
+    L.orc_soma_step.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _U8, _F, _D, _D,
+                                C.POINTER(_SomaParams), _D, _D, _D]
     L.orc_sir_step.argtypes = [C.c_int64, _D, _D, _D, _U8, C.POINTER(_SirParams), C.c_int64, _I64]
     for name in ("orc_generate_cube", "orc_generate_ball", "orc_generate_sir", "orc_grid_setup",
                  "orc_grid_sort", "orc_pair_force_f64", "orc_pair_force_f32", "orc_displacement",
                  "orc_mech_step", "orc_mech_sample", "orc_contacts", "orc_grow_divide", "orc_spheroid_step",
-                 "orc_apoptosis", "orc_migrate", "orc_oncology_step", "orc_sir_step"):
+                 "orc_apoptosis", "orc_migrate", "orc_oncology_step", "orc_sir_step", "orc_diffuse",
+                 "orc_secrete", "orc_chemotaxis", "orc_soma_step"):
         getattr(L, name).restype = C.c_int
 
 
@@ -406,3 +425,79 @@ def sir_step(state, params: _SirParams, step: int):
                               _p(state["z"], C.c_double), _p(state["state"], C.c_uint8),
                               C.byref(params), step, _p(counts, C.c_int64)), "sir_step")
     return counts
+
+
+# ---------------------------------------------------------------------------------------------
+# Extracellular substances and soma clustering
+# ---------------------------------------------------------------------------------------------
+def field(nx, ny, nz, h, x0=0.0, y0=0.0, z0=0.0):
+    return _Field(nx, ny, nz, x0, y0, z0, h)
+
+
+def field_size(f: _Field) -> int:
+    return int(f.nx * f.ny * f.nz)
+
+
+def diffusion_coefficients(D, decay, dt, h):
+    out = np.zeros(2)
+    lib().orc_diffusion_coefficients(D, decay, dt, h, _p(out, C.c_double))
+    return float(out[0]), float(out[1])
+
+
+def diffuse(f: _Field, c, lam, kdec):
+    """One diffusion step of one substance (array of nx*ny*nz, x fastest); returns the new array."""
+    c = _f64(c)
+    out = np.empty_like(c)
+    _check(lib().orc_diffuse(C.byref(f), _p(c, C.c_double), _p(out, C.c_double), lam, kdec), "diffuse")
+    return out
+
+
+def _agents(state):
+    for key in ("x", "y", "z"):
+        state[key] = _f64(state[key])
+    state["state"] = np.ascontiguousarray(state["state"], dtype=np.uint8)
+    return len(state["x"])
+
+
+def secrete(f: _Field, state, q, c):
+    """Secretion in place on c (both substances, 2*nx*ny*nz)."""
+    n = _agents(state)
+    _check(lib().orc_secrete(C.byref(f), n, _p(state["x"], C.c_double), _p(state["y"], C.c_double),
+                             _p(state["z"], C.c_double), _p(state["state"], C.c_uint8), q,
+                             _p(c, C.c_double)), "secrete")
+
+
+def chemotaxis(f: _Field, state, c, speed):
+    """Chemotaxis in place on state['x'|'y'|'z'] along the substances c."""
+    n = _agents(state)
+    c = _f64(c)
+    _check(lib().orc_chemotaxis(C.byref(f), n, _p(state["x"], C.c_double), _p(state["y"], C.c_double),
+                                _p(state["z"], C.c_double), _p(state["state"], C.c_uint8),
+                                _p(c, C.c_double), speed), "chemotaxis")
+
+
+def soma_params(D, decay, secrete, speed, **mech):
+    return _SomaParams(mech_params(**mech), D, decay, secrete, speed)
+
+
+def generate_soma(n, seed, L, dmin, dmax, adh, salt=0):
+    """Cells uniform in [0, L)^3 (as generate_cube) with cell type id mod 2 in 'state'."""
+    s = generate_cube(n, seed, L, dmin, dmax, adh, salt)
+    s["state"] = (np.arange(n) & 1).astype(np.uint8)
+    return s
+
+
+def soma_step(state, f: _Field, c, params: _SomaParams):
+    """One soma-clustering step in place on state (x, y, z) and on c (secretion); returns
+    (c_next, fx, fy, fz)."""
+    n = _agents(state)
+    for key in ("d", "adh"):
+        state[key] = _f64(state[key])
+    c_next = np.empty_like(c)
+    fx, fy, fz = _zeros(n), _zeros(n), _zeros(n)
+    _check(lib().orc_soma_step(n, _p(state["x"], C.c_double), _p(state["y"], C.c_double),
+                               _p(state["z"], C.c_double), _p(state["d"], C.c_double),
+                               _p(state["adh"], C.c_double), _p(state["state"], C.c_uint8), C.byref(f),
+                               _p(c, C.c_double), _p(c_next, C.c_double), C.byref(params),
+                               _p(fx, C.c_double), _p(fy, C.c_double), _p(fz, C.c_double)), "soma_step")
+    return c_next, fx, fy, fz
