@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_mech_fp64_n16m.json"),
                     help="HBM bytes per mech_step launch from rocprofv3 counters (optional)")
     ap.add_argument("--no-serve", action="store_true", help="skip the batched/served stream")
-    ap.add_argument("--no-workloads", action="store_true", help="skip the spheroid and SIR runs")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the other workloads (spheroid, oncology, soma clustering, SIR)")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-budget-gib", type=float, default=4.0,
                     help="HBM the server may hold for resident simulations")
@@ -282,6 +282,37 @@ def workloads():
                            diameter_seconds=round(t_obs, 4), hull_candidates=stats.get("candidates"),
                            flags=bdm.status(pop.ws), precision="fp64")
     del pop, counts
+    torch.cuda.empty_cache()
+    # soma clustering: 2^21 cells of two types in a 1600 um cube (C0's density, d in [10, 15)),
+    # each type secreting its own substance on 320^3 voxels of 5 um; per step secretion (1 per
+    # cell), diffusion (D 250 um^2 per unit time, decay 0.1, dt 0.01: lam 0.1), chemotaxis
+    # (0.1 um per step), grid and binary64 mechanics
+    n, L = 1 << 21, 1600.0
+    steps = 20
+    pop = bdm.Population(n, bdm.box_count_hint(L, 14.9, 3), with_state=True)
+    bdm.generate(pop.soa, bdm.gen(bdm.GEN_SOMA, n, L, 10.0, 15.0, 0.4, seed=0))
+    fld = bdm.Field(320, 320, 320, 5.0)
+    p_soma = bdm.params(diff_D=250.0, diff_decay=0.1, secrete=1.0, chemo_speed=0.1)
+    fld.step(pop.soa, p_soma, pop.ws)  # warm-up (and box-sorted order)
+
+    def soma(step):
+        fld.step(pop.soa, p_soma, pop.ws)
+    t = timed_steps(torch, soma, steps)
+    flags = bdm.status(pop.ws)
+
+    def diff_only(step):
+        fld.diffuse(p_soma)
+    t_diff = timed_steps(torch, diff_only, steps) / steps
+    voxels = 2 * fld.V
+    diff_gbps = voxels * 16 / t_diff / 1e9  # one binary64 read and one write per voxel
+    out["soma_clustering"] = dict(
+        cells=n, voxels=voxels, steps=steps, seconds=t, steps_per_s=steps / t, agent_updates_per_s=n * steps / t,
+        flags=flags, precision="fp64",
+        diffusion=dict(ms_per_launch=round(t_diff * 1e3, 4), voxel_updates_per_s=voxels / t_diff,
+                       roofline=dict(bound="hbm", achieved=round(diff_gbps, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
+                                     frac=round(diff_gbps / HBM_PEAK_GBPS, 4), bytes_per_voxel=16,
+                                     scope="k_diffuse, both substances, one launch")))
+    del pop, fld
     torch.cuda.empty_cache()
     # SIR: 10^7 points in a periodic 5000^3 cube, box 20 (250^3 boxes), radius 2, p_inf 0.3,
     # p_rec 0.01, walk 1, 0.1 % infected, 200 steps

@@ -64,6 +64,7 @@ extern "C" {
 #define BDM_GEN_CUBE 0  /* uniform in [0, L)^3, diameter uniform in [dlo, dhi) */
 #define BDM_GEN_BALL 1  /* uniform in the ball of radius L about the origin (rejection) */
 #define BDM_GEN_SIR 2   /* points uniform in [0, L)^3, ids < n_infected infected */
+#define BDM_GEN_SOMA 3  /* as CUBE, with cell type (state) = id mod 2 */
 
 /* Agent state.  Every array has `capacity` elements; `n` points to the device-resident live
  * count (int64).  diam/adh may be NULL for point agents (SIR); fx/fy/fz may be NULL when the
@@ -95,6 +96,10 @@ typedef struct bdm_params {
     int32_t skip_static;   /* 1: skip agents in stationary regions (mechanical steps; see below) */
     double p_apo;          /* oncology: probability per step that a cell dies, in [0, 1] */
     double migrate;        /* oncology: bound of the Brownian displacement per axis and step (>= 0) */
+    double diff_D;         /* substances: diffusion coefficient (>= 0; D*dt/h^2 <= 1/6) */
+    double diff_decay;     /* substances: decay rate (>= 0; decay*dt <= 1) */
+    double secrete;        /* soma clustering: quantity a cell adds to its substance per step */
+    double chemo_speed;    /* soma clustering: chemotactic displacement per step (>= 0) */
 } bdm_params;
 
 /* Stationary regions [paper Sec. 2.3 (iv): detect stationary regions and skip their expensive
@@ -255,6 +260,50 @@ int bdm_extreme_points(const bdm_soa *soa, const double *dirs, int32_t ndir, uin
                        int32_t *out_slot, void *stream);
 int bdm_hull_candidates(const bdm_soa *soa, const double *planes, int32_t nplane, double tol,
                         int32_t *out_slot, int64_t max_out, int64_t *out_count, void *stream);
+
+/* Extracellular substances [paper Sec. 2.1: the diffusion of extracellular substances is a
+ * standalone operation run once per step; growth-factor secretion and chemotaxis are agent
+ * behaviours] on a uniform voxel grid, and the soma-clustering model [the Sec. 3.4 benchmark:
+ * two cell types, each secreting its own substance and moving up its gradient, so that cells of
+ * one type gather].
+ *
+ * Voxel (i, j, k) covers [x0 + i*h, x0 + (i+1)*h) x ...; substance s's value at the voxel is
+ * element s*V + i + nx*(j + ny*k), V = nx*ny*nz, binary64.  An agent belongs to the voxel
+ * floor((x - x0)/h) per axis, clamped into the grid.  All arrays are caller-owned device memory;
+ * c and c_next must not overlap. */
+typedef struct bdm_field {
+    int32_t nx, ny, nz;    /* voxels per axis, each in [1, 2^20], nx*ny*nz <= 2^30 */
+    double x0, y0, z0;     /* lower corner */
+    double h;              /* voxel edge (> 0) */
+    double *c;             /* 2*V values: both substances now */
+    double *c_next;        /* 2*V values: receives the next step's values (the caller then swaps) */
+    uint32_t *count;       /* 2*V secretion counters: zero between calls */
+} bdm_field;
+
+/* c = 0 and count = 0 (both substances).  Errors: BDM_EINVAL. */
+int bdm_field_init(const bdm_field *field, void *stream);
+
+/* One diffusion step of both substances, c -> c_next: with lam = (diff_D*dt)/(h*h) and
+ * kdec = diff_decay*dt (params->dt is the time step),
+ *   c_next = c + (lam*L - kdec*c),  L = ((dx- + dx+) + (dy- + dy+)) + (dz- + dz+),
+ * d = neighbour - c; the boundary is closed (a neighbour outside the grid is the voxel itself).
+ * BDM_EINVAL unless 0 <= lam <= 1/6 and 0 <= kdec <= 1 (the explicit step's stable range). */
+int bdm_diffuse(const bdm_field *field, const bdm_params *params, void *stream);
+
+/* One soma-clustering step.  soa->state holds each cell's type: types 0 and 1 secrete and follow
+ * substances 0 and 1, other types are inert.
+ *   1. secretion: each voxel's substance s grows by secrete*m, m = its cells of type s (in c);
+ *   2. diffusion of both substances, c -> c_next, as bdm_diffuse;
+ *   3. chemotaxis: a cell of type s at voxel (i, j, k) takes g = (c(i+1) - c(i-1), c(j+1) -
+ *      c(j-1), c(k+1) - c(k-1)) of substance s in c_next (neighbours outside the grid are the
+ *      voxel itself) and moves by (chemo_speed/|g|)*g, |g| = sqrt((gx*gx + gy*gy) + gz*gz); no
+ *      move where g = 0;
+ *   4. grid build + mechanical step, as BDM_MODEL_MECH (positions after chemotaxis).
+ * After the call the substances are in field->c_next (and field->c holds the secreted values
+ * before diffusion): swap the two pointers before the next step.  Errors: BDM_EINVAL, BDM_ENOWS;
+ * device: as bdm_sim_step. */
+int bdm_soma_step(const bdm_soa *soa, const bdm_params *params, const bdm_field *field,
+                  const bdm_workspace *ws, void *stream);
 
 /* Sticky status bits of the workspace into *flags (host); clears them when `clear` != 0.
  * Synchronises the stream.  Errors: BDM_ENOWS, BDM_EHIP. */

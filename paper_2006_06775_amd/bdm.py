@@ -22,7 +22,7 @@ OK, EINVAL, ENOWS, EHIP, ENODEV = 0, -1, -2, -3, -4
 (FLAG_CAPACITY, FLAG_BOXES, FLAG_NONFINITE, FLAG_BOXSMALL, FLAG_NOGRID, FLAG_SCAN,
  FLAG_BADCOUNT, FLAG_BADID) = (0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40, 0x80)
 MODEL_MECH, MODEL_SPHEROID, MODEL_SIR, MODEL_ONCOLOGY = 0, 1, 2, 3
-GEN_CUBE, GEN_BALL, GEN_SIR = 0, 1, 2
+GEN_CUBE, GEN_BALL, GEN_SIR, GEN_SOMA = 0, 1, 2, 3
 
 # Exported C symbols, in declaration order of include/bdm.h.
 SYMBOLS = (
@@ -31,7 +31,8 @@ SYMBOLS = (
     "bdm_grid_info", "bdm_grid_export", "bdm_contacts", "bdm_sim_step_traced", "bdm_sim_step_noalloc",
     "bdm_batch_workspace_bytes", "bdm_batch_init", "bdm_batch_set_slot", "bdm_batch_clear_slot",
     "bdm_batch_step", "bdm_batch_step_traced", "bdm_batch_slot_status", "bdm_fp_probe",
-    "bdm_extreme_points", "bdm_hull_candidates", "bdm_strerror", "bdm_last_error",
+    "bdm_extreme_points", "bdm_hull_candidates", "bdm_field_init", "bdm_diffuse", "bdm_soma_step",
+    "bdm_strerror", "bdm_last_error",
 )
 MAX_SLOTS, SLOT_ALIGN, BOX_ALIGN = 4096, 1024, 64
 
@@ -60,7 +61,8 @@ class Params(C.Structure):
                 ("p_inf", C.c_double), ("p_rec", C.c_double), ("walk", C.c_double),
                 ("grow", C.c_double), ("div_d", C.c_double), ("half_cbrt", C.c_double),
                 ("seed", C.c_uint64), ("salt", C.c_uint64), ("skip_static", C.c_int32),
-                ("p_apo", C.c_double), ("migrate", C.c_double)]
+                ("p_apo", C.c_double), ("migrate", C.c_double), ("diff_D", C.c_double),
+                ("diff_decay", C.c_double), ("secrete", C.c_double), ("chemo_speed", C.c_double)]
 
 
 class Gen(C.Structure):
@@ -77,6 +79,12 @@ class Workspace(C.Structure):
 class BatchRec(C.Structure):
     _fields_ = [("ptr", C.c_void_p), ("bytes", C.c_size_t), ("capacity", C.c_int64),
                 ("max_boxes", C.c_int64), ("slots", C.c_int32), ("grid_cap", C.c_int32)]
+
+
+class FieldRec(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("x0", C.c_double),
+                ("y0", C.c_double), ("z0", C.c_double), ("h", C.c_double), ("c", C.c_void_p),
+                ("c_next", C.c_void_p), ("count", C.c_void_p)]
 
 
 class GridDesc(C.Structure):
@@ -116,6 +124,9 @@ def _load():
         "bdm_batch_slot_status": ([P, C.c_int32, P, P, P], C.c_int),
         "bdm_extreme_points": ([P, P, C.c_int32, P, P, P], C.c_int),
         "bdm_hull_candidates": ([P, P, C.c_int32, C.c_double, P, C.c_int64, P, P], C.c_int),
+        "bdm_field_init": ([P, P], C.c_int),
+        "bdm_diffuse": ([P, P, P], C.c_int),
+        "bdm_soma_step": ([P, P, P, P, P], C.c_int),
         "bdm_strerror": ([C.c_int], C.c_char_p),
         "bdm_last_error": ([], C.c_char_p),
     }
@@ -157,9 +168,10 @@ def _ref(s):
 def params(k=2.0, gamma=1.0, dt=0.01, max_disp=3.0, box=0.0, force_bits=64, periodic=0, L=0.0,
            r_inf=0.0, p_inf=0.0, p_rec=0.0, walk=0.0, grow=1.05 ** (1.0 / 3.0), div_d=14.0,
            half_cbrt=0.5 ** (1.0 / 3.0), seed=0, salt=0, skip_static=0, p_apo=0.0,
-           migrate=0.0) -> Params:
+           migrate=0.0, diff_D=0.0, diff_decay=0.0, secrete=0.0, chemo_speed=0.0) -> Params:
     return Params(k, gamma, dt, max_disp, box, force_bits, periodic, L, r_inf, p_inf, p_rec,
-                  walk, grow, div_d, half_cbrt, seed, salt, skip_static, p_apo, migrate)
+                  walk, grow, div_d, half_cbrt, seed, salt, skip_static, p_apo, migrate, diff_D,
+                  diff_decay, secrete, chemo_speed)
 
 
 def gen(kind=GEN_CUBE, n=0, L=200.0, dlo=10.0, dhi=15.0, adh=0.4, n_infected=0, seed=0,
@@ -358,6 +370,48 @@ def hull_candidates(soa: Soa, planes: torch.Tensor, tol: float, out_slot: torch.
     _check(_lib.bdm_hull_candidates(_ref(soa), _ptr(planes), planes.shape[0], tol,
                                     _ptr(out_slot), out_slot.numel(), _ptr(out_count), _stream(stream)),
            "hull_candidates")
+
+
+class Field:
+    """Two substances on an nx*ny*nz voxel grid (device tensors c, c_next, count; see bdm_field).
+    `step` runs bdm_soma_step and swaps c and c_next; `diffuse` runs bdm_diffuse and swaps."""
+
+    def __init__(self, nx: int, ny: int, nz: int, h: float, origin=(0.0, 0.0, 0.0), device="cuda"):
+        V = int(nx) * int(ny) * int(nz)
+        self.dims, self.h, self.origin, self.V = (int(nx), int(ny), int(nz)), float(h), tuple(origin), V
+        self.c = torch.zeros(2 * V, dtype=torch.float64, device=device)
+        self.c_next = torch.zeros(2 * V, dtype=torch.float64, device=device)
+        self.count = torch.zeros(2 * V, dtype=torch.int32, device=device)
+        field_init(self.rec())
+
+    def rec(self) -> FieldRec:
+        return FieldRec(*self.dims, *self.origin, self.h, _ptr(self.c), _ptr(self.c_next), _ptr(self.count))
+
+    def swap(self):
+        self.c, self.c_next = self.c_next, self.c
+
+    def load(self, values):
+        self.c.copy_(torch.as_tensor(values, dtype=torch.float64))
+
+    def diffuse(self, p: Params, stream=None):
+        diffuse(self.rec(), p, stream)
+        self.swap()
+
+    def step(self, soa: Soa, p: Params, ws: Workspace, stream=None):
+        soma_step(soa, p, self.rec(), ws, stream)
+        self.swap()
+
+
+def field_init(f: FieldRec, stream=None):
+    _check(_lib.bdm_field_init(_ref(f), _stream(stream)), "field_init")
+
+
+def diffuse(f: FieldRec, p: Params, stream=None):
+    _check(_lib.bdm_diffuse(_ref(f), _ref(p), _stream(stream)), "diffuse")
+
+
+def soma_step(soa: Soa, p: Params, f: FieldRec, ws: Workspace, stream=None):
+    _check(_lib.bdm_soma_step(_ref(soa), _ref(p), _ref(f), _ref(ws), _stream(stream)), "soma_step")
 
 
 def fp_probe(a: torch.Tensor, b: torch.Tensor, stream=None):

@@ -200,6 +200,34 @@ int check_oncology_params(const bdm_params *p) {
     return BDM_OK;
 }
 
+int check_field(const bdm_field *f, bdm::FieldDev *out) {
+    if (!f) return fail(BDM_EINVAL, "field is NULL");
+    const int32_t lim = 1 << 20;
+    if (f->nx < 1 || f->ny < 1 || f->nz < 1 || f->nx > lim || f->ny > lim || f->nz > lim)
+        return fail(BDM_EINVAL, "field voxels per axis must be in [1, 2^20]");
+    const int64_t V = int64_t(f->nx) * f->ny * f->nz;
+    if (V > (int64_t(1) << 30)) return fail(BDM_EINVAL, "field has more than 2^30 voxels");
+    if (!(f->h > 0.0) || !is_fin(f->h) || !is_fin(f->x0) || !is_fin(f->y0) || !is_fin(f->z0))
+        return fail(BDM_EINVAL, "field corner must be finite and h > 0");
+    if (!f->c || !f->c_next || !f->count) return fail(BDM_EINVAL, "field arrays c, c_next and count are required");
+    const char *a = reinterpret_cast<const char *>(f->c), *b = reinterpret_cast<const char *>(f->c_next);
+    const size_t bytes = size_t(2 * V) * sizeof(double);
+    if (a < b + bytes && b < a + bytes) return fail(BDM_EINVAL, "c and c_next overlap");
+    *out = bdm::FieldDev{f->nx, f->ny, f->nz, f->x0, f->y0, f->z0, f->h, V};
+    return BDM_OK;
+}
+
+int diffusion_coefficients(const bdm_params *p, double h, double *lam, double *kdec) {
+    if (!p) return fail(BDM_EINVAL, "params is NULL");
+    if (!(p->dt > 0.0) || !is_fin(p->dt)) return fail(BDM_EINVAL, "dt must be > 0");
+    *lam = (p->diff_D * p->dt) / (h * h);
+    *kdec = p->diff_decay * p->dt;
+    if (!(*lam >= 0.0) || !(*lam <= 1.0 / 6.0))
+        return fail(BDM_EINVAL, "diff_D*dt/h^2 = %g outside [0, 1/6]", *lam);
+    if (!(*kdec >= 0.0) || !(*kdec <= 1.0)) return fail(BDM_EINVAL, "diff_decay*dt = %g outside [0, 1]", *kdec);
+    return BDM_OK;
+}
+
 int read_grid(const bdm::GridDev *src, bdm::GridDev *dst, hipStream_t st) {
     if (hipMemcpyAsync(dst, src, sizeof *dst, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
@@ -235,11 +263,13 @@ int bdm_generate(const bdm_soa *soa, const bdm_gen *gen, void *stream) {
     if (gen->n < 0 || gen->n > soa->capacity)
         return fail(BDM_EINVAL, "gen n %lld outside [0, capacity]", (long long)gen->n);
     if (gen->n > (int64_t(1) << 32) - 2) return fail(BDM_EINVAL, "at most 2^32 - 2 agents");
-    if (gen->kind != BDM_GEN_CUBE && gen->kind != BDM_GEN_BALL && gen->kind != BDM_GEN_SIR)
+    if (gen->kind != BDM_GEN_CUBE && gen->kind != BDM_GEN_BALL && gen->kind != BDM_GEN_SIR &&
+        gen->kind != BDM_GEN_SOMA)
         return fail(BDM_EINVAL, "unknown generator kind %d", gen->kind);
     if (!is_fin(gen->L) || !is_fin(gen->dlo) || !is_fin(gen->dhi) || !is_fin(gen->adh))
         return fail(BDM_EINVAL, "generator parameters must be finite");
-    if (gen->kind == BDM_GEN_SIR && !soa->state) return fail(BDM_EINVAL, "SIR generator needs state");
+    if ((gen->kind == BDM_GEN_SIR || gen->kind == BDM_GEN_SOMA) && !soa->state)
+        return fail(BDM_EINVAL, "SIR and soma generators need state");
     bdm::GenArgs a{gen->kind, gen->n, gen->L, gen->dlo, gen->dhi, gen->adh, gen->n_infected, gen->seed, gen->salt};
     bdm::launch_generate(*soa, a, as_stream(stream));
     return hip_check("generate launch");
@@ -490,6 +520,66 @@ int bdm_hull_candidates(const bdm_soa *soa, const double *planes, int32_t nplane
     if (rc) return rc;
     bdm::launch_hull_keep(*soa, planes, nplane, tol, out_slot, max_out, out_count, as_stream(stream));
     return hip_check("hull_candidates launch");
+}
+
+int bdm_field_init(const bdm_field *field, void *stream) {
+    g_last_error.clear();
+    bdm::FieldDev f;
+    int rc = check_field(field, &f);
+    if (rc) return rc;
+    rc = check_device();
+    if (rc) return rc;
+    bdm::launch_field_fill(field->c, field->count, 2 * f.V, as_stream(stream));
+    return hip_check("field_init launch");
+}
+
+int bdm_diffuse(const bdm_field *field, const bdm_params *params, void *stream) {
+    g_last_error.clear();
+    bdm::FieldDev f;
+    int rc = check_field(field, &f);
+    if (rc) return rc;
+    double lam = 0.0, kdec = 0.0;
+    rc = diffusion_coefficients(params, f.h, &lam, &kdec);
+    if (rc) return rc;
+    rc = check_device();
+    if (rc) return rc;
+    bdm::launch_diffuse(f, field->c, field->c_next, lam, kdec, as_stream(stream));
+    return hip_check("diffuse launch");
+}
+
+int bdm_soma_step(const bdm_soa *soa, const bdm_params *params, const bdm_field *field, const bdm_workspace *ws,
+                  void *stream) {
+    g_last_error.clear();
+    bdm::Ws w;
+    int rc = get_ws(ws, &w);
+    if (rc) return rc;
+    if (!params) return fail(BDM_EINVAL, "params is NULL");
+    rc = check_soa(soa, w.lay.capacity, true, true);
+    if (rc) return rc;
+    rc = check_mech_params(params);
+    if (rc) return rc;
+    bdm::FieldDev f;
+    rc = check_field(field, &f);
+    if (rc) return rc;
+    double lam = 0.0, kdec = 0.0;
+    rc = diffusion_coefficients(params, f.h, &lam, &kdec);
+    if (rc) return rc;
+    if (!is_fin(params->secrete)) return fail(BDM_EINVAL, "secrete must be finite");
+    if (!(params->chemo_speed >= 0.0) || !is_fin(params->chemo_speed))
+        return fail(BDM_EINVAL, "chemo_speed must be finite and >= 0");
+    hipStream_t st = as_stream(stream);
+    bdm::launch_secrete(*soa, soa->capacity, f, field->count, field->c, params->secrete, st);
+    bdm::launch_diffuse(f, field->c, field->c_next, lam, kdec, st);
+    bdm::launch_chemotaxis(*soa, soa->capacity, f, field->c_next, params->chemo_speed, st);
+    rc = hip_check("substance launches");
+    if (rc) return rc;
+    bdm::SlotDev rec = slot_record(params, 0, soa->capacity, 0, w.lay.max_boxes, 1, true);
+    rec.skip = 0;
+    bdm::launch_grid_build(*soa, plain_slots(w, rec), soa->capacity, false, w, st);
+    rc = hip_check("grid_build launch");
+    if (rc) return rc;
+    bdm::launch_mech(*soa, plain_slots(w, rec), soa->capacity, params->force_bits, false, w, st);
+    return hip_check("mech_step launch");
 }
 
 int bdm_status(const bdm_workspace *ws, uint32_t *flags, int32_t clear, void *stream) {

@@ -4,6 +4,7 @@
 // by (seed, salt); u = (word >> 11) * 2^-53.  Cube: words 0..2 give x, y, z = L*u, word 3 the
 // diameter dlo + (dhi - dlo)*u.  Ball: v = 2u - 1 per axis, accepted when |v|^2 <= 1 (at most 64
 // attempts, else the origin), position L*v.  SIR: cube positions, state 1 for id < n_infected.
+// Soma: cube positions and diameters, cell type (state) id mod 2.
 // The paper places tumour cells in a ball (Sec. 3.2) and persons at random in a cube (Sec. 3.3).
 #include "kernels.hpp"
 
@@ -44,7 +45,12 @@ __global__ __launch_bounds__(kBlock) void k_generate(bdm_soa s, GenArgs a) {
     if (s.fy) s.fy[i] = 0.0;
     if (s.fz) s.fz[i] = 0.0;
     s.id[i] = uint32_t(i);
-    if (s.state) s.state[i] = (a.kind == BDM_GEN_SIR && i < a.n_infected) ? 1 : 0;
+    if (s.state) {
+        uint8_t st = 0;
+        if (a.kind == BDM_GEN_SIR && i < a.n_infected) st = 1;
+        if (a.kind == BDM_GEN_SOMA) st = uint8_t(i & 1);
+        s.state[i] = st;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_fp_probe(const double *a, const double *b, int64_t n,

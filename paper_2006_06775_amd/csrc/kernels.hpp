@@ -42,6 +42,13 @@ struct MigArgs {
     uint64_t seed, salt, step;
 };
 
+// A substance grid: nx*ny*nz voxels of edge h from (x0, y0, z0), V voxels per substance.
+struct FieldDev {
+    int32_t nx, ny, nz;
+    double x0, y0, z0, h;
+    int64_t V;
+};
+
 struct GenArgs {
     int32_t kind;
     int64_t n;
@@ -86,6 +93,14 @@ void launch_extreme_points(const bdm_soa &s, const double *dirs, int32_t ndir, u
                            int32_t *out_slot, hipStream_t st);
 void launch_hull_keep(const bdm_soa &s, const double *planes, int32_t nplane, double tol, int32_t *out_slot,
                       int64_t max_out, int64_t *out_count, hipStream_t st);
+// Substances: secretion into c (counters left at zero), one diffusion step of both substances
+// cin -> cout, chemotaxis along c, zero fill of c and the counters.
+void launch_secrete(const bdm_soa &s, int64_t capacity, const FieldDev &f, uint32_t *count, double *c, double q,
+                    hipStream_t st);
+void launch_diffuse(const FieldDev &f, const double *cin, double *cout, double lam, double kdec, hipStream_t st);
+void launch_chemotaxis(const bdm_soa &s, int64_t capacity, const FieldDev &f, const double *c, double speed,
+                       hipStream_t st);
+void launch_field_fill(double *c, uint32_t *count, int64_t len, hipStream_t st);
 void launch_batch_advance(const Ws &w, hipStream_t st);
 void launch_set_slot(const Ws &w, int32_t slot, const SlotDev &rec, int64_t first_tile, int64_t ntile,
                      int32_t value, hipStream_t st);
