@@ -24,6 +24,8 @@
  *   - Extracellular substances [Sec. 2.1]: an explicit diffusion step with decay on a voxel grid
  *     (a standalone operation), secretion and chemotaxis (agent behaviours), and the soma-
  *     clustering model built from them [Sec. 3.4 benchmark].
+ *   - Cylinder geometry of neurite elements [Sec. 2.2]: sphere-cylinder and cylinder-cylinder
+ *     contacts through the closest points of the bodies' axes, on the same grid.
  *   - Counter-based Philox4x64-10 random numbers (Salmon, Moraes, Dror, Shaw, SC'11).
  *
  * Where the paper is silent the readings are fixed as follows (each one is restated at the
@@ -942,4 +944,190 @@ int orc_soma_step(int64_t n, double *x, double *y, double *z, const double *d, c
     rc = orc_chemotaxis(f, n, x, y, z, type, c_next, p->speed);
     if (rc) return rc;
     return orc_mech_step(n, x, y, z, d, adh, &p->mech, fx, fy, fz, NULL, NULL);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Cylinder geometry: neurite elements [Sec. 2.2, neuroscience module]                        */
+/* ------------------------------------------------------------------------------------------ */
+/* A neurite element is a cylinder from its proximal end p to its distal end q, where its point
+ * mass sits; its agent position is q.  Spheres and cylinders share the grid: an agent's grid
+ * diameter is the diameter of the smallest sphere about its position that holds its whole
+ * geometry (a sphere's own diameter; 2|q - p| + dc for a cylinder of diameter dc), so the box
+ * edge (the largest grid diameter) still finds every contact in the 27 boxes.
+ *
+ * Contact geometry: the closest points of the two bodies' axes (a sphere's axis is its centre)
+ * carry virtual spheres of the bodies' diameters, and the sphere-sphere law acts between them.
+ * A cylinder's point mass takes the share t of the force, t in [0, 1] being the position of its
+ * closest point along p -> q (1 at the distal end); the remainder would act on its proximal end,
+ * which belongs to the element it grows from and does not move in this step. */
+enum { GEOM_SPHERE = 0, GEOM_CYLINDER = 1 };
+
+static double dot3(const double a[3], const double b[3]) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
+
+static double clamp01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
+
+/* Parameter t in [0, 1] of the point of segment p -> q closest to c: t = ((c - p).d)/(d.d),
+ * d = q - p, clamped.  A segment of length 0 is its distal point: t = 1. */
+double orc_segment_point_param(const double p[3], const double q[3], const double c[3])
+{
+    double d[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
+    double w[3] = {c[0] - p[0], c[1] - p[1], c[2] - p[2]};
+    double a = dot3(d, d);
+    if (!(a > 0.0)) return 1.0;
+    return clamp01(dot3(w, d) / a);
+}
+
+/* Parameters (s, t) of the closest points of segments p1 -> q1 and p2 -> q2, from minimising
+ * |p1 + s d1 - p2 - t d2|^2 over [0, 1]^2: with r = p1 - p2, a = d1.d1, e = d2.d2, b = d1.d2,
+ * c = d1.r, f = d2.r, the unconstrained s = (b f - c e)/(a e - b^2) is clamped, t = (b s + f)/e
+ * follows, and when t leaves [0, 1] it is clamped and s recomputed for that t.  Segments within
+ * an angle of about 1e-6 rad of parallel (a e - b^2 <= 2^-40 a e) start from s = 0.  A segment
+ * of length 0 is its distal point (parameter 1). */
+void orc_segment_segment_params(const double p1[3], const double q1[3], const double p2[3],
+                                const double q2[3], double *s_out, double *t_out)
+{
+    double d1[3] = {q1[0] - p1[0], q1[1] - p1[1], q1[2] - p1[2]};
+    double d2[3] = {q2[0] - p2[0], q2[1] - p2[1], q2[2] - p2[2]};
+    double r[3] = {p1[0] - p2[0], p1[1] - p2[1], p1[2] - p2[2]};
+    double a = dot3(d1, d1), e = dot3(d2, d2), f = dot3(d2, r);
+    double s = 0.0, t = 0.0;
+    if (!(a > 0.0) && !(e > 0.0)) {
+        s = 1.0; t = 1.0;
+    } else if (!(a > 0.0)) {
+        s = 1.0; t = clamp01(f / e);
+    } else {
+        double c = dot3(d1, r);
+        if (!(e > 0.0)) {
+            t = 1.0; s = clamp01(-c / a);
+        } else {
+            double b = dot3(d1, d2);
+            double ae = a * e;
+            double denom = ae - b * b;
+            s = denom > 0x1.0p-40 * ae ? clamp01((b * f - c * e) / denom) : 0.0;
+            double tn = b * s + f;
+            if (tn < 0.0) {
+                t = 0.0; s = clamp01(-c / a);
+            } else if (tn > e) {
+                t = 1.0; s = clamp01((b - c) / a);
+            } else {
+                t = tn / e;
+            }
+        }
+    }
+    *s_out = s; *t_out = t;
+}
+
+/* Grid diameter of a cylinder from p to q of diameter dc: 2|q - p| + dc. */
+double orc_cylinder_reach(const double p[3], const double q[3], double dc)
+{
+    double d[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
+    return 2.0 * sqrt(dot3(d, d)) + dc;
+}
+
+/* Force on body i from body j.  Body = (kind, position x = centre or distal end, diameter d of a
+ * sphere, proximal end p and diameter dc of a cylinder).  Returns 1 on contact and writes the
+ * force on i (for a cylinder: the share that acts on its point mass). */
+int orc_geom_pair(int kind_i, const double xi[3], double di, const double pi_[3], double dci,
+                  int kind_j, const double xj[3], double dj, const double pj[3], double dcj,
+                  double k, double gamma, double out[3])
+{
+    double ci[3], cj[3], Di, Dj, share = 1.0;
+    if (kind_i == GEOM_CYLINDER && kind_j == GEOM_CYLINDER) {
+        double s, t;
+        orc_segment_segment_params(pi_, xi, pj, xj, &s, &t);
+        for (int a = 0; a < 3; ++a) {
+            ci[a] = pi_[a] + s * (xi[a] - pi_[a]);
+            cj[a] = pj[a] + t * (xj[a] - pj[a]);
+        }
+        Di = dci; Dj = dcj; share = s;
+    } else if (kind_i == GEOM_CYLINDER) {
+        double s = orc_segment_point_param(pi_, xi, xj);
+        for (int a = 0; a < 3; ++a) {
+            ci[a] = pi_[a] + s * (xi[a] - pi_[a]);
+            cj[a] = xj[a];
+        }
+        Di = dci; Dj = dj; share = s;
+    } else if (kind_j == GEOM_CYLINDER) {
+        double t = orc_segment_point_param(pj, xj, xi);
+        for (int a = 0; a < 3; ++a) {
+            ci[a] = xi[a];
+            cj[a] = pj[a] + t * (xj[a] - pj[a]);
+        }
+        Di = di; Dj = dcj;
+    } else {
+        for (int a = 0; a < 3; ++a) { ci[a] = xi[a]; cj[a] = xj[a]; }
+        Di = di; Dj = dj;
+    }
+    int hit = orc_pair_force_f64(ci[0], ci[1], ci[2], Di, cj[0], cj[1], cj[2], Dj, k, gamma, out);
+    out[0] = share * out[0]; out[1] = share * out[1]; out[2] = share * out[2];
+    return hit;
+}
+
+/* One mechanical step of spheres and cylinders (binary64 law).  kind[i] = 1 marks a cylinder
+ * whose proximal end and diameter are (px, py, pz)[i], dc[i]; every other kind is a sphere of
+ * diameter d[i].  First each cylinder's d[i] is set to its grid diameter (orc_cylinder_reach),
+ * then the grid is built.  Forces are summed in ascending (key, id) candidate order from +0.0;
+ * the gate, the clamp and the synchronous update are those of the sphere step; a cylinder moves
+ * its distal end only.  fx/fy/fz receive the summed forces (on a cylinder's point mass);
+ * ncontact (optional) each agent's contact count. */
+int orc_geom_step(int64_t n, double *x, double *y, double *z, double *d, const double *adh,
+                  const uint8_t *kind, const double *px, const double *py, const double *pz,
+                  const double *dc, const orc_mech_params *p, double *fx, double *fy, double *fz,
+                  uint32_t *ncontact)
+{
+    int rc = check_mech_params(p);
+    if (rc) return rc;
+    if (p->force_bits != 64) return ORC_EINVAL;
+    if (n == 0) return ORC_OK;
+    for (int64_t i = 0; i < n; ++i) {
+        if (kind[i] != GEOM_CYLINDER) continue;
+        double q[3] = {x[i], y[i], z[i]}, pp[3] = {px[i], py[i], pz[i]};
+        d[i] = orc_cylinder_reach(pp, q, dc[i]);
+    }
+    orc_grid g;
+    rc = orc_grid_setup(n, x, y, z, d, p->box, 0, 0.0, p->max_boxes, &g);
+    if (rc) return rc;
+    uint32_t *key = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+    uint32_t *order = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+    uint32_t *start = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(g.nboxes + 1));
+    if (!key || !order || !start) { free(key); free(order); free(start); return ORC_ENOMEM; }
+    rc = orc_grid_sort(n, x, y, z, &g, key, order, start);
+    for (int64_t i = 0; i < n && !rc; ++i) {
+        int ki = kind[i] == GEOM_CYLINDER ? GEOM_CYLINDER : GEOM_SPHERE;
+        double xi[3] = {x[i], y[i], z[i]}, pi_[3] = {px[i], py[i], pz[i]};
+        int64_t cx = box_coord(&g, x[i], 0), cy = box_coord(&g, y[i], 1), cz = box_coord(&g, z[i], 2);
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        uint32_t contacts = 0;
+        for (int oz = -1; oz <= 1; ++oz)
+            for (int oy = -1; oy <= 1; ++oy)
+                for (int ox = -1; ox <= 1; ++ox) {
+                    int64_t nk = neighbour_key(&g, cx, cy, cz, ox, oy, oz);
+                    if (nk < 0) continue;
+                    for (uint32_t s = start[nk]; s < start[nk + 1]; ++s) {
+                        uint32_t j = order[s];
+                        if ((int64_t)j == i) continue;
+                        int kj = kind[j] == GEOM_CYLINDER ? GEOM_CYLINDER : GEOM_SPHERE;
+                        double xj[3] = {x[j], y[j], z[j]}, pj[3] = {px[j], py[j], pz[j]};
+                        double f[3];
+                        if (orc_geom_pair(ki, xi, d[i], pi_, dc[i], kj, xj, d[j], pj, dc[j], p->k,
+                                          p->gamma, f)) {
+                            contacts += 1;
+                            sx = sx + f[0]; sy = sy + f[1]; sz = sz + f[2];
+                        }
+                    }
+                }
+        fx[i] = sx; fy[i] = sy; fz[i] = sz;
+        if (ncontact) ncontact[i] = contacts;
+    }
+    if (!rc) {
+        for (int64_t i = 0; i < n; ++i) {
+            double disp[3];
+            if (orc_displacement(fx[i], fy[i], fz[i], adh[i], p->dt, p->max_disp, disp) == 1) continue;
+            x[i] = x[i] + disp[0];
+            y[i] = y[i] + disp[1];
+            z[i] = z[i] + disp[2];
+        }
+    }
+    free(key); free(order); free(start);
+    return rc;
 }

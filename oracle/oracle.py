@@ -136,12 +136,23 @@ def _declare(L):
     L.orc_chemotaxis.argtypes = [_F, C.c_int64, _D, _D, _D, _U8, _D, C.c_double]
     L.orc_soma_step.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _U8, _F, _D, _D,
                                 C.POINTER(_SomaParams), _D, _D, _D]
+    _V3 = C.POINTER(C.c_double)
+    L.orc_segment_point_param.argtypes = [_V3, _V3, _V3]
+    L.orc_segment_point_param.restype = C.c_double
+    L.orc_segment_segment_params.argtypes = [_V3, _V3, _V3, _V3, _D, _D]
+    L.orc_segment_segment_params.restype = None
+    L.orc_cylinder_reach.argtypes = [_V3, _V3, C.c_double]
+    L.orc_cylinder_reach.restype = C.c_double
+    L.orc_geom_pair.argtypes = [C.c_int, _V3, C.c_double, _V3, C.c_double, C.c_int, _V3, C.c_double, _V3,
+                                C.c_double, C.c_double, C.c_double, _D]
+    L.orc_geom_step.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _U8, _D, _D, _D, _D, C.POINTER(_MechParams),
+                                _D, _D, _D, _U32]
     L.orc_sir_step.argtypes = [C.c_int64, _D, _D, _D, _U8, C.POINTER(_SirParams), C.c_int64, _I64]
     for name in ("orc_generate_cube", "orc_generate_ball", "orc_generate_sir", "orc_grid_setup",
                  "orc_grid_sort", "orc_pair_force_f64", "orc_pair_force_f32", "orc_displacement",
                  "orc_mech_step", "orc_mech_sample", "orc_contacts", "orc_grow_divide", "orc_spheroid_step",
                  "orc_apoptosis", "orc_migrate", "orc_oncology_step", "orc_sir_step", "orc_diffuse",
-                 "orc_secrete", "orc_chemotaxis", "orc_soma_step"):
+                 "orc_secrete", "orc_chemotaxis", "orc_soma_step", "orc_geom_pair", "orc_geom_step"):
         getattr(L, name).restype = C.c_int
 
 
@@ -501,3 +512,53 @@ def soma_step(state, f: _Field, c, params: _SomaParams):
                                _p(c, C.c_double), _p(c_next, C.c_double), C.byref(params),
                                _p(fx, C.c_double), _p(fy, C.c_double), _p(fz, C.c_double)), "soma_step")
     return c_next, fx, fy, fz
+
+
+# ---------------------------------------------------------------------------------------------
+# Cylinder geometry (neurite elements)
+# ---------------------------------------------------------------------------------------------
+GEOM_SPHERE, GEOM_CYLINDER = 0, 1
+
+
+def segment_point_param(p, q, c) -> float:
+    p, q, c = (_f64(v) for v in (p, q, c))
+    return float(lib().orc_segment_point_param(_p(p, C.c_double), _p(q, C.c_double), _p(c, C.c_double)))
+
+
+def segment_segment_params(p1, q1, p2, q2):
+    a = [_f64(v) for v in (p1, q1, p2, q2)]
+    s, t = np.zeros(1), np.zeros(1)
+    lib().orc_segment_segment_params(*(_p(v, C.c_double) for v in a), _p(s, C.c_double), _p(t, C.c_double))
+    return float(s[0]), float(t[0])
+
+
+def cylinder_reach(p, q, dc) -> float:
+    p, q = _f64(p), _f64(q)
+    return float(lib().orc_cylinder_reach(_p(p, C.c_double), _p(q, C.c_double), dc))
+
+
+def geom_pair(kind_i, xi, di, pi, dci, kind_j, xj, dj, pj, dcj, k=2.0, gamma=1.0):
+    """(hit, force on i) between body i and body j."""
+    xi, pi, xj, pj = (_f64(v) for v in (xi, pi, xj, pj))
+    out = np.zeros(3)
+    hit = lib().orc_geom_pair(kind_i, _p(xi, C.c_double), di, _p(pi, C.c_double), dci, kind_j,
+                              _p(xj, C.c_double), dj, _p(pj, C.c_double), dcj, k, gamma, _p(out, C.c_double))
+    return bool(hit), out
+
+
+def geom_step(state, k=2.0, gamma=1.0, dt=0.01, max_disp=3.0, box=0.0, max_boxes=1 << 31):
+    """One mechanical step of spheres and cylinders, in place on state['x'|'y'|'z'|'d'] (keys
+    also 'adh', 'state' = kind, 'px', 'py', 'pz', 'dc').  Returns (fx, fy, fz, ncontact)."""
+    for key in ("x", "y", "z", "d", "adh", "px", "py", "pz", "dc"):
+        state[key] = _f64(state[key])
+    state["state"] = np.ascontiguousarray(state["state"], dtype=np.uint8)
+    n = len(state["x"])
+    p = mech_params(k, gamma, dt, max_disp, box, 64, max_boxes)
+    fx, fy, fz = _zeros(n), _zeros(n), _zeros(n)
+    nc = _zeros(n, np.uint32)
+    _check(lib().orc_geom_step(n, *(_p(state[k_], C.c_double) for k_ in ("x", "y", "z", "d", "adh")),
+                               _p(state["state"], C.c_uint8),
+                               *(_p(state[k_], C.c_double) for k_ in ("px", "py", "pz", "dc")), C.byref(p),
+                               _p(fx, C.c_double), _p(fy, C.c_double), _p(fz, C.c_double), _p(nc, C.c_uint32)),
+           "geom_step")
+    return fx, fy, fz, nc
