@@ -314,6 +314,30 @@ def workloads():
                                      scope="k_diffuse, both substances, one launch")))
     del pop, fld
     torch.cuda.empty_cache()
+    # spheres and cylinders (neurite elements): 2^20 agents, 20 % spheres d in [10, 15), 80 %
+    # cylinders of length [4, 8) and diameter [1, 2), in an 800 um cube; binary64 law
+    from paper_2006_06775_amd import synth
+    n = 1 << 20
+    s = synth.neurite_mix(n, 800.0, seed=0)
+    pop = bdm.Population(n, 1 << 22, with_state=True)
+    pop.load({k: s[k] for k in ("x", "y", "z", "d", "adh", "state")})
+    cyl = bdm.Cylinders(n)
+    cyl.load(s)
+    del s
+    crec, p_geom = cyl.rec(), bdm.params()
+    counts = torch.zeros(n, dtype=torch.int32, device="cuda")
+    bdm.geom_step(pop.soa, crec, p_geom, pop.ws, counts)  # warm-up (and box-sorted order)
+    contacts = int(counts.sum().item())
+
+    def geom(step):
+        bdm.geom_step(pop.soa, crec, p_geom, pop.ws)
+    steps = 20
+    t = timed_steps(torch, geom, steps)
+    out["neurites"] = dict(agents=n, cylinders_fraction=0.8, steps=steps, seconds=t, steps_per_s=steps / t,
+                           agent_updates_per_s=n * steps / t, contacts_per_agent=round(contacts / n, 3),
+                           flags=bdm.status(pop.ws), precision="fp64")
+    del pop, cyl, counts
+    torch.cuda.empty_cache()
     # SIR: 10^7 points in a periodic 5000^3 cube, box 20 (250^3 boxes), radius 2, p_inf 0.3,
     # p_rec 0.01, walk 1, 0.1 % infected, 200 steps
     n, L, steps = 10_000_000, 5000.0, 200

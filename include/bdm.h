@@ -305,6 +305,37 @@ int bdm_diffuse(const bdm_field *field, const bdm_params *params, void *stream);
 int bdm_soma_step(const bdm_soa *soa, const bdm_params *params, const bdm_field *field,
                   const bdm_workspace *ws, void *stream);
 
+/* Spheres and cylinders [paper Sec. 2.2: the neuroscience module's neurite elements are
+ * cylinders, each a spring with a point mass at its distal end; Sec. 2.1: mechanical forces
+ * between agents found in the 27 boxes].  An agent with state 1 is a cylinder whose position
+ * (x, y, z) is its distal end q; its proximal end p and diameter dc are in the id-indexed arrays
+ * below.  Every other state is a sphere of diameter diam.
+ *
+ * bdm_geom_step: one mechanical step of such a population.
+ *   1. each cylinder's diam is set to its grid diameter 2|q - p| + dc (|v| = sqrt((vx*vx +
+ *      vy*vy) + vz*vz)), the diameter of the sphere about q that holds the whole cylinder;
+ *   2. grid build on x, y, z and diam, as bdm_grid_build (box = largest diam, or params->box);
+ *   3. forces: for each pair in contact, the closest points of the two axes (a sphere's axis is
+ *      its centre; segment p -> q parameters from the clamped stationary point of the squared
+ *      distance, re-clamped; segments within about 1e-6 rad of parallel start from parameter 0;
+ *      a segment of length 0 is its distal end) carry virtual spheres of the bodies' diameters,
+ *      and the sphere law of bdm_mech_step acts between them (contact iff delta > 0); a
+ *      cylinder's point mass takes the share s in [0, 1] of the force, s the position of its
+ *      closest point along p -> q; forces are summed in ascending (key, id) candidate order;
+ *   4. gate, clamp and synchronous move as bdm_mech_step; a cylinder moves its distal end (p and
+ *      dc do not change).
+ * Outputs as bdm_mech_step (box-sorted slots; fx, fy, fz = the summed forces on the point
+ * masses); counts (device uint32 per box-sorted slot, may be NULL) = each agent's contacts.
+ * params->force_bits must be 64.  Errors: BDM_EINVAL, BDM_ENOWS; device: as bdm_sim_step,
+ * BDM_FLAG_BADID for a cylinder id >= capacity. */
+typedef struct bdm_cylinders {
+    double *px, *py, *pz;  /* device, soa->capacity entries indexed by agent id: proximal ends */
+    double *dc;            /* device, indexed by agent id: cylinder diameters */
+} bdm_cylinders;
+
+int bdm_geom_step(const bdm_soa *soa, const bdm_cylinders *cyl, const bdm_params *params,
+                  const bdm_workspace *ws, uint32_t *counts, void *stream);
+
 /* Sticky status bits of the workspace into *flags (host); clears them when `clear` != 0.
  * Synchronises the stream.  Errors: BDM_ENOWS, BDM_EHIP. */
 int bdm_status(const bdm_workspace *ws, uint32_t *flags, int32_t clear, void *stream);

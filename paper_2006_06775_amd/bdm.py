@@ -32,6 +32,7 @@ SYMBOLS = (
     "bdm_batch_workspace_bytes", "bdm_batch_init", "bdm_batch_set_slot", "bdm_batch_clear_slot",
     "bdm_batch_step", "bdm_batch_step_traced", "bdm_batch_slot_status", "bdm_fp_probe",
     "bdm_extreme_points", "bdm_hull_candidates", "bdm_field_init", "bdm_diffuse", "bdm_soma_step",
+    "bdm_geom_step",
     "bdm_strerror", "bdm_last_error",
 )
 MAX_SLOTS, SLOT_ALIGN, BOX_ALIGN = 4096, 1024, 64
@@ -87,6 +88,10 @@ class FieldRec(C.Structure):
                 ("c_next", C.c_void_p), ("count", C.c_void_p)]
 
 
+class CylRec(C.Structure):
+    _fields_ = [("px", C.c_void_p), ("py", C.c_void_p), ("pz", C.c_void_p), ("dc", C.c_void_p)]
+
+
 class GridDesc(C.Structure):
     _fields_ = [("b", C.c_double), ("cmin", C.c_int32 * 3), ("dims", C.c_int32 * 3),
                 ("nboxes", C.c_int64), ("n", C.c_int64), ("valid", C.c_int32),
@@ -127,6 +132,7 @@ def _load():
         "bdm_field_init": ([P, P], C.c_int),
         "bdm_diffuse": ([P, P, P], C.c_int),
         "bdm_soma_step": ([P, P, P, P, P], C.c_int),
+        "bdm_geom_step": ([P, P, P, P, P, P], C.c_int),
         "bdm_strerror": ([C.c_int], C.c_char_p),
         "bdm_last_error": ([], C.c_char_p),
     }
@@ -412,6 +418,26 @@ def diffuse(f: FieldRec, p: Params, stream=None):
 
 def soma_step(soa: Soa, p: Params, f: FieldRec, ws: Workspace, stream=None):
     _check(_lib.bdm_soma_step(_ref(soa), _ref(p), _ref(f), _ref(ws), _stream(stream)), "soma_step")
+
+
+class Cylinders:
+    """Proximal ends and diameters of cylinder agents, by agent id (device tensors of capacity)."""
+
+    def __init__(self, capacity: int, device="cuda"):
+        f64 = dict(dtype=torch.float64, device=device)
+        self.t = {k: torch.zeros(max(int(capacity), 1), **f64) for k in ("px", "py", "pz", "dc")}
+
+    def load(self, arrays: dict):
+        for k, v in self.t.items():
+            src = torch.as_tensor(arrays[k], dtype=torch.float64)
+            v[:len(src)].copy_(src)
+
+    def rec(self) -> CylRec:
+        return CylRec(*(_ptr(self.t[k]) for k in ("px", "py", "pz", "dc")))
+
+
+def geom_step(soa: Soa, cyl: CylRec, p: Params, ws: Workspace, counts=None, stream=None):
+    _check(_lib.bdm_geom_step(_ref(soa), _ref(cyl), _ref(p), _ref(ws), _ptr(counts), _stream(stream)), "geom_step")
 
 
 def fp_probe(a: torch.Tensor, b: torch.Tensor, stream=None):

@@ -582,6 +582,33 @@ int bdm_soma_step(const bdm_soa *soa, const bdm_params *params, const bdm_field 
     return hip_check("mech_step launch");
 }
 
+int bdm_geom_step(const bdm_soa *soa, const bdm_cylinders *cyl, const bdm_params *params, const bdm_workspace *ws,
+                  uint32_t *counts, void *stream) {
+    g_last_error.clear();
+    bdm::Ws w;
+    int rc = get_ws(ws, &w);
+    if (rc) return rc;
+    if (!params) return fail(BDM_EINVAL, "params is NULL");
+    rc = check_soa(soa, w.lay.capacity, true, true);
+    if (rc) return rc;
+    rc = check_mech_params(params);
+    if (rc) return rc;
+    if (params->force_bits != 64) return fail(BDM_EINVAL, "the cylinder step uses the binary64 law (force_bits 64)");
+    if (!cyl || !cyl->px || !cyl->py || !cyl->pz || !cyl->dc)
+        return fail(BDM_EINVAL, "cylinder arrays px, py, pz and dc are required");
+    hipStream_t st = as_stream(stream);
+    const bdm::CylIn in{cyl->px, cyl->py, cyl->pz, cyl->dc};
+    bdm::launch_geom_reach(*soa, soa->capacity, in, st);
+    bdm::SlotDev rec = slot_record(params, 0, soa->capacity, 0, w.lay.max_boxes, 1, true);
+    rec.skip = 0;
+    bdm::launch_grid_build(*soa, plain_slots(w, rec), soa->capacity, false, w, st);
+    rc = hip_check("grid_build launch");
+    if (rc) return rc;
+    const bdm::GeomArgs a{params->k, params->gamma, params->dt, params->max_disp, soa->capacity};
+    bdm::launch_geom(*soa, in, a, w, counts, st);
+    return hip_check("geom_step launch");
+}
+
 int bdm_status(const bdm_workspace *ws, uint32_t *flags, int32_t clear, void *stream) {
     g_last_error.clear();
     bdm::Ws w;

@@ -49,6 +49,16 @@ struct FieldDev {
     int64_t V;
 };
 
+// Cylinder agents: proximal end and diameter by agent id.
+struct CylIn {
+    const double *px, *py, *pz, *dc;
+};
+
+struct GeomArgs {
+    double k, gamma, dt, max_disp;
+    int64_t capacity;  // entries of the cylinder arrays (ids beyond are rejected)
+};
+
 struct GenArgs {
     int32_t kind;
     int64_t n;
@@ -101,6 +111,10 @@ void launch_diffuse(const FieldDev &f, const double *cin, double *cout, double l
 void launch_chemotaxis(const bdm_soa &s, int64_t capacity, const FieldDev &f, const double *c, double speed,
                        hipStream_t st);
 void launch_field_fill(double *c, uint32_t *count, int64_t len, hipStream_t st);
+// Spheres and cylinders: grid diameters of the cylinders; the mechanical step after a grid build.
+void launch_geom_reach(const bdm_soa &s, int64_t capacity, const CylIn &cyl, hipStream_t st);
+void launch_geom(const bdm_soa &s, const CylIn &cyl, const GeomArgs &a, const Ws &w, uint32_t *counts,
+                 hipStream_t st);
 void launch_batch_advance(const Ws &w, hipStream_t st);
 void launch_set_slot(const Ws &w, int32_t slot, const SlotDev &rec, int64_t first_tile, int64_t ntile,
                      int32_t value, hipStream_t st);
