@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 TESTS = ["tests/test_oracle_rng.py", "tests/test_oracle_grid.py", "tests/test_oracle_mech.py",
          "tests/test_oracle_f32_law.py", "tests/test_oracle_spheroid.py", "tests/test_oracle_sir.py",
+         "tests/test_oracle_oncology.py", "tests/test_oracle_diffusion.py", "tests/test_oracle_geometry.py",
          "tests/test_pretest_record.py"]
 SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
 

@@ -159,8 +159,9 @@ class Server:
 
     @staticmethod
     def footprint_bytes(n: int, box: float = D_HI) -> int:
-        """HBM a request occupies: packed SoA (68 B/agent) + workspace (118 B/agent and 1/16 of a
-        64-byte partial) + per reserved box 4 B of box start and 8 B per bucket of 64 boxes."""
+        """HBM a request occupies: packed SoA (68 B/agent) + workspace (118 B/agent) + 4 B/agent
+        of margin (bounds partials, alignment) + per reserved box 4 B of box start, 1 B of
+        stationary mark and 12 B per bucket of 64 boxes."""
         return int(n * (68 + 118 + 4) + (5 + 12 / 64) * box_reserve(n, box))
 
     def box_of(self, req: Request) -> float:
