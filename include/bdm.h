@@ -112,7 +112,13 @@ typedef struct bdm_params {
  * (so it is gated again) and its position, bit for bit: results are identical with and without
  * skipping.  Precondition: between two skip_static steps the agents change only through the
  * library's mechanical steps (after bdm_generate or any other change, take one step with
- * skip_static = 0, or re-initialise the workspace).  The batched and spheroid steps ignore it. */
+ * skip_static = 0, or re-initialise the workspace).  The force law (k, gamma, force_bits) must
+ * also be unchanged for an agent to be skipped; after a change every agent walks again.  When
+ * the last step skipped every agent (so nothing moved), the step has nothing to change: with the
+ * same live count, force law and requested box edge, its grid build and neighbour walk return at
+ * once and the agents, forces and grid stay as they are (a mechanical step after such a build
+ * that asks for another force law sets BDM_FLAG_NOGRID and moves nothing).  The batched and
+ * spheroid steps ignore it. */
 
 /* Seeded initial state. */
 typedef struct bdm_gen {

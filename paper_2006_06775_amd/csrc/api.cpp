@@ -356,7 +356,7 @@ int sim_step(const bdm_soa *soa, int32_t model, const bdm_params *params, int64_
             rc = hip_check("migrate launch");
             if (rc) return rc;
         }
-        bdm::launch_grid_build(*soa, plain_slots(w, rec), soa->capacity, cells, w, st);
+        bdm::launch_grid_build(*soa, plain_slots(w, rec), soa->capacity, cells, w, st, trace == nullptr);
         rc = hip_check("grid_build launch");
         if (rc) return rc;
         bdm::launch_mech(*soa, plain_slots(w, rec), soa->capacity, params->force_bits, cells, w, st, trace);

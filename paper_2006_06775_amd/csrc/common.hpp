@@ -76,6 +76,9 @@ struct GridDev {
     int32_t mark_ready;             // the last plain step skipped stationary agents and marked its movers
     int32_t skip_ok;                // this build may skip stationary agents (same lattice, marks ready)
     int64_t skipped;                // agents the last skipping step skipped
+    double law_k, law_gamma, law_box;  // force law and requested box edge of the last build
+    int32_t law_bits;
+    int32_t frozen;                 // this build and its step are skipped whole (nothing moved)
 };
 static_assert(sizeof(GridDev) <= 256, "grid record must fit its slot");
 
@@ -83,6 +86,11 @@ static_assert(sizeof(GridDev) <= 256, "grid record must fit its slot");
 // 8-byte pre-test records, the same plus the binary32 copies (spheroid steps), or the periodic
 // (SIR) lattice, which writes no pre-test records.
 enum : int32_t { kGridNone = 0, kGridOpen = 1, kGridOpenF32 = 2, kGridPeriodic = 3, kGridOpenSkip = 4 };
+
+// A plain skipping build whose step changes nothing: the last step skipped every agent (so
+// none moved), and the force law, requested box edge and live count are the same.  Every kernel
+// of the build and of its mechanical step then leaves the workspace and the agents as they are.
+__device__ __forceinline__ bool frozen_plain(const GridDev *g, bool table) { return !table && g->frozen; }
 
 // Parameters and placement of one slot.
 struct SlotDev {

@@ -81,6 +81,9 @@ __device__ void clear_grid(GridDev *g) {
     g->kind = kGridNone;
     g->consumed = 0;
     g->mark_ready = 0;
+    g->law_k = g->law_gamma = g->law_box = 0.0;
+    g->law_bits = 0;
+    g->frozen = 0;
     g->skip_ok = 0;
     g->skipped = 0;
 }

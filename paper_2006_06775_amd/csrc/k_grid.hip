@@ -99,6 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_bounds(Slots sl, int64_t nbtiles, co
                                                    const double *__restrict__ z,
                                                    const double *__restrict__ d, double *partials,
                                                    unsigned long long *tiles, int64_t max_tiles) {
+    if (frozen_plain(&sl.grids[0], sl.table)) return;
     if (blockIdx.x == 0) {  // reset the scan tiles of the coming histogram scan
         for (int64_t t = threadIdx.x; t < max_tiles; t += blockDim.x) tiles[t] = 0ull;
         if (threadIdx.x == 0) {
@@ -116,6 +117,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Slots sl, const int64_t *n_
     if (slot >= sl.nslots) return;
     const SlotDev a = slot_record(sl, slot);
     GridDev *g = &sl.grids[slot];
+    if (frozen_plain(g, sl.table)) return;
     const int64_t n_raw = n_ptr[slot];
     const int64_t n = live_count(n_ptr, slot, a.capacity);
     const bool idle = a.steps_left <= 0 || a.capacity <= 0;
@@ -161,7 +163,13 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Slots sl, const int64_t *n_
     const double prev_b = g->b;
     const int32_t prev_cmin[3] = {g->cmin[0], g->cmin[1], g->cmin[2]};
     const int32_t prev_dims[3] = {g->dims[0], g->dims[1], g->dims[2]};
-    const bool marks = kind == kGridOpenSkip && g->mark_ready && g->valid && g->consumed && g->kind == kGridOpenSkip;
+    // (a skipped agent keeps its last force: the force law must be the same too)
+    const bool marks = kind == kGridOpenSkip && g->mark_ready && g->valid && g->consumed && g->kind == kGridOpenSkip &&
+                       g->law_k == a.k && g->law_gamma == a.gamma && g->law_bits == a.force_bits;
+    g->law_k = a.k;
+    g->law_gamma = a.gamma;
+    g->law_bits = a.force_bits;
+    g->law_box = a.box;
     g->mark_ready = 0;
     g->skip_ok = 0;
     g->sir_counts[0] = g->sir_counts[1] = g->sir_counts[2] = 0ull;
@@ -330,6 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_key_bucket(Slots sl, int64_t ntiles,
                                                        uint32_t *__restrict__ key,
                                                        uint32_t *__restrict__ brank, uint8_t *dirty,
                                                        const uint8_t *__restrict__ moved) {
+    if (frozen_plain(&sl.grids[0], sl.table)) return;
     const int lane = threadIdx.x & 63;
     const bool mark = dirty && sl.grids[0].skip_ok;
     const int64_t ngroups = (ntiles + kKeyTiles - 1) / kKeyTiles;
@@ -392,7 +401,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_prepare(unsigned long long *til
 // prefix).  Wavefront 0 looks back 64 predecessors at a time with ballots.
 __global__ __launch_bounds__(kBlock) void k_scan(uint32_t *in, uint32_t *out, const int64_t *len_ptr,
                                                  int64_t len_fixed, unsigned long long *tiles,
-                                                 uint32_t *ticket, int zero_in, GridDev *g) {
+                                                 uint32_t *ticket, int zero_in, GridDev *g, int32_t build) {
+    if (build && g->frozen) return;  // the bucket scan of a plain build that changes nothing
     __shared__ uint32_t s_tile, s_prefix;
     __shared__ uint32_t s_wave[kBlock / 64];
     int64_t len = len_fixed;  // a device-resident length never exceeds the arrays' length
@@ -511,6 +521,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_scatter(Slots sl, int64_t nti
                                                            const uint32_t *__restrict__ brank,
                                                            const uint32_t *__restrict__ bstart,
                                                            uint32_t *__restrict__ item, int64_t capacity) {
+    if (frozen_plain(&sl.grids[0], sl.table)) return;
     const int64_t ngroups = (ntiles + kKeyTiles - 1) / kKeyTiles;
     for (int64_t grp = xcd_tile(blockIdx.x, gridDim.x); grp < ngroups; grp += gridDim.x) {
         const int64_t tile = grp * kKeyTiles, t1 = ntiles;
@@ -697,6 +708,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(Slots sl, int64_t nbucke
                                                         uint32_t *__restrict__ grouped, uint32_t *__restrict__ grouped_i,
                                                         uint32_t *__restrict__ start, SortOut o, int periodic,
                                                         int64_t capacity, uint32_t *__restrict__ crowd) {
+    if (frozen_plain(&sl.grids[0], sl.table)) return;
     __shared__ uint32_t s_hist[kBlock / 64][kBucketBoxes];
     __shared__ uint32_t s_ls[kBlock / 64][kBucketBoxes];
     __shared__ uint32_t s_cur[kBlock / 64][kBucketBoxes];
@@ -812,6 +824,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_crowded(Slots sl, int64_t max
                                                            const uint32_t *__restrict__ start, SortOut o,
                                                            int periodic, int64_t capacity,
                                                            const uint32_t *__restrict__ crowd) {
+    if (frozen_plain(&sl.grids[0], sl.table)) return;
     __shared__ uint32_t s_grp[kBlock / 64][kBucketLds];
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (uniform)
     uint32_t *grp = s_grp[wave];
@@ -885,6 +898,7 @@ struct OrderGeom {
 __global__ __launch_bounds__(kBlock) void k_order_runs(const GridDev *__restrict__ g,
                                                        const uint32_t *__restrict__ tile_key, uint32_t *first,
                                                        uint32_t *last) {
+    if (g->frozen) return;
     const OrderGeom o(g);
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (!o.ok || c >= o.ntile) return;
@@ -900,6 +914,7 @@ __global__ __launch_bounds__(kBlock) void k_order_runs(const GridDev *__restrict
 // builds), so only those are read and reset; a small grid's scan skips the rest.
 __global__ __launch_bounds__(1024) void k_order_scan(const GridDev *__restrict__ g, uint32_t *first,
                                                      uint32_t *last, uint32_t *shift) {
+    if (g->frozen) return;
     __shared__ uint32_t s_part[1024 / 64];
     const OrderGeom o(g);
     const int t = threadIdx.x;
@@ -933,6 +948,7 @@ __global__ __launch_bounds__(kBlock) void k_order_write(const GridDev *__restric
                                                         const uint32_t *__restrict__ tile_key,
                                                         const uint32_t *__restrict__ shift,
                                                         uint32_t *__restrict__ order, int64_t max_tiles) {
+    if (g->frozen) return;
     const OrderGeom o(g);
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= o.ntile || c >= max_tiles) return;
@@ -957,6 +973,19 @@ __global__ __launch_bounds__(kBlock) void k_read_agents(const int64_t *n_ptr, co
     if (o.state) o.state[id] = s.state[i];
 }
 
+// Whether a plain build and its step change nothing (stationary skip): the last step was a
+// skipping step of this workspace that skipped every live agent, so no position moved; with the
+// same live count, force law and requested box edge the lattice, the sorted agents and every
+// force are what they are now.  Every later kernel of the build and of the step then returns at
+// once.  A build that may not skip clears the flag.
+__global__ void k_freeze_check(GridDev *g, SlotDev a, const int64_t *n_ptr, int32_t skip) {
+    if (threadIdx.x != 0) return;
+    const bool f = skip && g->kind == kGridOpenSkip && g->valid && g->consumed && g->mark_ready && g->skip_ok &&
+                   g->skipped == g->n && n_ptr[0] == g->n && g->law_k == a.k && g->law_gamma == a.gamma &&
+                   g->law_bits == a.force_bits && g->law_box == a.box;
+    g->frozen = f ? 1 : 0;
+}
+
 // ---------------------------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------------------------
@@ -974,14 +1003,16 @@ unsigned tile_grid(const Slots &sl, int64_t ntiles) {
 }
 
 void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, bool f32_copy, const Ws &w,
-                       hipStream_t st) {
+                       hipStream_t st, bool allow_freeze) {
     const bool has_d = sl.table ? true : sl.one.has_d != 0;
     const double *d = has_d ? s.diam : nullptr;
     const int64_t nbt = (capacity + kBoundsTile - 1) / kBoundsTile;
-    hipLaunchKernelGGL(k_bounds, dim3(tile_grid(sl, nbt)), dim3(kBlock), 0, st, sl, nbt, s.n, s.x, s.y, s.z, d,
-                       w.partials, w.tiles, w.lay.max_tiles);
     // plain open-space mechanics that skips stationary agents (needs the forces of the last step)
     const bool skip = !sl.table && !sl.one.periodic && sl.one.skip && !f32_copy && s.fx && s.fy && s.fz;
+    if (!sl.table)
+        hipLaunchKernelGGL(k_freeze_check, dim3(1), dim3(64), 0, st, w.grid, sl.one, s.n, int32_t(skip && allow_freeze));
+    hipLaunchKernelGGL(k_bounds, dim3(tile_grid(sl, nbt)), dim3(kBlock), 0, st, sl, nbt, s.n, s.x, s.y, s.z, d,
+                       w.partials, w.tiles, w.lay.max_tiles);
     const int32_t kind = (!sl.table && sl.one.periodic) ? kGridPeriodic
                          : f32_copy                     ? kGridOpenF32
                          : skip                         ? kGridOpenSkip
@@ -993,7 +1024,7 @@ void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, bool
     const unsigned nbk = tile_grid(sl, (nt + kKeyTiles - 1) / kKeyTiles);
     hipLaunchKernelGGL(k_key_bucket, dim3(nbk), dim3(kBlock), 0, st, sl, nt, s.x, s.y, s.z, w.count, w.key, w.rank,
                        skip ? w.dirty : nullptr, w.moved);
-    launch_scan(w.count, w.bstart, nullptr, w.lay.nbuckets, w, 1, false, st);
+    launch_scan(w.count, w.bstart, nullptr, w.lay.nbuckets, w, 1, false, st, !sl.table);
     hipLaunchKernelGGL(k_bucket_scatter, dim3(nbk), dim3(kBlock), 0, st, sl, nt, w.key, w.rank, w.bstart, w.item,
                        capacity);
     // per-bucket order; the sorted agents' keys go to the rank array, which nothing reads after
@@ -1023,13 +1054,13 @@ void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, bool
 }
 
 void launch_scan(uint32_t *in, uint32_t *out, const int64_t *len_ptr, int64_t max_len, const Ws &w,
-                 int zero_in, bool prepare, hipStream_t st) {
+                 int zero_in, bool prepare, hipStream_t st, bool build) {
     const unsigned nt = unsigned((max_len + kScanTile) / kScanTile);
     if (prepare)
         hipLaunchKernelGGL(k_scan_prepare, dim3(blocks_for(w.lay.max_tiles)), dim3(kBlock), 0, st, w.tiles,
                            w.lay.max_tiles, &w.grid[0].scan_ticket);
     hipLaunchKernelGGL(k_scan, dim3(nt), dim3(kBlock), 0, st, in, out, len_ptr, max_len, w.tiles,
-                       &w.grid[0].scan_ticket, zero_in, &w.grid[0]);
+                       &w.grid[0].scan_ticket, zero_in, &w.grid[0], int32_t(build));
 }
 
 void launch_read_agents(const bdm_soa &s, const ReadOut &o, hipStream_t st) {

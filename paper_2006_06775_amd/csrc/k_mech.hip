@@ -728,6 +728,7 @@ __device__ __forceinline__ void mech_plain(const Slots &sl, const uint32_t *__re
     __shared__ uint32_t s_q[kQ][kBlock];
     __shared__ typename Rec::Pre s_stage[kQ == kQueueCrowded ? kBlock : 1];  // records of a cooperative walk
     GridDev *g0 = &sl.grids[0];
+    if (frozen_plain(g0, sl.table)) return;  // nothing moved since the last step: nothing changes
     // no usable grid of these agents: never built, its build failed, already used by a step,
     // or built for another model (the periodic lattice has no pre-test records; the crowded
     // kernel reads the binary32 copies only spheroid builds write)
@@ -874,8 +875,15 @@ static void launch_mech_traced(const bdm_soa &s, const Slots &sl, int64_t ntiles
 // A plain mechanical step has used its grid build: the next step needs a new one.  After a step
 // that skips stationary agents, its marks are ready for the next build, and the agents skipped
 // are summed from the per-wavefront counts of the tiles it ran.
-__global__ __launch_bounds__(1024) void k_grid_consume(GridDev *g, const uint32_t *tileskip, int32_t skip) {
+// A build that found nothing to do (frozen) holds for its force law only: a step that asked for
+// another one was refused (it needs a new build; its kernel left the agents as they are).
+__global__ __launch_bounds__(1024) void k_grid_consume(GridDev *g, const uint32_t *tileskip, int32_t skip, SlotDev a) {
     __shared__ unsigned long long s_part[1024 / 64];
+    if (g->frozen) {
+        if (threadIdx.x == 0 && (g->law_k != a.k || g->law_gamma != a.gamma || g->law_bits != a.force_bits))
+            atomicOr(&g->flags, BDM_FLAG_NOGRID);
+        return;
+    }
     if (skip) {
         const bool ran = g->valid && g->kind == kGridOpenSkip && !g->consumed;
         const int64_t nw = ran ? (g->n + kBlock - 1) / kBlock * (kBlock / 64) : 0;
@@ -920,7 +928,8 @@ void launch_mech(const bdm_soa &s, const Slots &sl, int64_t capacity, int precis
         launch_mech_traced(s, sl, ntiles, nb, precision, order, RecGlobal{w.pos4, w.pos8}, w, trace, st);
     }
     if (!sl.table)
-        hipLaunchKernelGGL(k_grid_consume, dim3(1), dim3(1024), 0, st, w.grid, w.tileskip, int32_t(sl.one.skip));
+        hipLaunchKernelGGL(k_grid_consume, dim3(1), dim3(1024), 0, st, w.grid, w.tileskip, int32_t(sl.one.skip),
+                           sl.one);
 }
 
 void launch_contacts_mech(int f32, const Slots &sl, const Ws &w, uint32_t *counts, const int64_t *offsets,

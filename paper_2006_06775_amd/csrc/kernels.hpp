@@ -82,11 +82,13 @@ struct ContactArgs {
 unsigned tile_grid(const Slots &sl, int64_t ntiles);
 // Grid build (bounds, finalize, key/histogram, scan, scatter, canonical order) of every slot.
 // f32_copy: also write the binary32 pre-test copies (read by the crowded mechanics kernel).
+// allow_freeze: a plain skipping build may find that nothing changed since the last step and
+// skip itself and its step whole (traced steps pass false: they record every contact).
 void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, bool f32_copy, const Ws &w,
-                       hipStream_t st);
+                       hipStream_t st, bool allow_freeze = true);
 // Exclusive scan of in[0, len) into out[0, len] (len read on the device).
 void launch_scan(uint32_t *in, uint32_t *out, const int64_t *len_ptr, int64_t max_len, const Ws &w,
-                 int zero_in, bool prepare, hipStream_t st);
+                 int zero_in, bool prepare, hipStream_t st, bool build = false);
 // trace: NULL for the step itself; else the traced instantiation of the same kernels.
 void launch_mech(const bdm_soa &s, const Slots &sl, int64_t capacity, int precision, bool crowded, const Ws &w,
                  hipStream_t st, const TraceOut *trace = nullptr);

@@ -132,3 +132,54 @@ def test_skip_full_size_sampled():
         flag, disp = orc.displacement((fx[j], fy[j], fz[j]), 0.4, DT, 3.0)
         exp = [x_t[a][i] if flag == 1 else x_t[a][i] + disp[c] for c, a in enumerate("xyz")]
         assert [res["x"][i], res["y"][i], res["z"][i]] == exp, i
+
+
+def relaxed_population(skip, n=1 << 14, steps=40, seed=0):
+    """2^14 agents at the 2^24 workload's density (d in [8, 12)), `steps` relaxing steps; every
+    agent is gated after about 20 of them, so the later steps change nothing."""
+    L = 3200.0 / 1024 ** (1.0 / 3.0)
+    pop = bdm.Population(n, 1 << 18)
+    bdm.generate(pop.soa, bdm.gen(bdm.GEN_CUBE, n, L, 8.0, 12.0, 0.4, seed=seed))
+    p = bdm.params(dt=DT, skip_static=skip)
+    skipped = []
+    for step in range(steps):
+        bdm.sim_step(pop.soa, bdm.MODEL_MECH, p, step, pop.ws)
+        skipped.append(bdm.grid_info(pop.ws)["skipped"])
+    return pop, skipped
+
+
+def test_relaxed_steps_change_nothing_and_a_new_law_recomputes():
+    """Once a step skipped every agent, the next steps skip their build and walk whole; they
+    must still equal the run without the skip, and a change of the force law must bring the
+    full step back (no agent skipped) with the same results as without the skip."""
+    say("case: frozen relaxed steps")
+    out = []
+    for skip in (0, 1):
+        pop, skipped = relaxed_population(skip)
+        p2 = bdm.params(k=2.5, gamma=1.25, dt=DT, skip_static=skip)
+        for step in range(40, 48):
+            bdm.sim_step(pop.soa, bdm.MODEL_MECH, p2, step, pop.ws)
+            skipped.append(bdm.grid_info(pop.ws)["skipped"])
+        assert bdm.status(pop.ws) == 0
+        out.append((pop.read(("x", "y", "z", "fx", "fy", "fz")), skipped, pop.n))
+    (a, _, _), (b, skipped, n) = out
+    say(f"skipped per step: {skipped}")
+    for k in a:
+        assert np.array_equal(bits(a[k]), bits(b[k])), k
+    assert skipped[38] == n and skipped[39] == n  # relaxed: whole steps skipped
+    assert skipped[40] == 0  # another force law: every agent walks again
+    assert max(skipped[41:]) > n // 2  # and the skip resumes under the new law
+
+
+def test_relaxed_build_then_step_with_another_law_is_refused():
+    """A build that found nothing to do belongs to its force law: a mechanical step asking for
+    another law reports BDM_FLAG_NOGRID and moves nothing."""
+    say("case: frozen build, other law")
+    pop, skipped = relaxed_population(1)
+    assert skipped[-1] == pop.n
+    p = bdm.params(dt=DT, skip_static=1)
+    bdm.grid_build(pop.soa, p, pop.ws)
+    x0 = pop.t["x"][:pop.n].clone()
+    bdm.mech_step(pop.soa, bdm.params(k=3.0, dt=DT, skip_static=1), pop.ws)
+    assert torch.equal(pop.t["x"][:pop.n], x0)
+    assert bdm.status(pop.ws, clear=True) == bdm.FLAG_NOGRID
