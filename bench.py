@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_mech_fp64_n16m.json"),
                     help="HBM bytes per mech_step launch from rocprofv3 counters (optional)")
     ap.add_argument("--no-serve", action="store_true", help="skip the batched/served stream")
+    ap.add_argument("--no-skip", action="store_true", help="skip the stationary-skip comparison")
     ap.add_argument("--no-workloads", action="store_true", help="skip the other workloads (spheroid, oncology, soma clustering, SIR)")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-budget-gib", type=float, default=4.0,
@@ -89,8 +90,8 @@ def run_variant(bdm, torch, n, L, steps, warmup, force_bits):
 def stationary_skip(bdm, torch, n, L, relax=24, steps=20, dt=0.3):
     """The stationary-region skip (paper Sec. 2.3 (iv)) on the mechanics workload as it relaxes:
     dt 0.3 (30 times the benchmark's), `relax` timed steps while agents come to rest (each
-    followed by a read of the skipped count), then `steps` timed steps of the relaxed state, once
-    without and once with the skip, from the same seed; the two end states must be
+    followed by a read of the skipped count), then `steps` timed steps, then `steps` more timed one
+    by one, once without and once with the skip, from the same seed; the two end states must be
     bit-identical."""
     out, ends = {}, {}
     for skip in (0, 1):
@@ -107,13 +108,15 @@ def stationary_skip(bdm, torch, n, L, relax=24, steps=20, dt=0.3):
         def one(step):
             bdm.sim_step(pop.soa, bdm.MODEL_MECH, p, relax + step, pop.ws)
         t = timed_steps(torch, one, steps)
+        per_step = timed_each(torch, lambda step: one(steps + step), steps)
         info = bdm.grid_info(pop.ws)
         out["skip" if skip else "plain"] = dict(ms_per_step=round(t * 1e3 / steps, 4),
                                                 agent_updates_per_s=n * steps / t,
                                                 relaxing_ms_per_step=round(t_relax * 1e3 / relax, 4),
                                                 skipped_per_relaxing_step=skipped,
+                                                ms_each_of_next_steps=per_step,
                                                 skipped_last_step=info["skipped"], flags=info["flags"])
-        ends[skip] = pop.read(("x", "y", "z", "fx", "fy", "fz"))
+        ends[skip] = pop.read(("x", "y", "z", "fx", "fy", "fz"))  # after relax + 2 * steps steps
         del pop
         torch.cuda.empty_cache()
     same = all(np.array_equal(ends[0][k].view(np.uint64), ends[1][k].view(np.uint64)) for k in ends[0])
@@ -222,6 +225,18 @@ def timed_steps(torch, fn, steps):
     e.record()
     torch.cuda.synchronize()
     return s.elapsed_time(e) * 1e-3
+
+
+def timed_each(torch, fn, steps):
+    """Milliseconds of each of `steps` calls, from HIP events around each (one sync at the end)."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for step in range(steps):
+        ev[step][0].record()
+        fn(step)
+        ev[step][1].record()
+    torch.cuda.synchronize()
+    return [round(a.elapsed_time(b), 4) for a, b in ev]
 
 
 def workloads():
@@ -452,7 +467,7 @@ def main():
     del r64["pop"]
     torch.cuda.empty_cache()
 
-    skip = stationary_skip(bdm, torch, n, L)
+    skip = None if args.no_skip else stationary_skip(bdm, torch, n, L)
     served = None if args.no_serve else serving(args)
     other = None if args.no_workloads else workloads()
     copy_gbps = copy_bandwidth(torch)
