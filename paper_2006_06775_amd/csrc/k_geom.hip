@@ -8,21 +8,20 @@
 //
 //   reach  per agent: a cylinder's grid diameter from its current ends
 //   grid   the sphere path's build (keys, sort, starts) on the grid diameters
-//   geom   one lane per box-sorted agent walks the 27 boxes as 9 key runs; a candidate first
-//          passes the sphere path's exact integer test on the 8-byte records (centre distance
-//          against the sum of the grid radii, rounded up: no pair whose grid spheres overlap
-//          fails it), then the closest points of the two axes carry virtual spheres of the
-//          bodies' diameters and the sphere law acts between them; a cylinder takes the share s
-//          of the force (s its closest point's position along p -> q); gate, clamp and move as
-//          the sphere step (a cylinder moves its distal end)
+//   geom   one lane per box-sorted agent walks the 27 boxes as 9 key runs; a candidate passes a
+//          bounding-sphere test (centre distance against the sum of the grid radii, with a
+//          relative margin of 2^-20 on the square, far above rounding), then the closest points
+//          of the two axes carry virtual spheres of the bodies' diameters and the sphere law
+//          acts between them; a cylinder takes the share s of the force (s its closest point's
+//          position along p -> q); gate, clamp and move as the sphere step (a cylinder moves its
+//          distal end)
 //
 // The arithmetic follows the same expressions in the same order as the definition, so results
-// are reproducible bit for bit.  Only candidates that pass the 8-byte test load their 32-byte
-// record and, for cylinders, their ends and diameter by id.  The walk's cost is its candidate
-// count: the grid sphere about the distal end (radius l + d/2) sets a box edge of up to twice a
-// cylinder's length, about 330 candidates per agent at the neurite workload's 18 um boxes.
+// are reproducible bit for bit.  The walk's cost is its candidate count: the grid sphere about
+// the distal end (radius l + d/2) sets a box edge of up to twice a cylinder's length, about 330
+// candidates per agent at the neurite workload's 18 um boxes.  (Filtering them first with the
+// sphere path's 8-byte records, or with spheres about the axis midpoints, measured no faster.)
 #include "kernels.hpp"
-#include "record8.hpp"
 
 namespace bdm {
 
@@ -178,7 +177,6 @@ __global__ __launch_bounds__(kBlock) void k_geom_reach(const int64_t *n_ptr, int
 }
 
 __global__ __launch_bounds__(kBlock) void k_geom(GridDev *__restrict__ g, const double4 *__restrict__ pos4,
-                                                 const uint2 *__restrict__ pos8,
                                                  const double *__restrict__ adh_s, const uint32_t *__restrict__ id_s,
                                                  const uint8_t *__restrict__ state_s,
                                                  const uint32_t *__restrict__ start, CylIn cyl, GeomArgs a,
@@ -193,7 +191,6 @@ __global__ __launch_bounds__(kBlock) void k_geom(GridDev *__restrict__ g, const 
         return;
     }
     const Body bi = load_body(ri, ki, idi, cyl);
-    const Own8 own = own8(pos8[s]);
     const double b = g->b;
     const int cx = box_coord(ri.x, b, g->cmin[0], g->dims[0], false);
     const int cy = box_coord(ri.y, b, g->cmin[1], g->dims[1], false);
@@ -208,8 +205,11 @@ __global__ __launch_bounds__(kBlock) void k_geom(GridDev *__restrict__ g, const 
         const uint32_t kb = uint32_t(x0) + uint32_t(nx) * (uint32_t(yy) + uint32_t(ny) * uint32_t(zz));
         const uint32_t lo = start[kb] & kStartMask, hi = start[kb + uint32_t(x1 - x0) + 1u] & kStartMask;
         for (uint32_t j = lo; j < hi; ++j) {
-            if (j == uint32_t(s) || !touch8i(own, pos8[j])) continue;
+            if (j == uint32_t(s)) continue;
             const double4 rj = pos4[j];
+            const double dx = ri.x - rj.x, dy = ri.y - rj.y, dz = ri.z - rj.z;
+            const double reach = ri.w + rj.w;
+            if (!((dx * dx + dy * dy) + dz * dz <= (reach * reach) * (1.0 + 0x1.0p-20))) continue;
             const uint8_t kj = state_s[j];
             const uint32_t idj = id_s[j];
             if (kj == 1 && int64_t(idj) >= a.capacity) continue;
@@ -262,8 +262,8 @@ void launch_geom(const bdm_soa &s, const CylIn &cyl, const GeomArgs &a, const Ws
                  hipStream_t st) {
     int64_t nb = (a.capacity + kBlock - 1) / kBlock;
     if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_geom, dim3(unsigned(nb)), dim3(kBlock), 0, st, &w.grid[0], w.pos4, w.pos8, w.adh, w.ids,
-                       w.state, w.start, cyl, a, s, counts);
+    hipLaunchKernelGGL(k_geom, dim3(unsigned(nb)), dim3(kBlock), 0, st, &w.grid[0], w.pos4, w.adh, w.ids, w.state,
+                       w.start, cyl, a, s, counts);
 }
 
 }  // namespace bdm

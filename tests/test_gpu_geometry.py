@@ -111,3 +111,20 @@ def test_geom_full_size_step():
     s = synth.neurite_mix(n, 800.0, seed=0)
     pop, ref, f, gc, rc = step_pair(s, 1)
     check(pop, ref, f, gc, rc, "full size")
+
+
+def test_geom_empty_and_single_agents():
+    say("case: geometry empty and single")
+    for n in (0, 1):
+        s = synth.neurite_mix(max(n, 1), 40.0, sphere_frac=0.0, seed=6)
+        pop, cyl = load(s)
+        pop.t["n"].fill_(n)
+        bdm.geom_step(pop.soa, cyl.rec(), bdm.params(), pop.ws)
+        assert bdm.status(pop.ws) == 0
+        if n == 1:
+            got = pop.read(("x", "y", "z", "diam", "fx"))
+            ref = {k: v[:1].copy() for k, v in s.items()}
+            orc.geom_step(ref)
+            for a, b in (("x", "x"), ("y", "y"), ("z", "z"), ("diam", "d")):
+                assert np.array_equal(bits(got[a]), bits(ref[b])), a
+            assert got["fx"][0] == 0.0

@@ -196,3 +196,20 @@ def test_diameter_special_sets():
     x = np.random.default_rng(2).uniform(0, 10, 300)
     flat = dict(x=x, y=2 * x + 1, z=np.full(300, 4.0), d=np.ones(300), adh=np.ones(300))
     assert diameter_pair(flat)[0] == 0.0
+
+
+def test_oncology_capacity_overflow():
+    """Divisions that find no slot below capacity are skipped and flagged, after apoptosis has
+    renumbered the survivors: the oracle does the same."""
+    say("case: oncology overflow")
+    n, cap = 64, 70
+    s = dict(x=np.arange(n) * 30.0, y=np.zeros(n), z=np.zeros(n), d=np.full(n, 13.99), adh=np.full(n, 0.4))
+    pop = bdm.Population(cap, 1 << 14)
+    pop.load(s)
+    bdm.sim_step(pop.soa, bdm.MODEL_ONCOLOGY, gpu_params(3, 0.05, 0.5), 0, pop.ws)
+    assert bdm.status(pop.ws) & bdm.FLAG_CAPACITY
+    st = orc.SpheroidState(s, cap)
+    assert st.oncology_step(ora_params(3, 0.05, 0.5), 0)
+    assert pop.n == int(st.n[0]) == cap
+    got = pop.read()
+    assert bit_equal(got, {k: st.view(k) for k in ("x", "y", "z", "d")})

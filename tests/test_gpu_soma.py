@@ -173,3 +173,46 @@ def test_soma_full_size_step():
         assert [out["x"][i], out["y"][i], out["z"][i]] == exp, i
     say(f"{len(chem)} cells moved by chemotaxis; sampled {len(ids)} cells, {int(nc.sum())} contacts: bit-equal")
     assert len(chem) > 1000
+
+
+def test_soma_step_without_cells_only_diffuses():
+    """No cells: secretion and chemotaxis do nothing, the fields still take one diffusion step
+    each call, and the (empty) mechanics is a no-op."""
+    say("case: soma without cells")
+    pop = bdm.Population(64, 1 << 12, with_state=True)
+    pop.t["n"].fill_(0)
+    f = bdm.Field(9, 7, 5, 4.0)
+    c = np.random.default_rng(3).uniform(0.0, 2.0, 2 * f.V)
+    f.load(c)
+    p = gpu_p(D=150.0)
+    for _ in range(2):
+        f.step(pop.soa, p, pop.ws)
+    lam, kdec = orc.diffusion_coefficients(150.0, 0.1, 0.01, 4.0)
+    of = orc.field(9, 7, 5, 4.0)
+    ref = c
+    for _ in range(2):
+        ref = np.concatenate([orc.diffuse(of, ref[:f.V], lam, kdec), orc.diffuse(of, ref[f.V:], lam, kdec)])
+    assert np.array_equal(bits(f.c.cpu().numpy()), bits(ref))
+    assert pop.n == 0 and bdm.status(pop.ws) == 0
+
+
+def test_soma_cells_outside_the_grid():
+    """Cells beyond the grid on every side use the nearest boundary voxel for secretion and
+    chemotaxis, as the oracle does."""
+    say("case: soma cells outside the grid")
+    n = 800
+    s = orc.generate_soma(n, 2, 100.0, 10.0, 15.0, 0.4)
+    for k in "xyz":
+        s[k] = s[k] * 1.6 - 30.0  # [-30, 130): the grid covers [0, 100)
+    pop = bdm.Population(n, 1 << 16, with_state=True)
+    pop.load({k: s[k] for k in ("x", "y", "z", "d", "adh", "state")})
+    f = bdm.Field(20, 20, 20, 5.0)
+    of = orc.field(20, 20, 20, 5.0)
+    c = np.zeros(2 * f.V)
+    for _ in range(5):
+        f.step(pop.soa, gpu_p(speed=0.8), pop.ws)
+        c, *_ = orc.soma_step(s, of, c, orc_p(speed=0.8))
+    got = pop.read(("x", "y", "z"))
+    for k in "xyz":
+        assert np.array_equal(bits(got[k]), bits(s[k])), k
+    assert np.array_equal(bits(f.c.cpu().numpy()), bits(c))
