@@ -278,7 +278,7 @@ int bdm_hull_candidates(const bdm_soa *soa, const double *planes, int32_t nplane
  * floor((x - x0)/h) per axis, clamped into the grid.  All arrays are caller-owned device memory;
  * c and c_next must not overlap. */
 typedef struct bdm_field {
-    int32_t nx, ny, nz;    /* voxels per axis, each in [1, 2^20], nx*ny*nz <= 2^30 */
+    int32_t nx, ny, nz;    /* voxels per axis, in [1, 2^20] (ny <= 1048560), nx*ny*nz <= 2^30 */
     double x0, y0, z0;     /* lower corner */
     double h;              /* voxel edge (> 0) */
     double *c;             /* 2*V values: both substances now */

@@ -207,6 +207,7 @@ int check_field(const bdm_field *f, bdm::FieldDev *out) {
         return fail(BDM_EINVAL, "field voxels per axis must be in [1, 2^20]");
     const int64_t V = int64_t(f->nx) * f->ny * f->nz;
     if (V > (int64_t(1) << 30)) return fail(BDM_EINVAL, "field has more than 2^30 voxels");
+    if (f->ny > 16 * 65535) return fail(BDM_EINVAL, "field ny must be at most 1048560");  // (launch rows of 16)
     if (!(f->h > 0.0) || !is_fin(f->h) || !is_fin(f->x0) || !is_fin(f->y0) || !is_fin(f->z0))
         return fail(BDM_EINVAL, "field corner must be finite and h > 0");
     if (!f->c || !f->c_next || !f->count) return fail(BDM_EINVAL, "field arrays c, c_next and count are required");

@@ -76,3 +76,23 @@ def test_validation_without_gpu():
     assert lib.bdm_sim_step_noalloc(C.byref(big), 0, C.byref(p), 0, 1 << 20, None, None) == bdm.ENOWS
     assert b"static scratch" in lib.bdm_last_error()
     assert bdm.workspace_bytes(1 << 22, 1 << 20) > bdm.NOALLOC_SCRATCH_BYTES
+
+
+def test_substance_and_hull_validation_without_gpu():
+    from paper_2006_06775_amd import bdm
+    lib = bdm.lib()
+    p = bdm.params(diff_D=100.0, dt=0.01)
+    a, b, cnt = C.c_void_p(0x1000), C.c_void_p(0x100000000), C.c_void_p(0x200000000)
+    for dims in ((0, 4, 4), (4, 1048561, 1), (1 << 21, 1, 1), (1024, 1024, 1025)):
+        f = bdm.FieldRec(*dims, 0.0, 0.0, 0.0, 5.0, a, b, cnt)
+        assert lib.bdm_diffuse(C.byref(f), C.byref(p), None) == bdm.EINVAL, dims
+    f = bdm.FieldRec(8, 8, 8, 0.0, 0.0, 0.0, 5.0, a, a, cnt)  # c == c_next
+    assert lib.bdm_diffuse(C.byref(f), C.byref(p), None) == bdm.EINVAL
+    assert b"overlap" in lib.bdm_last_error()
+    f = bdm.FieldRec(8, 8, 8, 0.0, 0.0, 0.0, 5.0, a, b, cnt)
+    unstable = bdm.params(diff_D=1000.0, dt=0.01)  # D dt / h^2 = 0.4 > 1/6
+    assert lib.bdm_diffuse(C.byref(f), C.byref(unstable), None) == bdm.EINVAL
+    soa = bdm.Soa(10, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 0)
+    assert lib.bdm_extreme_points(C.byref(soa), None, 0, None, None, None) == bdm.EINVAL
+    assert lib.bdm_hull_candidates(C.byref(soa), a, 2000, 0.0, None, 0, cnt, None) == bdm.EINVAL
+    assert lib.bdm_geom_step(C.byref(soa), None, C.byref(p), None, None, None) == bdm.ENOWS
