@@ -68,7 +68,9 @@ extern "C" {
 
 /* Agent state.  Every array has `capacity` elements; `n` points to the device-resident live
  * count (int64).  diam/adh may be NULL for point agents (SIR); fx/fy/fz may be NULL when the
- * forces are not wanted; state may be NULL except for SIR (0 = S, 1 = I, 2 = R). */
+ * forces are not wanted; state may be NULL except for SIR (0 = S, 1 = I, 2 = R), soma
+ * clustering (cell type) and cylinders (1 = cylinder).  Where it is kept it travels with its
+ * agent: through every sort, to a dividing cell's daughter and with an apoptosis survivor. */
 typedef struct bdm_soa {
     int64_t capacity;
     int64_t *n;

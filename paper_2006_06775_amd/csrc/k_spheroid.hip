@@ -6,6 +6,7 @@
 //              threshold floor(p_apo * 2^64)
 //   scan       exclusive scan of the survival flags in id order: the new id of each survivor
 //   apo_stage  survivor -> staging slot (its new id), in the workspace's sorted-copy arrays
+//              (position and diameter, adherence, and the state when the caller keeps one)
 //   apo_commit staging -> slots 0 .. n'-1 of the caller's arrays, id = slot
 //   apo_count  n = n'
 //   migrate    every live agent moves by walk * (2u - 1) per axis, u from (MIG, id, step)
@@ -80,6 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_divide(const int64_t *n_ptr, int64_t
     s.z[slot] = z + oz;
     s.diam[slot] = dp;
     s.adh[slot] = s.adh[i];
+    if (s.state) s.state[slot] = s.state[i];
     s.id[slot] = uint32_t(slot);
     s.x[i] = x - ox;
     s.y[i] = y - oy;
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_apo_flag(const int64_t *n_ptr, int64
 __global__ __launch_bounds__(kBlock) void k_apo_stage(const int64_t *n_ptr, int64_t capacity, bdm_soa s,
                                                       const uint32_t *__restrict__ flagid,
                                                       const uint32_t *__restrict__ rankid, double4 *pos,
-                                                      double *adh) {
+                                                      double *adh, uint8_t *state) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t n = live_count(n_ptr, 0, capacity);
     if (i >= n) return;
@@ -124,12 +126,14 @@ __global__ __launch_bounds__(kBlock) void k_apo_stage(const int64_t *n_ptr, int6
     if (j >= n) return;
     pos[j] = make_double4(s.x[i], s.y[i], s.z[i], s.diam[i]);
     adh[j] = s.adh[i];
+    if (s.state) state[j] = s.state[i];
 }
 
 __global__ __launch_bounds__(kBlock) void k_apo_commit(const int64_t *n_ptr, int64_t capacity, bdm_soa s,
                                                        const uint32_t *__restrict__ rankid,
                                                        const double4 *__restrict__ pos,
-                                                       const double *__restrict__ adh) {
+                                                       const double *__restrict__ adh,
+                                                       const uint8_t *__restrict__ state) {
     const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t n = live_count(n_ptr, 0, capacity);
     int64_t kept = rankid[n];
@@ -141,6 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_apo_commit(const int64_t *n_ptr, int
     s.z[j] = p.z;
     s.diam[j] = p.w;
     s.adh[j] = adh[j];
+    if (s.state) s.state[j] = state[j];
     s.id[j] = uint32_t(j);
 }
 
@@ -170,9 +175,9 @@ void launch_apoptosis(const bdm_soa &s, int64_t capacity, const ApoArgs &a, cons
                        &w.grid[0]);
     launch_scan(w.flagid, w.rankid, s.n, capacity, w, 0, true, st);
     hipLaunchKernelGGL(k_apo_stage, dim3(unsigned(nb)), dim3(kBlock), 0, st, s.n, capacity, s, w.flagid, w.rankid,
-                       w.pos4, w.adh);
+                       w.pos4, w.adh, w.state);
     hipLaunchKernelGGL(k_apo_commit, dim3(unsigned(nb)), dim3(kBlock), 0, st, s.n, capacity, s, w.rankid, w.pos4,
-                       w.adh);
+                       w.adh, w.state);
     hipLaunchKernelGGL(k_apo_count, dim3(1), dim3(64), 0, st, s.n, capacity, w.rankid);
 }
 

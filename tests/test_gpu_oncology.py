@@ -213,3 +213,24 @@ def test_oncology_capacity_overflow():
     assert pop.n == int(st.n[0]) == cap
     got = pop.read()
     assert bit_equal(got, {k: st.view(k) for k in ("x", "y", "z", "d")})
+
+
+def test_state_travels_with_survivors_and_daughters():
+    """A caller's state array follows each cell through apoptosis (renumbering) and division
+    (the daughter takes the mother's): the adherence, which the oracle carries the same way,
+    encodes the expected state."""
+    say("case: oncology state array")
+    n, cap = 1500, 6000
+    s = orc.generate_ball(n, 7, 30.0, 14.0 * H, 14.0, 0.4)
+    tag = (np.arange(n) % 4).astype(np.uint8)
+    s["adh"] = 0.4 + 0.01 * tag
+    pop = bdm.Population(cap, 1 << 18, with_state=True)
+    pop.load({**s, "state": tag})
+    st = orc.SpheroidState(s, cap)
+    for t in range(4):
+        bdm.sim_step(pop.soa, bdm.MODEL_ONCOLOGY, gpu_params(7, 0.05, 1.0), t, pop.ws)
+        st.oncology_step(ora_params(7, 0.05, 1.0), t)
+    got = pop.read(("x", "y", "z", "diam", "state"))
+    assert bit_equal(got, {k: st.view(k) for k in ("x", "y", "z", "d")})
+    want = np.rint((st.view("adh") - 0.4) / 0.01).astype(np.uint8)
+    assert pop.n > n and np.array_equal(got["state"], want)
