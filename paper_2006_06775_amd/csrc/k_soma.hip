@@ -16,9 +16,9 @@
 // write of 8 bytes per voxel.  A workgroup owns a 64 x 16 column of voxels and walks along z:
 // each lane keeps the values below, at and above its voxels in registers, so z-neighbours cost
 // no loads; x/y-neighbours come from the current plane staged in LDS with a one-voxel halo
-// (two buffers, one barrier per plane).  A row of 64 lanes reads 512 contiguous bytes.  The
-// closed boundary is a clamped neighbour index: outside the grid the neighbour is the voxel
-// itself and its difference is exactly zero.
+// (two buffers, one barrier per plane).  A row of 64 lanes reads 512 contiguous bytes; results
+// are stored non-temporally.  The closed boundary is a clamped neighbour index: outside the
+// grid the neighbour is the voxel itself and its difference is exactly zero.
 #include "kernels.hpp"
 
 namespace bdm {
@@ -120,7 +120,8 @@ __global__ __launch_bounds__(kBlock) void k_diffuse(FieldDev f, const double *__
             const double xm = s_pl[b][row][tx], xp = s_pl[b][row][tx + 2];
             const double ym = s_pl[b][row - 1][tx + 1], yp = s_pl[b][row + 1][tx + 1];
             const double lap = (((xm - c) + (xp - c)) + ((ym - c) + (yp - c))) + ((below[r] - c) + (above[r] - c));
-            if (x < nx && yr[r] < ny) out[zoff + int64_t(yr[r]) * nx + x] = c + (lam * lap - kdec * c);
+            if (x < nx && yr[r] < ny)  // streamed out: the next read is a whole field later
+                __builtin_nontemporal_store(c + (lam * lap - kdec * c), &out[zoff + int64_t(yr[r]) * nx + x]);
             below[r] = c;
             cur[r] = above[r];
         }
@@ -167,9 +168,10 @@ static unsigned agent_blocks(int64_t capacity) {
 
 void diffusion_launch_shape(const FieldDev &f, int32_t *zchunk, int32_t *nzc, dim3 *grid) {
     const int64_t tiles = int64_t((f.nx + kDiffTX - 1) / kDiffTX) * ((f.ny + kDiffTY - 1) / kDiffTY);
-    // enough workgroups for 256 CUs (a few per CU), at least 8 planes per chunk, at most 32767
-    // chunks per substance
-    int64_t want = (2048 + 2 * tiles - 1) / (2 * tiles);
+    // about 8192 workgroups (32 per CU: the latency of the plane loads is hidden by many
+    // workgroups in flight rather than by long z runs), at least 8 planes per chunk, at most
+    // 32767 chunks per substance
+    int64_t want = (8192 + 2 * tiles - 1) / (2 * tiles);
     if (want < 1) want = 1;
     int64_t zc = (f.nz + want - 1) / want;
     if (zc < 8) zc = 8;
