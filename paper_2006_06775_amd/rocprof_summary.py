@@ -24,7 +24,8 @@ import os
 import statistics
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-MECH_SOURCES = ("paper_2006_06775_amd/csrc/k_mech.hip", "paper_2006_06775_amd/csrc/common.hpp")
+MECH_SOURCES = ("paper_2006_06775_amd/csrc/k_mech.hip", "paper_2006_06775_amd/csrc/record8.hpp",
+                "paper_2006_06775_amd/csrc/common.hpp")
 MECH_KERNEL = "k_mech<64"
 COPY_KERNEL = "copyBuffer"
 
