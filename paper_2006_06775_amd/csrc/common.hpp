@@ -79,6 +79,8 @@ struct GridDev {
     double law_k, law_gamma, law_box;  // force law and requested box edge of the last build
     int32_t law_bits;
     int32_t frozen;                 // this build and its step are skipped whole (nothing moved)
+    unsigned long long skip_acc;    // a skipping step's skipped count while its workgroups sum it (0 between steps)
+    uint32_t consume_ticket;        // workgroups of that sum done (0 between steps)
 };
 static_assert(sizeof(GridDev) <= 256, "grid record must fit its slot");
 

@@ -86,6 +86,8 @@ __device__ void clear_grid(GridDev *g) {
     g->frozen = 0;
     g->skip_ok = 0;
     g->skipped = 0;
+    g->skip_acc = 0ull;
+    g->consume_ticket = 0u;
 }
 
 // Zero the grid records, the histogram and the scan tiles; empty the batch slot table.
