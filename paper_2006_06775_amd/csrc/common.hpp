@@ -81,6 +81,8 @@ struct GridDev {
     int32_t frozen;                 // this build and its step are skipped whole (nothing moved)
     unsigned long long skip_acc;    // a skipping step's skipped count while its workgroups sum it (0 between steps)
     uint32_t consume_ticket;        // workgroups of that sum done (0 between steps)
+    unsigned long long sir_acc[3];  // a SIR step's S/I/R totals while its workgroups sum them (0 between steps)
+    uint32_t sir_ticket;            // workgroups of that sum done (0 between steps)
 };
 static_assert(sizeof(GridDev) <= 256, "grid record must fit its slot");
 

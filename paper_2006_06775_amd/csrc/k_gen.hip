@@ -88,6 +88,8 @@ __device__ void clear_grid(GridDev *g) {
     g->skipped = 0;
     g->skip_acc = 0ull;
     g->consume_ticket = 0u;
+    g->sir_acc[0] = g->sir_acc[1] = g->sir_acc[2] = 0ull;
+    g->sir_ticket = 0u;
 }
 
 // Zero the grid records, the histogram and the scan tiles; empty the batch slot table.

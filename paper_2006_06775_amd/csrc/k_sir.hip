@@ -139,22 +139,38 @@ __global__ __launch_bounds__(kBlock) void k_sir(Slots sl, const double4 *__restr
     }
 }
 
-// The S/I/R totals of a plain step: the sum of the tiles' counts (one workgroup).
+// The S/I/R totals of a plain step: the tiles' counts summed by kTotalGroups workgroups.  Each
+// adds its share to an accumulator, and the last one to finish (a ticket) records the totals and
+// resets the accumulator and the ticket for the next step.  (One workgroup took 18 us for the
+// 39 063 tiles of 10^7 agents.)
 constexpr int kTotalThreads = 1024;
+constexpr unsigned kTotalGroups = 64;
 __global__ __launch_bounds__(kTotalThreads) void k_sir_total(GridDev *g, const uint32_t *__restrict__ tile_counts,
                                                              int64_t ntiles) {
+    __shared__ unsigned long long s_part[kTotalThreads / 64][3];
     unsigned long long v[3] = {0ull, 0ull, 0ull};
-    for (int64_t t = threadIdx.x; t < ntiles; t += kTotalThreads)
+    for (int64_t t = int64_t(blockIdx.x) * kTotalThreads + threadIdx.x; t < ntiles;
+         t += int64_t(gridDim.x) * kTotalThreads)
         for (int k = 0; k < 3; ++k) v[k] += tile_counts[4 * t + k];
-    __shared__ unsigned long long s_sum[kTotalThreads][3];
-    for (int k = 0; k < 3; ++k) s_sum[threadIdx.x][k] = v[k];
+    for (int d = 32; d >= 1; d >>= 1)
+        for (int k = 0; k < 3; ++k) v[k] += __shfl_xor(v[k], d, 64);
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 3; ++k) s_part[threadIdx.x >> 6][k] = v[k];
     __syncthreads();
-    for (int off = kTotalThreads / 2; off > 0; off >>= 1) {
-        if (int(threadIdx.x) < off)
-            for (int k = 0; k < 3; ++k) s_sum[threadIdx.x][k] += s_sum[threadIdx.x + off][k];
-        __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int k = 0; k < 3; ++k) {
+        unsigned long long sum = 0ull;
+        for (int w = 0; w < kTotalThreads / 64; ++w) sum += s_part[w][k];
+        atomicAdd(&g->sir_acc[k], sum);
     }
-    if (threadIdx.x < 3) g->sir_counts[threadIdx.x] = s_sum[0][threadIdx.x];
+    __threadfence();
+    if (atomicAdd(&g->sir_ticket, 1u) != gridDim.x - 1) return;
+    __threadfence();
+    for (int k = 0; k < 3; ++k) {
+        g->sir_counts[k] = atomicAdd(&g->sir_acc[k], 0ull);
+        g->sir_acc[k] = 0ull;
+    }
+    g->sir_ticket = 0u;
 }
 
 // Test hook: SIR contacts (any state) per sorted slot, boxes visited in (dz, dy, dx) order.
@@ -210,7 +226,7 @@ void launch_sir(const bdm_soa &s, const Slots &sl, int64_t capacity, const SirAr
     uint32_t *tile_counts = reinterpret_cast<uint32_t *>(w.partials);
     hipLaunchKernelGGL(k_sir, dim3(unsigned(nb)), dim3(kBlock), 0, st, sl, w.pos4, w.state, w.ids, w.flagid, a, s,
                        tile_counts);
-    hipLaunchKernelGGL(k_sir_total, dim3(1), dim3(kTotalThreads), 0, st, sl.grids, tile_counts, nb);
+    hipLaunchKernelGGL(k_sir_total, dim3(kTotalGroups), dim3(kTotalThreads), 0, st, sl.grids, tile_counts, nb);
 }
 
 void launch_contacts(const ContactArgs &a, const Slots &sl, const Ws &w, uint32_t *counts,
