@@ -169,8 +169,9 @@ typedef struct bdm_batch {
     int64_t max_boxes;     /* length of the packed histogram */
     int32_t slots;         /* number of slots (1..BDM_MAX_SLOTS) */
     int32_t grid_cap;      /* work split: workgroups the per-tile launches of bdm_batch_step deal
-                              the packed tiles to, striding (0 = 8192; else 64..65536).  Results
-                              do not depend on it; keep it fixed while a step is captured. */
+                              the packed tiles to, striding (0 = 8192; else 64..65536), or -1:
+                              one workgroup per tile.  Results do not depend on it; keep it fixed
+                              while a step is captured. */
 } bdm_batch;
 
 /* Size in bytes of the workspace for `capacity` agents and `max_boxes` boxes; 0 when either is

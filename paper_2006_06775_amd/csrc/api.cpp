@@ -69,8 +69,8 @@ int get_ws(const bdm_workspace *ws, bdm::Ws *out) {
 int get_batch(const bdm_batch *b, bdm::Ws *out) {
     if (!b) return fail(BDM_ENOWS, "batch is NULL");
     if (b->slots < 1 || b->slots > BDM_MAX_SLOTS) return fail(BDM_EINVAL, "batch slots must be in [1, %d]", BDM_MAX_SLOTS);
-    if (b->grid_cap != 0 && (b->grid_cap < 64 || b->grid_cap > 65536))
-        return fail(BDM_EINVAL, "batch grid_cap must be 0 or in [64, 65536]");
+    if (b->grid_cap != 0 && b->grid_cap != -1 && (b->grid_cap < 64 || b->grid_cap > 65536))
+        return fail(BDM_EINVAL, "batch grid_cap must be 0, -1 or in [64, 65536]");
     return view(b->ptr, b->bytes, b->capacity, b->max_boxes, b->slots, out);
 }
 

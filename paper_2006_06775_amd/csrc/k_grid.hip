@@ -999,10 +999,12 @@ static inline unsigned blocks_for(int64_t n, int64_t per = kBlock) {
 }
 
 // Workgroups of a per-tile launch: one per tile for a plain call; a batch strides over its
-// tiles with at most kBatchGrid workgroups, so empty capacity costs a table read, not a dispatch.
+// tiles with at most grid_cap workgroups (0: 8192), so empty capacity costs a table read, not a
+// dispatch, or (grid_cap -1) takes one workgroup per tile as well.
 unsigned tile_grid(const Slots &sl, int64_t ntiles) {
-    const int64_t cap = sl.grid_cap > 0 ? sl.grid_cap : 8192;
     if (ntiles < 1) return 1;
+    if (sl.grid_cap < 0) return unsigned(ntiles);
+    const int64_t cap = sl.grid_cap > 0 ? sl.grid_cap : 8192;
     return unsigned(sl.table && ntiles > cap ? cap : ntiles);
 }
 

@@ -763,6 +763,21 @@ __global__ __launch_bounds__(kBlock) void k_mech_batch(Slots sl, int64_t ntiles,
         mech_tile<0, kQueue, Tr>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q, nullptr, tout);
 }
 
+// Batch, one workgroup per tile (the work split that deals every tile its own workgroup): without
+// the striding loop the kernel needs 76 registers and runs six wavefronts per SIMD; the striding
+// form needs 113 and runs four.
+template <class Tr, class Rec>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_mech_batch_tile(
+    Slots sl, int64_t ntiles, Rec rec, const double *__restrict__ adh_s, const uint32_t *__restrict__ id_s,
+    const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s, const uint32_t *__restrict__ start,
+    bdm_soa out, TraceOut tout) {
+    __shared__ uint2 s_run[9][kBlock];
+    __shared__ uint32_t s_q[kQueue][kBlock];
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile < ntiles)
+        mech_tile<0, kQueue, Tr>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q, nullptr, tout);
+}
+
 // Test hook: contact lists per sorted slot in force-sum order (mechanical contact, plain calls).
 __global__ __launch_bounds__(kBlock) void k_contacts_mech(Slots sl, const double4 *__restrict__ pos4,
                                                           const uint32_t *__restrict__ id_s,
@@ -827,6 +842,9 @@ static void launch_mech_rec(const bdm_soa &s, const Slots &sl, int64_t ntiles, u
         BDM_MECH(k_mech, 32);
     } else if (precision == 64) {
         BDM_MECH(k_mech, 64);
+    } else if (int64_t(nb) >= ntiles) {  // a workgroup for every tile
+        hipLaunchKernelGGL((k_mech_batch_tile<Tr, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, ntiles, rec, w.adh,
+                           w.ids, w.state, w.rank, w.start, s, tout);
     } else {
         hipLaunchKernelGGL((k_mech_batch<Tr, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, ntiles, rec, w.adh, w.ids,
                            w.state, w.rank, w.start, s, tout);

@@ -29,7 +29,7 @@ from dataclasses import dataclass, field
 
 SIZE_CLASSES = (1_000, 10_000, 100_000, 1_000_000)
 FACTORS = (1.0, 1.2, 1.4)
-GRID_CAPS = (2048, 4096, 8192, 16384, 32768)
+GRID_CAPS = (2048, 4096, 8192, 16384, 32768, -1)  # -1: one workgroup per tile
 DEFAULT_CAP = 8192
 CLASS_AGENTS = 2_000_000  # agents per size-class batch (at least one simulation)
 

@@ -51,9 +51,9 @@ def layout(mix):
     return out, off, boff
 
 
-def run_batch(mix, slots=8, late=()):
+def run_batch(mix, slots=8, late=(), grid_cap=0):
     lay, cap, boxes = layout(mix)
-    b = bdm.Batch(cap, boxes, slots)
+    b = bdm.Batch(cap, boxes, slots, grid_cap=grid_cap)
     started = set()
 
     def start(i):
@@ -81,9 +81,12 @@ def run_batch(mix, slots=8, late=()):
     return out
 
 
-def test_batch_equals_alone_bitwise():
-    say("case: batch mix vs alone")
-    got = run_batch(MIX, late=(1, 4))
+@pytest.mark.parametrize("grid_cap", [0, -1, 64])
+def test_batch_equals_alone_bitwise(grid_cap):
+    """Every slot equals its plain run bit for bit, whatever the work split: the default striding
+    grid, one workgroup per tile (its own mechanics kernel), and a tiny striding grid."""
+    say(f"case: batch mix vs alone, grid_cap {grid_cap}")
+    got = run_batch(MIX, late=(1, 4), grid_cap=grid_cap)
     for i, m in enumerate(MIX):
         ref = alone(*m)
         for k in ("x", "y", "z", "fx", "fy", "fz"):
@@ -156,6 +159,9 @@ def test_batch_graph_replay():
 
 def test_batch_validation():
     say("case: batch validation")
+    for bad in (-2, 1, 63, 65537):
+        with pytest.raises(bdm.BdmError):
+            bdm.Batch(4096, 10000, 2, grid_cap=bad)
     b = bdm.Batch(4096, 10000, 2)
     with pytest.raises(bdm.BdmError):
         b.set_slot(0, 100, 1000, 0, 1000, 1, bdm.params())  # misaligned
