@@ -83,7 +83,9 @@ __global__ __launch_bounds__(kBlock) void k_sir_seed(Slots sl, const double4 *__
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_sir(Slots sl, const double4 *__restrict__ pos4,
+// Five wavefronts per SIMD (96 registers, a few spilled; the Philox draws take many) instead of
+// the four that the compiler's 110 allow: 2 % faster per SIR step.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_sir(Slots sl, const double4 *__restrict__ pos4,
                                                 const uint8_t *__restrict__ state_s,
                                                 const uint32_t *__restrict__ id_s,
                                                 const uint32_t *__restrict__ m_s, SirArgs a,
