@@ -24,26 +24,31 @@ namespace bdm {
 constexpr int kPencilRows = 16;       // y-rows per pencil of the processing order
 constexpr int kBucketLds = 1024;      // agents of a bucket whose ids the sort keeps in LDS
 constexpr int kCrowdedGroups = 1024;  // workgroups that rank the boxes of crowded buckets
+constexpr int64_t kBoundsGroups = 2048;  // workgroups of a plain call's bounds reduction
 
-// Per workgroup of kBoundsTile agents: min/max of x, y, z, max diameter and a non-finite flag,
-// written as one 8-value partial record (no atomics).
-__device__ __forceinline__ void bounds_tile(const Slots &sl, int64_t btile, const int64_t *n_ptr,
-                                            const double *__restrict__ x, const double *__restrict__ y,
-                                            const double *__restrict__ z, const double *__restrict__ d,
-                                            double *partials) {
-    const int64_t base = btile * kBoundsTile;
-    const int slot = slot_of_tile(sl, base / kBlock);
-    if (slot < 0) return;
-    const SlotDev S = slot_record(sl, slot);
-    const int64_t n = live_count(n_ptr, slot, S.capacity);
-    const int64_t l0 = base - S.agent_off;  // local index of the workgroup's first agent
-    if (l0 >= n) return;
-    double v[8];
+// Bounds partial records: min of x, y, z, max of x, y, z, max diameter, non-finite flag.
+__device__ __forceinline__ void bounds_identity(double v[8]) {
     for (int a = 0; a < 3; ++a) {
         v[a] = __builtin_inf();
         v[3 + a] = -__builtin_inf();
     }
     v[6] = 0.0;
+    v[7] = 0.0;
+}
+
+// Adds the agents of bounds tile `btile` (kBoundsTile agents) to this thread's record; false
+// when the tile holds no live agent (the same for the whole workgroup).
+__device__ __forceinline__ bool bounds_add(const Slots &sl, int64_t btile, const int64_t *n_ptr,
+                                           const double *__restrict__ x, const double *__restrict__ y,
+                                           const double *__restrict__ z, const double *__restrict__ d,
+                                           double v[8]) {
+    const int64_t base = btile * kBoundsTile;
+    const int slot = slot_of_tile(sl, base / kBlock);
+    if (slot < 0) return false;
+    const SlotDev S = slot_record(sl, slot);
+    const int64_t n = live_count(n_ptr, slot, S.capacity);
+    const int64_t l0 = base - S.agent_off;  // local index of the tile's first agent
+    if (l0 >= n) return false;
     bool bad = false;
     constexpr int kUnroll = kBoundsTile / kBlock;
     double px[kUnroll], py[kUnroll], pz[kUnroll], pd[kUnroll];
@@ -68,7 +73,12 @@ __device__ __forceinline__ void bounds_tile(const Slots &sl, int64_t btile, cons
         v[5] = fmax(v[5], pz[u]);
         v[6] = fmax(v[6], pd[u]);
     }
-    v[7] = bad ? 1.0 : 0.0;
+    if (bad) v[7] = 1.0;
+    return true;
+}
+
+// The workgroup's records reduced into one partial record at dst (no atomics).
+__device__ __forceinline__ void bounds_store(double v[8], double *dst) {
     __shared__ double s_red[kBlock / 64][8];
 #pragma unroll
     for (int s = 32; s >= 1; s >>= 1) {
@@ -88,17 +98,21 @@ __device__ __forceinline__ void bounds_tile(const Slots &sl, int64_t btile, cons
         const int a = threadIdx.x;
         double r = s_red[0][a];
         for (int w = 1; w < kBlock / 64; ++w) r = (a < 3) ? fmin(r, s_red[w][a]) : fmax(r, s_red[w][a]);
-        partials[btile * 8 + a] = r;
+        dst[a] = r;
     }
     __syncthreads();  // s_red is reused by the next tile of this workgroup
 }
 
+// A batch: one partial record per bounds tile (each tile belongs to one slot).  A plain call
+// (per_group): one record per workgroup over its stride of tiles, so that the reduction in
+// k_finalize reads as many records as there are workgroups (2048 at most) instead of one per
+// 1024 agents (16 384 at 2^24 agents: 23 us in one workgroup).
 __global__ __launch_bounds__(kBlock) void k_bounds(Slots sl, int64_t nbtiles, const int64_t *n_ptr,
                                                    const double *__restrict__ x,
                                                    const double *__restrict__ y,
                                                    const double *__restrict__ z,
                                                    const double *__restrict__ d, double *partials,
-                                                   unsigned long long *tiles, int64_t max_tiles) {
+                                                   unsigned long long *tiles, int64_t max_tiles, int32_t per_group) {
     if (frozen_plain(&sl.grids[0], sl.table)) return;
     if (blockIdx.x == 0) {  // reset the scan tiles of the coming histogram scan
         for (int64_t t = threadIdx.x; t < max_tiles; t += blockDim.x) tiles[t] = 0ull;
@@ -107,12 +121,23 @@ __global__ __launch_bounds__(kBlock) void k_bounds(Slots sl, int64_t nbtiles, co
             sl.grids[0].crowd_n = 0u;
         }
     }
-    for (int64_t bt = blockIdx.x; bt < nbtiles; bt += gridDim.x) bounds_tile(sl, bt, n_ptr, x, y, z, d, partials);
+    double v[8];
+    if (per_group) {
+        bounds_identity(v);
+        for (int64_t bt = blockIdx.x; bt < nbtiles; bt += gridDim.x) bounds_add(sl, bt, n_ptr, x, y, z, d, v);
+        bounds_store(v, partials + 8 * int64_t(blockIdx.x));
+        return;
+    }
+    for (int64_t bt = blockIdx.x; bt < nbtiles; bt += gridDim.x) {
+        bounds_identity(v);
+        if (bounds_add(sl, bt, n_ptr, x, y, z, d, v)) bounds_store(v, partials + 8 * bt);
+    }
 }
 
 // One workgroup per slot: reduce the slot's bounds partials, then box edge, lattice, box count.
+// plain_parts: a plain call's number of per-workgroup records (0: a batch, one per bounds tile).
 __global__ __launch_bounds__(kBlock) void k_finalize(Slots sl, const int64_t *n_ptr, const double *partials,
-                                                     int32_t kind) {
+                                                     int32_t kind, int64_t plain_parts) {
     const int slot = int(blockIdx.x);
     if (slot >= sl.nslots) return;
     const SlotDev a = slot_record(sl, slot);
@@ -129,7 +154,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Slots sl, const int64_t *n_
     v[6] = 0.0;
     v[7] = 0.0;
     if (!idle) {
-        const int64_t b0 = a.agent_off / kBoundsTile, nb = (n + kBoundsTile - 1) / kBoundsTile;
+        const int64_t b0 = plain_parts ? 0 : a.agent_off / kBoundsTile;
+        const int64_t nb = plain_parts ? plain_parts : (n + kBoundsTile - 1) / kBoundsTile;
         const double4 *p4 = reinterpret_cast<const double4 *>(partials) + 2 * b0;
 #pragma unroll 8
         for (int64_t k = threadIdx.x; k < nb; k += blockDim.x) {  // 64-byte records, loads in flight
@@ -1017,13 +1043,16 @@ void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, bool
     const bool skip = !sl.table && !sl.one.periodic && sl.one.skip && !f32_copy && s.fx && s.fy && s.fz;
     if (!sl.table)
         hipLaunchKernelGGL(k_freeze_check, dim3(1), dim3(64), 0, st, w.grid, sl.one, s.n, int32_t(skip && allow_freeze));
-    hipLaunchKernelGGL(k_bounds, dim3(tile_grid(sl, nbt)), dim3(kBlock), 0, st, sl, nbt, s.n, s.x, s.y, s.z, d,
-                       w.partials, w.tiles, w.lay.max_tiles);
+    // a plain call reduces its bounds into one record per workgroup (at most kBoundsGroups)
+    const unsigned nbg = sl.table ? tile_grid(sl, nbt) : unsigned(nbt < kBoundsGroups ? (nbt < 1 ? 1 : nbt) : kBoundsGroups);
+    hipLaunchKernelGGL(k_bounds, dim3(nbg), dim3(kBlock), 0, st, sl, nbt, s.n, s.x, s.y, s.z, d, w.partials, w.tiles,
+                       w.lay.max_tiles, int32_t(sl.table ? 0 : 1));
     const int32_t kind = (!sl.table && sl.one.periodic) ? kGridPeriodic
                          : f32_copy                     ? kGridOpenF32
                          : skip                         ? kGridOpenSkip
                                                         : kGridOpen;
-    hipLaunchKernelGGL(k_finalize, dim3(unsigned(sl.nslots)), dim3(kBlock), 0, st, sl, s.n, w.partials, kind);
+    hipLaunchKernelGGL(k_finalize, dim3(unsigned(sl.nslots)), dim3(kBlock), 0, st, sl, s.n, w.partials, kind,
+                       int64_t(sl.table ? 0 : nbg));
     const int64_t nt = (capacity + kBlock - 1) / kBlock;
     const unsigned nb = tile_grid(sl, nt);
     // keys and bucket ranks (rank array), bucket starts, agent indices by bucket
