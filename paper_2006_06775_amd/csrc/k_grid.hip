@@ -2,7 +2,8 @@
 // centre, box edge from the largest agent, 27-box neighbourhood).
 //
 // Pipeline for every slot at once (one launch each, all device-resident, no host read-back):
-//   bounds     min/max of x, y, z and max diameter per 1024 agents (one partial record each)
+//   bounds     min/max of x, y, z and max diameter: one partial record per 1024 agents (batch)
+//              or per workgroup (plain call)
 //   finalize   one workgroup per slot: reduce its partials, box edge, lattice origin and dims,
 //              box count check
 //   key_count  box key per agent and its arrival rank in the box (integer atomics)
