@@ -75,3 +75,9 @@ def test_tune_pick_and_plan_lookup():
     assert tune.pick_cap({4096: 0.99e-9, 8192: 1.0e-9}) == 8192
     assert tune.pick_cap({4096: 0.97e-9, 8192: 1.0e-9}) == 4096
     assert tune.pick_cap({2048: 1.0e-9, 16384: 2e-9}) == 2048  # default not measured
+    # one workgroup per tile (-1) competes like any other split
+    assert tune.pick_cap({-1: 0.145e-9, 8192: 0.187e-9, 32768: 0.146e-9}) == -1
+    assert tune.pick_cap({-1: 0.186e-9, 8192: 0.187e-9}) == 8192
+    assert -1 in tune.GRID_CAPS
+    summary = tune.BoxPlan(15.0, {1000: 1.0}, grid_cap=-1, split_table={-1: 1e-10, 8192: 2e-10}).summary()
+    assert summary["grid_cap"] == -1 and set(summary["split_ns_per_agent_update"]) == {"-1", "8192"}
