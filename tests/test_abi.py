@@ -78,6 +78,23 @@ def test_validation_without_gpu():
     assert bdm.workspace_bytes(1 << 22, 1 << 20) > bdm.NOALLOC_SCRATCH_BYTES
 
 
+def test_batch_work_split_validation_without_gpu():
+    """The batch's work split is checked on the host before anything else: 0 (the default
+    stride), -1 (one workgroup per tile) or 64..65536 workgroups."""
+    from paper_2006_06775_amd import bdm
+    lib = bdm.lib()
+    nbytes = bdm.batch_workspace_bytes(4096, 10000, 2)
+    p = bdm.params()
+    for cap, ok in ((0, True), (-1, True), (64, True), (65536, True), (-2, False), (1, False), (63, False),
+                    (65537, False)):
+        rec = bdm.BatchRec(0x100000000, nbytes, 4096, 10000, 2, cap)
+        # slot 2 is outside a batch of two slots: an accepted split gets that far
+        rc = lib.bdm_batch_set_slot(C.byref(rec), 2, 0, 1024, 0, 64, 1, C.byref(p), None)
+        assert rc == bdm.EINVAL, cap
+        msg = lib.bdm_last_error()
+        assert (b"grid_cap" in msg) != ok, (cap, msg)
+
+
 def test_substance_and_hull_validation_without_gpu():
     from paper_2006_06775_amd import bdm
     lib = bdm.lib()
