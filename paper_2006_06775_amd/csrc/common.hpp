@@ -83,6 +83,8 @@ struct GridDev {
     uint32_t consume_ticket;        // workgroups of that sum done (0 between steps)
     unsigned long long sir_acc[3];  // a SIR step's S/I/R totals while its workgroups sum them (0 between steps)
     uint32_t sir_ticket;            // workgroups of that sum done (0 between steps)
+    int32_t rekey;                  // a build whose keys on the last lattice do not stand: key again
+    int32_t rezero;                 // ... and clear the histogram those keys counted into first
 };
 static_assert(sizeof(GridDev) <= 256, "grid record must fit its slot");
 

@@ -90,6 +90,8 @@ __device__ void clear_grid(GridDev *g) {
     g->consume_ticket = 0u;
     g->sir_acc[0] = g->sir_acc[1] = g->sir_acc[2] = 0ull;
     g->sir_ticket = 0u;
+    g->rekey = 0;
+    g->rezero = 0;
 }
 
 // Zero the grid records, the histogram and the scan tiles; empty the batch slot table.

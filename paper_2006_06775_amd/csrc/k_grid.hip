@@ -7,6 +7,9 @@
 //   finalize   one workgroup per slot: reduce its partials, box edge, lattice origin and dims,
 //              box count check
 //   key_count  box key per agent and its arrival rank in the box (integer atomics)
+//   A plain build (other than spheroid and skipping steps) fuses the first and third: it keys
+//   the agents on the last build's lattice while it reduces their bounds, and keys them again
+//   only when finalize finds that the lattice moved.
 //   scan       single-pass decoupled look-back exclusive scan of the packed histogram
 //   scatter    ids into their box range in arrival order
 //   canon      each agent counts the smaller ids in its box (ascending-id order inside a box)
@@ -137,13 +140,20 @@ __global__ __launch_bounds__(kBlock) void k_bounds(Slots sl, int64_t nbtiles, co
 
 // One workgroup per slot: reduce the slot's bounds partials, then box edge, lattice, box count.
 // plain_parts: a plain call's number of per-workgroup records (0: a batch, one per bounds tile).
+// spec (plain calls): k_key_spec has already keyed and counted the agents on the last build's
+// lattice if that build succeeded; this build keeps those keys when its lattice is the same,
+// and otherwise asks for the histogram to be cleared (if anything was counted) and for the keys
+// to be taken again.
 __global__ __launch_bounds__(kBlock) void k_finalize(Slots sl, const int64_t *n_ptr, const double *partials,
-                                                     int32_t kind, int64_t plain_parts) {
+                                                     int32_t kind, int64_t plain_parts, int32_t spec) {
     const int slot = int(blockIdx.x);
     if (slot >= sl.nslots) return;
     const SlotDev a = slot_record(sl, slot);
     GridDev *g = &sl.grids[slot];
     if (frozen_plain(g, sl.table)) return;
+    const bool counted = spec && g->valid && g->nboxes > 0;  // k_key_spec counted on the last lattice
+    g->rekey = 0;
+    g->rezero = counted ? 1 : 0;  // a build that fails clears what was counted
     const int64_t n_raw = n_ptr[slot];
     const int64_t n = live_count(n_ptr, slot, a.capacity);
     const bool idle = a.steps_left <= 0 || a.capacity <= 0;
@@ -288,9 +298,14 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Slots sl, const int64_t *n_
     g->div_nx = fastdiv_magic(uint32_t(g->dims[0]));
     g->div_ny = fastdiv_magic(uint32_t(g->dims[1]));
     // keys index the same boxes as in the last build only on the same lattice
-    g->skip_ok = marks && g->b == prev_b && g->cmin[0] == prev_cmin[0] && g->cmin[1] == prev_cmin[1] &&
-                 g->cmin[2] == prev_cmin[2] && g->dims[0] == prev_dims[0] && g->dims[1] == prev_dims[1] &&
-                 g->dims[2] == prev_dims[2];
+    const bool same = g->b == prev_b && g->cmin[0] == prev_cmin[0] && g->cmin[1] == prev_cmin[1] &&
+                      g->cmin[2] == prev_cmin[2] && g->dims[0] == prev_dims[0] && g->dims[1] == prev_dims[1] &&
+                      g->dims[2] == prev_dims[2];
+    g->skip_ok = marks && same;
+    if (spec) {
+        g->rekey = counted && same ? 0 : 1;
+        g->rezero = counted && !same ? 1 : 0;
+    }
     g->valid = 1;
 }
 
@@ -359,13 +374,15 @@ __device__ __forceinline__ KeyGrid key_grid(const Slots &sl, int slot) {
 // reads its one grid record once per group.
 // dirty / moved (plain calls that skip stationary agents, else NULL): the box of every agent
 // that moved in the last step is marked (the box it entered; the step marked the one it left).
+// gated (plain calls after k_key_spec): runs only when the build asked for the keys again.
 __global__ __launch_bounds__(kBlock) void k_key_bucket(Slots sl, int64_t ntiles, const double *__restrict__ x,
                                                        const double *__restrict__ y,
                                                        const double *__restrict__ z, uint32_t *count,
                                                        uint32_t *__restrict__ key,
                                                        uint32_t *__restrict__ brank, uint8_t *dirty,
-                                                       const uint8_t *__restrict__ moved) {
+                                                       const uint8_t *__restrict__ moved, int32_t gated) {
     if (frozen_plain(&sl.grids[0], sl.table)) return;
+    if (gated && !sl.grids[0].rekey) return;
     const int lane = threadIdx.x & 63;
     const bool mark = dirty && sl.grids[0].skip_ok;
     const int64_t ngroups = (ntiles + kKeyTiles - 1) / kKeyTiles;
@@ -412,6 +429,99 @@ __global__ __launch_bounds__(kBlock) void k_key_bucket(Slots sl, int64_t ntiles,
             if (mark && moved[r[u].i]) dirty[r[u].k] = 1;
         }
     }
+}
+
+// A plain build's first pass: the bounds of the agents (one record per workgroup, as k_bounds
+// writes them) and, on trust, every agent's key and bucket rank on the last build's lattice,
+// counted into the histogram.  Agents move by at most the clamp in a step, so in a running
+// simulation the lattice seldom changes, and the coordinates are then read once per build
+// instead of twice.  k_finalize keeps the keys when the bounds give the same lattice (box edge,
+// origin and dims; the keys depend on nothing else) and otherwise has the histogram cleared and
+// the keys taken again.  Nothing is counted when the last build failed, had no boxes or there
+// was none; a lane with a non-finite coordinate counts nothing either (its build fails).
+__global__ __launch_bounds__(kBlock) void k_key_spec(Slots sl, int64_t ntiles, const int64_t *n_ptr,
+                                                     const double *__restrict__ x, const double *__restrict__ y,
+                                                     const double *__restrict__ z, const double *__restrict__ d,
+                                                     uint32_t *count, uint32_t *__restrict__ key,
+                                                     uint32_t *__restrict__ brank, double *partials,
+                                                     unsigned long long *tiles, int64_t max_tiles) {
+    GridDev *g = &sl.grids[0];
+    if (blockIdx.x == 0) {  // reset the scan tiles of the coming histogram scan
+        for (int64_t t = threadIdx.x; t < max_tiles; t += blockDim.x) tiles[t] = 0ull;
+        if (threadIdx.x == 0) {
+            g->scan_ticket = 0u;
+            g->crowd_n = 0u;
+        }
+    }
+    const int lane = threadIdx.x & 63;
+    const SlotDev S = sl.one;
+    const int64_t n = live_count(n_ptr, 0, S.capacity);
+    const bool on_last = g->valid != 0 && g->nboxes > 0;  // a lattice with boxes to key into
+    KeyGrid k{};
+    k.per = S.periodic != 0;
+    k.b = g->b;
+    for (int a = 0; a < 3; ++a) {
+        k.cmin[a] = g->cmin[a];
+        k.dims[a] = g->dims[a];
+    }
+    double v[8];
+    bounds_identity(v);
+    bool bad = false;
+    const int64_t ngroups = (ntiles + kKeyTiles - 1) / kKeyTiles;
+    for (int64_t grp = xcd_tile(blockIdx.x, gridDim.x); grp < ngroups; grp += gridDim.x) {
+        const int64_t tile = grp * kKeyTiles;
+        KeyLane r[kKeyTiles];
+        bool in[kKeyTiles];
+        double xv[kKeyTiles], yv[kKeyTiles], zv[kKeyTiles], dv[kKeyTiles];
+#pragma unroll
+        for (int u = 0; u < kKeyTiles; ++u) {
+            r[u] = KeyLane{};
+            r[u].i = S.agent_off + (tile + u) * kBlock + threadIdx.x;
+            in[u] = tile + u < ntiles && r[u].i - S.agent_off < n;
+            xv[u] = in[u] ? x[r[u].i] : 0.0;
+            yv[u] = in[u] ? y[r[u].i] : 0.0;
+            zv[u] = in[u] ? z[r[u].i] : 0.0;
+            dv[u] = in[u] && d ? d[r[u].i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kKeyTiles; ++u) {
+            if (!in[u]) continue;
+            const bool fin = __builtin_isfinite(xv[u]) && __builtin_isfinite(yv[u]) && __builtin_isfinite(zv[u]);
+            bad |= !fin || !__builtin_isfinite(dv[u]);
+            v[0] = fmin(v[0], xv[u]);
+            v[3] = fmax(v[3], xv[u]);
+            v[1] = fmin(v[1], yv[u]);
+            v[4] = fmax(v[4], yv[u]);
+            v[2] = fmin(v[2], zv[u]);
+            v[5] = fmax(v[5], zv[u]);
+            v[6] = fmax(v[6], dv[u]);
+            r[u].live = on_last && fin;
+            if (!r[u].live) continue;
+            const int cx = box_coord(xv[u], k.b, k.cmin[0], k.dims[0], k.per);
+            const int cy = box_coord(yv[u], k.b, k.cmin[1], k.dims[1], k.per);
+            const int cz = box_coord(zv[u], k.b, k.cmin[2], k.dims[2], k.per);
+            r[u].k = uint32_t(cx) + uint32_t(k.dims[0]) * (uint32_t(cy) + uint32_t(k.dims[1]) * uint32_t(cz));
+            r[u].bk = uint32_t((uint64_t(S.box_off) + r[u].k) >> kBucketShift);
+        }
+#pragma unroll
+        for (int u = 0; u < kKeyTiles; ++u) key_bucket_run(r[u], count);
+#pragma unroll
+        for (int u = 0; u < kKeyTiles; ++u) {
+            const uint32_t base = __shfl(r[u].base, r[u].head, 64);
+            if (!r[u].live) continue;
+            key[r[u].i] = r[u].k;
+            brank[r[u].i] = base + uint32_t(lane - r[u].head);
+        }
+    }
+    if (bad) v[7] = 1.0;
+    bounds_store(v, partials + 8 * int64_t(blockIdx.x));
+}
+
+// Clears the histogram that k_key_spec counted into when the build did not keep its keys.
+__global__ __launch_bounds__(kBlock) void k_count_clear(const GridDev *g, uint32_t *count, int64_t len) {
+    if (!g->rezero) return;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < len; i += int64_t(gridDim.x) * blockDim.x)
+        count[i] = 0u;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_prepare(unsigned long long *tiles, int64_t max_tiles,
@@ -1044,22 +1154,39 @@ void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, bool
     const bool skip = !sl.table && !sl.one.periodic && sl.one.skip && !f32_copy && s.fx && s.fy && s.fz;
     if (!sl.table)
         hipLaunchKernelGGL(k_freeze_check, dim3(1), dim3(64), 0, st, w.grid, sl.one, s.n, int32_t(skip && allow_freeze));
-    // a plain call reduces its bounds into one record per workgroup (at most kBoundsGroups)
-    const unsigned nbg = sl.table ? tile_grid(sl, nbt) : unsigned(nbt < kBoundsGroups ? (nbt < 1 ? 1 : nbt) : kBoundsGroups);
-    hipLaunchKernelGGL(k_bounds, dim3(nbg), dim3(kBlock), 0, st, sl, nbt, s.n, s.x, s.y, s.z, d, w.partials, w.tiles,
-                       w.lay.max_tiles, int32_t(sl.table ? 0 : 1));
     const int32_t kind = (!sl.table && sl.one.periodic) ? kGridPeriodic
                          : f32_copy                     ? kGridOpenF32
                          : skip                         ? kGridOpenSkip
                                                         : kGridOpen;
-    hipLaunchKernelGGL(k_finalize, dim3(unsigned(sl.nslots)), dim3(kBlock), 0, st, sl, s.n, w.partials, kind,
-                       int64_t(sl.table ? 0 : nbg));
     const int64_t nt = (capacity + kBlock - 1) / kBlock;
+    const int64_t nkg = (nt + kKeyTiles - 1) / kKeyTiles;
+    // Plain calls other than spheroid steps (whose box edge follows the growing cells) and
+    // skipping steps (whose keys also mark the boxes of movers) key the agents on the last
+    // lattice in the bounds pass, and again only if the lattice moved.  A plain call reduces its
+    // bounds into one record per workgroup (at most kBoundsGroups).
+    const bool spec = !sl.table && !skip && !f32_copy;
+    const unsigned nbg = sl.table ? tile_grid(sl, nbt)
+                         : spec   ? unsigned(nkg < kBoundsGroups ? (nkg < 1 ? 1 : nkg) : kBoundsGroups)
+                                  : unsigned(nbt < kBoundsGroups ? (nbt < 1 ? 1 : nbt) : kBoundsGroups);
+    if (spec)
+        hipLaunchKernelGGL(k_key_spec, dim3(nbg), dim3(kBlock), 0, st, sl, nt, s.n, s.x, s.y, s.z, d, w.count, w.key,
+                           w.rank, w.partials, w.tiles, w.lay.max_tiles);
+    else
+        hipLaunchKernelGGL(k_bounds, dim3(nbg), dim3(kBlock), 0, st, sl, nbt, s.n, s.x, s.y, s.z, d, w.partials,
+                           w.tiles, w.lay.max_tiles, int32_t(sl.table ? 0 : 1));
+    hipLaunchKernelGGL(k_finalize, dim3(unsigned(sl.nslots)), dim3(kBlock), 0, st, sl, s.n, w.partials, kind,
+                       int64_t(sl.table ? 0 : nbg), int32_t(spec));
     const unsigned nb = tile_grid(sl, nt);
     // keys and bucket ranks (rank array), bucket starts, agent indices by bucket
-    const unsigned nbk = tile_grid(sl, (nt + kKeyTiles - 1) / kKeyTiles);
-    hipLaunchKernelGGL(k_key_bucket, dim3(nbk), dim3(kBlock), 0, st, sl, nt, s.x, s.y, s.z, w.count, w.key, w.rank,
-                       skip ? w.dirty : nullptr, w.moved);
+    if (spec) {
+        hipLaunchKernelGGL(k_count_clear, dim3(64), dim3(kBlock), 0, st, w.grid, w.count, int64_t(w.lay.nbuckets));
+        hipLaunchKernelGGL(k_key_bucket, dim3(nbg), dim3(kBlock), 0, st, sl, nt, s.x, s.y, s.z, w.count, w.key,
+                           w.rank, nullptr, w.moved, int32_t(1));
+    } else {
+        hipLaunchKernelGGL(k_key_bucket, dim3(tile_grid(sl, nkg)), dim3(kBlock), 0, st, sl, nt, s.x, s.y, s.z,
+                           w.count, w.key, w.rank, skip ? w.dirty : nullptr, w.moved, int32_t(0));
+    }
+    const unsigned nbk = tile_grid(sl, nkg);
     launch_scan(w.count, w.bstart, nullptr, w.lay.nbuckets, w, 1, false, st, !sl.table);
     hipLaunchKernelGGL(k_bucket_scatter, dim3(nbk), dim3(kBlock), 0, st, sl, nt, w.key, w.rank, w.bstart, w.item,
                        capacity);

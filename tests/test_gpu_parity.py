@@ -130,6 +130,77 @@ def test_grid_lockstep_bit_exact(case):
     assert np.array_equal(start, rs)
 
 
+def test_grid_rebuilds_on_the_last_lattice():
+    """A plain build keys the agents on the last build's lattice while it reduces their bounds,
+    and keys them again only when the bounds give another lattice (after clearing what it
+    counted).  Every rebuild below must equal the oracle's grid of the same positions: the same
+    lattice with agents moved between boxes, the extremes moved (a new origin and dims), a
+    failed build in between (a non-finite coordinate), a changed box edge, and the periodic
+    lattice twice."""
+    say("case: grid rebuilds on the last lattice")
+    s = inputs.uniform_cube(5001, 230.0, seed=21)
+    n = len(s["x"])
+    pop = population(s, capacity=n, max_boxes=1 << 16)
+
+    def check(arr, p, **kw):
+        for k in "xyz":
+            pop.t[k][:n].copy_(torch.as_tensor(arr[k]))
+        bdm.grid_build(pop.soa, p, pop.ws)
+        info, key, order, start = bdm.grid_export(pop.ws)
+        assert info["valid"] == 1 and info["flags"] == 0
+        ref_info, rk, ro, rs = orc.grid(arr["x"], arr["y"], arr["z"], arr["d"], **kw)
+        assert info["b"] == ref_info["b"]
+        assert info["cmin"] == tuple(ref_info["cmin"]) and info["dims"] == tuple(ref_info["dims"])
+        assert np.array_equal(key, rk) and np.array_equal(order, ro) and np.array_equal(start, rs)
+        return info
+
+    pop.t["n"].fill_(0)                             # a last lattice without boxes
+    bdm.grid_build(pop.soa, mech_p(), pop.ws)
+    assert bdm.grid_info(pop.ws)["valid"] == 1 and bdm.grid_info(pop.ws)["nboxes"] == 0
+    pop.t["n"].fill_(n)
+    first = check(s, mech_p())                      # nothing counted: keyed once, after the bounds
+    again = check(s, mech_p())                      # the same positions on the last lattice
+    assert again["cmin"] == first["cmin"] and again["dims"] == first["dims"]
+    # agents exchange places (the bounds and so the lattice stay): keys on the last lattice stand
+    rng = np.random.default_rng(5)
+    perm = rng.permutation(n)
+    moved = {k: (v[perm] if k in "xyz" else v) for k, v in s.items()}
+    assert check(moved, mech_p())["dims"] == first["dims"]
+    # one agent leaves the lattice by five boxes: new dims, the counted histogram is cleared
+    far = {k: v.copy() for k, v in moved.items()}
+    far["x"][17] = far["x"].max() + 5.0 * first["b"]
+    assert check(far, mech_p())["dims"] != first["dims"]
+    # the lowest agent moves up into the lattice: a new origin
+    up = {k: v.copy() for k, v in far.items()}
+    low = int(np.argmin(up["z"]))
+    up["z"][low] = up["z"].max()
+    check(up, mech_p())
+    # a build that fails after counting on the last lattice, then a good one
+    bad = {k: v.copy() for k, v in up.items()}
+    bad["y"][300] = np.nan
+    for k in "xyz":
+        pop.t[k][:n].copy_(torch.as_tensor(bad[k]))
+    bdm.grid_build(pop.soa, mech_p(), pop.ws)
+    assert bdm.status(pop.ws, clear=True) & bdm.FLAG_NONFINITE
+    assert bdm.grid_info(pop.ws)["valid"] == 0
+    check(up, mech_p())
+    check(up, mech_p())
+    # an explicit box edge (another lattice), then the largest diameter again
+    check(up, mech_p(box=20.0), box=20.0)
+    check(up, mech_p(box=20.0), box=20.0)
+    check(up, mech_p())
+    # the periodic lattice, built twice
+    sp = inputs.sir_uniform(20000, 100.0, seed=2)
+    per = population(sp, spheres=False, state=True, max_boxes=30 ** 3)
+    p = bdm.params(box=4.0, periodic=1, L=100.0)
+    ref_info, rk, ro, rs = orc.grid(sp["x"], sp["y"], sp["z"], None, box=4.0, periodic=True, L=100.0)
+    for _ in range(2):
+        bdm.grid_build(per.soa, p, per.ws)
+        info, key, order, start = bdm.grid_export(per.ws)
+        assert info["valid"] == 1 and info["dims"] == (25, 25, 25)
+        assert np.array_equal(key, rk) and np.array_equal(order, ro) and np.array_equal(start, rs)
+
+
 def test_grid_periodic_bit_exact():
     say("case: grid periodic")
     s = inputs.sir_uniform(20000, 100.0, seed=1)
