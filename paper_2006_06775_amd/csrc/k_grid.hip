@@ -7,7 +7,7 @@
 //   finalize   one workgroup per slot: reduce its partials, box edge, lattice origin and dims,
 //              box count check
 //   key_count  box key per agent and its arrival rank in the box (integer atomics)
-//   A plain build (other than spheroid and skipping steps) fuses the first and third: it keys
+//   A plain build (other than a spheroid step's) fuses the first and third: it keys
 //   the agents on the last build's lattice while it reduces their bounds, and keys them again
 //   only when finalize finds that the lattice moved.
 //   scan       single-pass decoupled look-back exclusive scan of the packed histogram
@@ -439,13 +439,18 @@ __global__ __launch_bounds__(kBlock) void k_key_bucket(Slots sl, int64_t ntiles,
 // origin and dims; the keys depend on nothing else) and otherwise has the histogram cleared and
 // the keys taken again.  Nothing is counted when the last build failed, had no boxes or there
 // was none; a lane with a non-finite coordinate counts nothing either (its build fails).
+// dirty / moved (skipping steps, else NULL): the box of every agent that moved in the last step
+// is marked on the last lattice.  The marks count only when the build may skip (same lattice,
+// marks ready); the bucket sort clears every box's mark in any case.
 __global__ __launch_bounds__(kBlock) void k_key_spec(Slots sl, int64_t ntiles, const int64_t *n_ptr,
                                                      const double *__restrict__ x, const double *__restrict__ y,
                                                      const double *__restrict__ z, const double *__restrict__ d,
                                                      uint32_t *count, uint32_t *__restrict__ key,
                                                      uint32_t *__restrict__ brank, double *partials,
-                                                     unsigned long long *tiles, int64_t max_tiles) {
+                                                     unsigned long long *tiles, int64_t max_tiles, uint8_t *dirty,
+                                                     const uint8_t *__restrict__ moved) {
     GridDev *g = &sl.grids[0];
+    if (frozen_plain(g, false)) return;
     if (blockIdx.x == 0) {  // reset the scan tiles of the coming histogram scan
         for (int64_t t = threadIdx.x; t < max_tiles; t += blockDim.x) tiles[t] = 0ull;
         if (threadIdx.x == 0) {
@@ -511,6 +516,7 @@ __global__ __launch_bounds__(kBlock) void k_key_spec(Slots sl, int64_t ntiles, c
             if (!r[u].live) continue;
             key[r[u].i] = r[u].k;
             brank[r[u].i] = base + uint32_t(lane - r[u].head);
+            if (dirty && moved[r[u].i]) dirty[r[u].k] = 1;
         }
     }
     if (bad) v[7] = 1.0;
@@ -519,7 +525,7 @@ __global__ __launch_bounds__(kBlock) void k_key_spec(Slots sl, int64_t ntiles, c
 
 // Clears the histogram that k_key_spec counted into when the build did not keep its keys.
 __global__ __launch_bounds__(kBlock) void k_count_clear(const GridDev *g, uint32_t *count, int64_t len) {
-    if (!g->rezero) return;
+    if (frozen_plain(g, false) || !g->rezero) return;
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < len; i += int64_t(gridDim.x) * blockDim.x)
         count[i] = 0u;
 }
@@ -1160,17 +1166,16 @@ void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, bool
                                                         : kGridOpen;
     const int64_t nt = (capacity + kBlock - 1) / kBlock;
     const int64_t nkg = (nt + kKeyTiles - 1) / kKeyTiles;
-    // Plain calls other than spheroid steps (whose box edge follows the growing cells) and
-    // skipping steps (whose keys also mark the boxes of movers) key the agents on the last
-    // lattice in the bounds pass, and again only if the lattice moved.  A plain call reduces its
-    // bounds into one record per workgroup (at most kBoundsGroups).
-    const bool spec = !sl.table && !skip && !f32_copy;
+    // Plain calls other than spheroid steps (whose box edge follows the growing cells) key the
+    // agents on the last lattice in the bounds pass, and again only if the lattice moved.  A
+    // plain call reduces its bounds into one record per workgroup (at most kBoundsGroups).
+    const bool spec = !sl.table && !f32_copy;
     const unsigned nbg = sl.table ? tile_grid(sl, nbt)
                          : spec   ? unsigned(nkg < kBoundsGroups ? (nkg < 1 ? 1 : nkg) : kBoundsGroups)
                                   : unsigned(nbt < kBoundsGroups ? (nbt < 1 ? 1 : nbt) : kBoundsGroups);
     if (spec)
         hipLaunchKernelGGL(k_key_spec, dim3(nbg), dim3(kBlock), 0, st, sl, nt, s.n, s.x, s.y, s.z, d, w.count, w.key,
-                           w.rank, w.partials, w.tiles, w.lay.max_tiles);
+                           w.rank, w.partials, w.tiles, w.lay.max_tiles, skip ? w.dirty : nullptr, w.moved);
     else
         hipLaunchKernelGGL(k_bounds, dim3(nbg), dim3(kBlock), 0, st, sl, nbt, s.n, s.x, s.y, s.z, d, w.partials,
                            w.tiles, w.lay.max_tiles, int32_t(sl.table ? 0 : 1));
@@ -1181,7 +1186,7 @@ void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, bool
     if (spec) {
         hipLaunchKernelGGL(k_count_clear, dim3(64), dim3(kBlock), 0, st, w.grid, w.count, int64_t(w.lay.nbuckets));
         hipLaunchKernelGGL(k_key_bucket, dim3(nbg), dim3(kBlock), 0, st, sl, nt, s.x, s.y, s.z, w.count, w.key,
-                           w.rank, nullptr, w.moved, int32_t(1));
+                           w.rank, skip ? w.dirty : nullptr, w.moved, int32_t(1));
     } else {
         hipLaunchKernelGGL(k_key_bucket, dim3(tile_grid(sl, nkg)), dim3(kBlock), 0, st, sl, nt, s.x, s.y, s.z,
                            w.count, w.key, w.rank, skip ? w.dirty : nullptr, w.moved, int32_t(0));
