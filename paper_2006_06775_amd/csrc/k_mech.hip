@@ -252,6 +252,95 @@ __device__ __forceinline__ bool maybe_touch(const float4 &a, const float4 &c, fl
     return d2 < __builtin_fmaf(s, s, slack);
 }
 
+// Coarse all-pairs pre-test of a cooperative walk on the matrix cores: for the 64 agents of a
+// wavefront and a chunk of 64 candidate records, which pairs may pass maybe_touch.  With
+// coordinates relative to the wavefront's origin o (lane 0's record), a' = a - o, c' = c - o,
+// the test value is the dot product of the agent vector (a'x, a'y, a'z, a.w, 1, A) and the
+// candidate vector (-2c'x, -2c'y, -2c'z, -2c.w, C, 1), with
+//   A = |a'|^2 - a.w^2 - slack - k (|a'|^2 + a.w^2 + slack),  C = |c'|^2 - c.w^2 - k (|c'|^2 + c.w^2),
+// which is |a' - c'|^2 - (a.w + c.w)^2 - slack - k (|a'|^2 + a.w^2 + |c'|^2 + c.w^2 + slack):
+// maybe_touch's condition less a margin.  A pair is kept when the value is negative.  Each
+// rounding on either side (the shift, maybe_touch's own arithmetic, the matrix product, which
+// adds each pair of products with one rounding, measured) is below 2^-23 of these magnitudes,
+// and about 32 of them add up, so the margin k = 2^-14 keeps every pair maybe_touch passes; it
+// widens the kept shell by about k (|a'|^2 + |c'|^2) / (a.w + c.w)^2, below 0.1 % here.  The
+// survivors still go through maybe_touch, so the queue holds exactly what the plain walk puts
+// there, in the same order.
+// v_mfma_f32_32x32x2f32: lane l gives A[l % 32][l / 32] and B[l / 32][l % 32]; output element v
+// of lane l is D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].  Candidates are the rows (two blocks
+// of 32), agents the columns (two blocks of 32); K = 6 takes three products per block.
+constexpr float kCoarseMargin = 0x1p-14f;
+typedef float mfma16f __attribute__((ext_vector_type(16)));
+
+struct CoarseAgents {
+    float ox, oy, oz;  // wavefront origin
+    float b[2][3];     // B operand of agent block ab, product s: component 2s + (lane / 32)
+};
+
+__device__ __forceinline__ float first_lane(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
+// (every lane of the wavefront takes part)
+__device__ __forceinline__ CoarseAgents coarse_agents(const float4 &pf, float slack, int lane) {
+    CoarseAgents ca;
+    ca.ox = first_lane(pf.x);
+    ca.oy = first_lane(pf.y);
+    ca.oz = first_lane(pf.z);
+    const float ax = pf.x - ca.ox, ay = pf.y - ca.oy, az = pf.z - ca.oz, aw = pf.w;
+    const float a2 = __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax)), w2 = aw * aw;
+    const float aA = ((a2 - w2) - slack) - kCoarseMargin * ((a2 + w2) + slack);
+    const bool hi = lane >= 32;
+#pragma unroll
+    for (int ab = 0; ab < 2; ++ab) {
+        const int src = ab * 32 + (lane & 31);
+        const float sx = __shfl(ax, src, 64), sy = __shfl(ay, src, 64), sz = __shfl(az, src, 64);
+        const float sw = __shfl(aw, src, 64), sa = __shfl(aA, src, 64);
+        ca.b[ab][0] = hi ? sy : sx;
+        ca.b[ab][1] = hi ? sw : sz;
+        ca.b[ab][2] = hi ? sa : 1.0f;
+    }
+    return ca;
+}
+
+// Bit e of the result: candidate e of the chunk staged at stage[0..63] may touch this lane's
+// agent (every lane of the wavefront takes part; entries past the chunk's end give bits that
+// the caller masks off).
+__device__ __forceinline__ uint64_t coarse_mask(const CoarseAgents &ca, const float4 *stage, int lane) {
+    const int h = lane >> 5;
+    uint32_t mine[2];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const float4 c = stage[cb * 32 + (lane & 31)];
+        const float cx = c.x - ca.ox, cy = c.y - ca.oy, cz = c.z - ca.oz, cw = c.w;
+        const float c2 = __builtin_fmaf(cz, cz, __builtin_fmaf(cy, cy, cx * cx)), w2 = cw * cw;
+        const float cC = (c2 - w2) - kCoarseMargin * (c2 + w2);
+        const float a0 = -2.0f * (h ? cy : cx), a1 = -2.0f * (h ? cw : cz), a2 = h ? 1.0f : cC;
+        uint32_t w[2];
+#pragma unroll
+        for (int ab = 0; ab < 2; ++ab) {
+            mfma16f acc = {};
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, ca.b[ab][0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, ca.b[ab][1], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, ca.b[ab][2], acc, 0, 0, 0);
+            uint32_t bits = 0u;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {  // the sign bit: negative values are kept
+                const float x = acc[v];  // (a bit cast of acc[v] itself would read element 0)
+                bits |= (__float_as_uint(x) >> 31) << (8 * (v / 4) + (v % 4));
+            }
+            w[ab] = bits << (4 * h);
+        }
+        // this lane's agent is column lane % 32 of block lane / 32: its rows of the other half
+        // are with lane ^ 32, which sends its block-(1 - its half) word
+        const uint32_t other = uint32_t(__shfl_xor(int(h ? w[0] : w[1]), 32, 64));
+        mine[cb] = (h ? w[1] : w[0]) | other;
+    }
+    return uint64_t(mine[0]) | (uint64_t(mine[1]) << 32);
+}
+
+__device__ __forceinline__ uint64_t low_bits(uint32_t n) { return n >= 64u ? ~0ull : (1ull << n) - 1ull; }
+
 // Packed-record loads by candidate offset u in units of kUnit.  RecBuf: raw buffer resources
 // with 32-bit byte offsets when the sorted arrays are below 4 GiB (u is 16 times the sorted
 // position: the binary64 record sits at byte 2u, the 8-byte record at u / 2); out-of-range
@@ -504,6 +593,8 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
         // each record that lies in its own run, in order.  A lane's candidates thus come in its
         // canonical order.  The queues are emptied together when one of them could fill.
         const int lane = t & 63, w0 = t - lane;
+        [[maybe_unused]] CoarseAgents ca{};
+        if constexpr (Rec::kF32Copy) ca = coarse_agents(pf, slack, lane);
 #pragma unroll 1
         for (int r = 0; r < 9; ++r) {
             const uint32_t ulo = un.lo[r], uhi = un.hi[r];
@@ -515,6 +606,38 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
                 s_stage[t] = nxt;
                 if (base + 64u < uhi) nxt = rec.pre(min(base + 64u + uint32_t(lane), uhi - 1u) * U);
                 wave_lds_sync();
+                if constexpr (Rec::kF32Copy) {
+                    // the matrix cores pick the pairs that may touch, and those go to the queue in
+                    // ascending order within the lane's run (a pair that does not touch adds
+                    // nothing in the exact law)
+                    const uint32_t kn = min(64u, uhi - base);
+                    const uint32_t a = own.x > base ? min(own.x - base, kn) : 0u;
+                    const uint32_t b = own.y > base ? min(own.y - base, kn) : 0u;
+                    uint64_t m = coarse_mask(ca, &s_stage[w0], lane) & low_bits(b) & ~low_bits(a);
+                    if constexpr (Tr::kOn) {  // the traced kernels leave the agent itself out
+                        const uint32_t self = qu / U - base;
+                        if (self < 64u) m &= ~(1ull << self);
+                    }
+                    uint32_t lo = uint32_t(m), hi = uint32_t(m >> 32);
+                    uint32_t pc = uint32_t(__builtin_popcount(lo) + __builtin_popcount(hi));
+                    while (__any(pc != 0u)) {
+                        if (__any(qn == uint32_t(kQ))) flush();
+                        const uint32_t take = min(pc, uint32_t(kQ) - qn);
+                        for (uint32_t k = 0; k < take; ++k) {
+                            const bool low = lo != 0u;
+                            const uint32_t word = low ? lo : hi;
+                            const uint32_t e = uint32_t(__builtin_ctz(word)) + (low ? 0u : 32u);
+                            if (low)
+                                lo &= lo - 1u;
+                            else
+                                hi &= hi - 1u;
+                            s_q[qn + k][t] = (base + e) * U;
+                        }
+                        qn += take;
+                        pc -= take;
+                    }
+                    continue;
+                }
                 // four records per step, read from LDS together; the queues are emptied first
                 // when one of them could fill within the step.  [a, b) is the lane's own run
                 // within the chunk (entries past the chunk's end are valid LDS and outside it).

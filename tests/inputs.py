@@ -108,3 +108,18 @@ def separated_pairs(npairs, d, separation, spacing=40.0, coincident=0, seed=0):
     n = len(pos)
     return dict(x=pos[:, 0].copy(), y=pos[:, 1].copy(), z=pos[:, 2].copy(), d=np.full(n, float(d)),
                 adh=np.full(n, 0.4))
+
+
+def touching_lattice(m=8, spacing=2.5, d=10.0, jitter=1e-8, seed=0):
+    """A crowded block (m^3 spheres of diameter d on a cubic lattice of `spacing`, d / spacing an
+    integer, so every box holds many agents) in which every axis-aligned pair d apart touches
+    exactly, up to an x jitter of +-`jitter` per sphere: about half of those pairs overlap by
+    about `jitter` and the others miss by as much.  Far below the binary32 copies' rounding, it
+    puts many pairs on the contact boundary of every pre-test."""
+    r = np.random.default_rng(seed)
+    g = np.stack(np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij"), -1).reshape(-1, 3)
+    pos = g.astype(np.float64) * spacing + 5.0
+    pos[:, 0] += r.choice([-jitter, jitter], len(pos))
+    n = len(pos)
+    return dict(x=pos[:, 0].copy(), y=pos[:, 1].copy(), z=pos[:, 2].copy(), d=np.full(n, float(d)),
+                adh=np.full(n, 0.4))

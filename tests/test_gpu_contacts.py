@@ -75,6 +75,7 @@ def cases():
         "far": {k: (v + 1.0e9 if k in "xyz" else v) for k, v in inputs.uniform_cube(2000, 150.0, seed=6).items()},
         "crowded8": inputs.uniform_cube(1237, 20.0, dmin=10.0, dmax=10.0, seed=12),
         "equilibrium": equilibrium_case(),
+        "touching": inputs.touching_lattice(seed=5),
     }
     return c
 
@@ -97,7 +98,8 @@ def traced_step(s, bits, model):
     ("clustered", 64, "mech"), ("clustered", 32, "mech"), ("reach", 64, "mech"), ("reach", 32, "mech"),
     ("far", 64, "mech"), ("equilibrium", 64, "mech"), ("equilibrium", 32, "mech"),
     ("c0", 64, "crowded"), ("clustered", 32, "crowded"), ("crowded8", 64, "crowded"),
-    ("crowded8", 32, "crowded"), ("equilibrium", 64, "crowded")])
+    ("crowded8", 32, "crowded"), ("equilibrium", 64, "crowded"), ("touching", 64, "crowded"),
+    ("touching", 32, "crowded"), ("touching", 64, "mech")])
 def test_traced_contacts_match_oracle(case, bits, model):
     """Every contact the kernel adds, in its order, is the oracle's, for the plain kernel and
     for the spheroid model's crowded kernel (growth 1, no division: one mechanical step)."""
@@ -111,6 +113,9 @@ def test_traced_contacts_match_oracle(case, bits, model):
     assert len(bad) == 0, (bad[:10], counts[bad[:10]], ec[bad[:10]])
     if case == "equilibrium":
         assert ec.sum() >= 2 * 400 + 2 * 40  # every pair (both sides) is a contact
+    if case == "touching":  # pairs within 1e-6 of touching, on both sides of it
+        dd = np.sqrt(sum((s[k][:, None] - s[k][None, :]) ** 2 for k in "xyz"))
+        assert ((dd < 10.0) & (dd > 10.0 - 1e-6)).sum() >= 100 and ((dd >= 10.0) & (dd < 10.0 + 1e-6)).sum() >= 100
 
 
 def test_traced_step_results_equal_untraced():
