@@ -41,7 +41,9 @@ __global__ __launch_bounds__(kBlock) void k_sir_zero(Slots sl, uint32_t *__restr
 // susceptible agent would find among its own 27 boxes: the periodic box neighbourhood is
 // symmetric (at least 3 boxes per axis), and the differences are taken as susceptible minus
 // infected, exactly as the susceptible agent takes them.  The count is an integer, so the order
-// of the additions does not matter.  The work is proportional to the infected agents.
+// of the additions does not matter.  The work is proportional to the infected agents.  Each
+// wavefront takes its infected agents one at a time, one of its lanes per box of the agent's 27,
+// so an infected agent costs one box's chain of dependent loads, not 27 of them in a row.
 __global__ __launch_bounds__(kBlock) void k_sir_seed(Slots sl, const double4 *__restrict__ pos4,
                                                      const uint8_t *__restrict__ state_s,
                                                      const uint32_t *__restrict__ start_all, SirArgs a,
@@ -52,33 +54,33 @@ __global__ __launch_bounds__(kBlock) void k_sir_seed(Slots sl, const double4 *__
     const GridDev *g = &sl.grids[slot];
     const SlotDev S = slot_record(sl, slot);
     const int64_t l = tile * kBlock + threadIdx.x - S.agent_off;
-    if (!g->valid || l >= g->n || l >= S.capacity) return;
-    const uint32_t q = uint32_t(g->sorted_base + l);
-    if (state_s[q] != 1) return;
+    const bool live = g->valid && l < g->n && l < S.capacity;
+    const uint32_t q = live ? uint32_t(g->sorted_base + l) : 0u;
+    unsigned long long inf = __ballot(live && state_s[q] == 1);
+    if (!inf) return;  // (the whole wavefront)
     const uint32_t *start = start_all + S.box_off;
-    const double4 p = pos4[q];
     const int nb = g->dims[0];
     const double b = g->b;
-    const int cx = box_coord(p.x, b, 0, nb, true);
-    const int cy = box_coord(p.y, b, 0, nb, true);
-    const int cz = box_coord(p.z, b, 0, nb, true);
-    for (int oz = -1; oz <= 1; ++oz) {
-        const int zz = (cz + oz + nb) % nb;
-        for (int oy = -1; oy <= 1; ++oy) {
-            const int yy = (cy + oy + nb) % nb;
-            for (int ox = -1; ox <= 1; ++ox) {
-                const int xx = (cx + ox + nb) % nb;
-                const uint32_t kb = uint32_t(xx) + uint32_t(nb) * (uint32_t(yy) + uint32_t(nb) * uint32_t(zz));
-                const uint32_t j1 = start[kb + 1];
-                for (uint32_t j = start[kb]; j < j1; ++j) {
-                    if (state_s[j] != 0) continue;
-                    const double4 c = pos4[j];
-                    const double dx = min_image(c.x - p.x, a.L, a.half);
-                    const double dy = min_image(c.y - p.y, a.L, a.half);
-                    const double dz = min_image(c.z - p.z, a.L, a.half);
-                    if (((dx * dx + dy * dy) + dz * dz) <= a.r2) atomicAdd(&m[j], 1u);
-                }
-            }
+    const int lane = threadIdx.x & 63;
+    const int ox = lane % 3 - 1, oy = (lane / 3) % 3 - 1, oz = lane / 9 - 1;  // lanes 0-26
+    while (inf) {
+        const int k = __ffsll(static_cast<long long>(inf)) - 1;
+        inf &= inf - 1ull;
+        const uint32_t qi = uint32_t(__shfl(int(q), k, 64));
+        if (lane >= 27) continue;
+        const double4 p = pos4[qi];
+        const int xx = (box_coord(p.x, b, 0, nb, true) + ox + nb) % nb;
+        const int yy = (box_coord(p.y, b, 0, nb, true) + oy + nb) % nb;
+        const int zz = (box_coord(p.z, b, 0, nb, true) + oz + nb) % nb;
+        const uint32_t kb = uint32_t(xx) + uint32_t(nb) * (uint32_t(yy) + uint32_t(nb) * uint32_t(zz));
+        const uint32_t j1 = start[kb + 1];
+        for (uint32_t j = start[kb]; j < j1; ++j) {
+            if (state_s[j] != 0) continue;
+            const double4 c = pos4[j];
+            const double dx = min_image(c.x - p.x, a.L, a.half);
+            const double dy = min_image(c.y - p.y, a.L, a.half);
+            const double dz = min_image(c.z - p.z, a.L, a.half);
+            if (((dx * dx + dy * dy) + dz * dz) <= a.r2) atomicAdd(&m[j], 1u);
         }
     }
 }
