@@ -176,6 +176,8 @@ __global__ __launch_bounds__(kBlock) void k_geom_reach(const int64_t *n_ptr, int
     s.diam[i] = 2.0 * __builtin_sqrt(dot3(dx, dy, dz, dx, dy, dz)) + cyl.dc[id];
 }
 
+constexpr int kGeomQueue = 16;  // candidates past the bounding-sphere test a lane holds (16 KB of LDS per workgroup)
+
 // Six wavefronts per SIMD (80 registers, a few spilled) instead of the four that the
 // compiler's 102 registers allow: measured 2.02 -> 1.95 ms per step of the neurite workload.
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_geom(GridDev *__restrict__ g, const double4 *__restrict__ pos4,
@@ -183,6 +185,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
                                                  const uint8_t *__restrict__ state_s,
                                                  const uint32_t *__restrict__ start, CylIn cyl, GeomArgs a,
                                                  bdm_soa out, uint32_t *counts) {
+    __shared__ uint32_t s_q[kGeomQueue][kBlock];  // each lane uses its own column only
     const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (!g->valid || s >= g->n) return;
     const double4 ri = pos4[s];
@@ -200,18 +203,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     const int nx = g->dims[0], ny = g->dims[1], nz = g->dims[2];
     double sx = 0.0, sy = 0.0, sz = 0.0;
     uint32_t contacts = 0;
-    for (int r = 0; r < 9; ++r) {
-        const int zz = cz + r / 3 - 1, yy = cy + r % 3 - 1;
-        if (zz < 0 || zz >= nz || yy < 0 || yy >= ny) continue;
-        const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < nx - 1 ? cx + 1 : nx - 1;
-        const uint32_t kb = uint32_t(x0) + uint32_t(nx) * (uint32_t(yy) + uint32_t(ny) * uint32_t(zz));
-        const uint32_t lo = start[kb] & kStartMask, hi = start[kb + uint32_t(x1 - x0) + 1u] & kStartMask;
-        for (uint32_t j = lo; j < hi; ++j) {
-            if (j == uint32_t(s)) continue;
+    // Candidates that pass the bounding-sphere test go to the lane's queue in walk order; the
+    // closest-point law runs over the queues when one fills and at the end.  Run inside the walk,
+    // it cost every lane of the wavefront a pair evaluation at nearly every candidate (some
+    // lane almost always passes); over the queues it runs as often as the longest queue.
+    uint32_t qn = 0;
+    const int t = threadIdx.x;
+    auto flush = [&]() {
+        for (uint32_t k = 0; k < qn; ++k) {
+            const uint32_t j = s_q[k][t];
             const double4 rj = pos4[j];
-            const double dx = ri.x - rj.x, dy = ri.y - rj.y, dz = ri.z - rj.z;
-            const double reach = ri.w + rj.w;
-            if (!((dx * dx + dy * dy) + dz * dz <= (reach * reach) * (1.0 + 0x1.0p-20))) continue;
             const uint8_t kj = state_s[j];
             const uint32_t idj = id_s[j];
             if (kj == 1 && int64_t(idj) >= a.capacity) continue;
@@ -224,7 +225,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
                 sz = sz + f[2];
             }
         }
+        qn = 0;
+    };
+    for (int r = 0; r < 9; ++r) {
+        const int zz = cz + r / 3 - 1, yy = cy + r % 3 - 1;
+        if (zz < 0 || zz >= nz || yy < 0 || yy >= ny) continue;
+        const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < nx - 1 ? cx + 1 : nx - 1;
+        const uint32_t kb = uint32_t(x0) + uint32_t(nx) * (uint32_t(yy) + uint32_t(ny) * uint32_t(zz));
+        const uint32_t lo = start[kb] & kStartMask, hi = start[kb + uint32_t(x1 - x0) + 1u] & kStartMask;
+        for (uint32_t j = lo; j < hi; ++j) {
+            if (j == uint32_t(s)) continue;
+            const double4 rj = pos4[j];
+            const double dx = ri.x - rj.x, dy = ri.y - rj.y, dz = ri.z - rj.z;
+            const double reach = ri.w + rj.w;
+            s_q[qn][t] = j;
+            qn += ((dx * dx + dy * dy) + dz * dz <= (reach * reach) * (1.0 + 0x1.0p-20)) ? 1u : 0u;
+            if (__any(qn == uint32_t(kGeomQueue))) flush();  // (the wavefront together)
+        }
     }
+    flush();
     // gate, clamp and move (the sphere step's rules)
     double nxp = ri.x, nyp = ri.y, nzp = ri.z;
     const double fnorm = __builtin_sqrt((sx * sx + sy * sy) + sz * sz);
