@@ -8,19 +8,20 @@
 //
 //   reach  per agent: a cylinder's grid diameter from its current ends
 //   grid   the sphere path's build (keys, sort, starts) on the grid diameters
+//   mid    per sorted agent, the binary32 sphere about its body's midpoint that holds the body
 //   geom   one lane per box-sorted agent walks the 27 boxes as 9 key runs; a candidate passes a
-//          bounding-sphere test (centre distance against the sum of the grid radii, with a
-//          relative margin of 2^-20 on the square, far above rounding), then the closest points
+//          conservative binary32 test of the two midpoint spheres, then the closest points
 //          of the two axes carry virtual spheres of the bodies' diameters and the sphere law
 //          acts between them; a cylinder takes the share s of the force (s its closest point's
 //          position along p -> q); gate, clamp and move as the sphere step (a cylinder moves its
 //          distal end)
 //
 // The arithmetic follows the same expressions in the same order as the definition, so results
-// are reproducible bit for bit.  The walk's cost is its candidate count: the grid sphere about
-// the distal end (radius l + d/2) sets a box edge of up to twice a cylinder's length, about 330
-// candidates per agent at the neurite workload's 18 um boxes.  (Filtering them first with the
-// sphere path's 8-byte records, or with spheres about the axis midpoints, measured no faster.)
+// are reproducible bit for bit.  The walk visits many candidates: the grid sphere about the
+// distal end (radius l + d/2) sets a box edge of up to twice a cylinder's length, about 330
+// candidates per agent at the neurite workload's 18 um boxes.  The midpoint spheres, half as
+// wide for a cylinder, pass far fewer of them to the closest-point law, which runs over per-lane
+// queues in walk order (the order of the sums is the walk's).
 #include "kernels.hpp"
 
 namespace bdm {
@@ -178,13 +179,42 @@ __global__ __launch_bounds__(kBlock) void k_geom_reach(const int64_t *n_ptr, int
 
 constexpr int kGeomQueue = 16;  // candidates past the bounding-sphere test a lane holds (16 KB of LDS per workgroup)
 
+// The walk's filter records, one per sorted agent: the sphere about the body's midpoint that
+// holds the whole body (half its length plus half its diameter; a sphere is its own), as the
+// binary32 copy of the crowded sphere kernel: relative to the lattice origin, the radius scaled
+// by kPretestRadius, tested with pretest_slack.  A contact's closest points lie on the two axes,
+// each within half its axis of the midpoint, and their distance is below the sum of the half
+// diameters, so the midpoint spheres of a contact overlap; their radii sum to at most the
+// largest grid diameter (twice a length plus a diameter), the box edge, which the slack assumes.
+// The grid sphere about the distal end, which the box search needs, has about twice the radius.
+__global__ __launch_bounds__(kBlock) void k_geom_mid(const GridDev *__restrict__ g, const double4 *__restrict__ pos4,
+                                                     const uint32_t *__restrict__ id_s,
+                                                     const uint8_t *__restrict__ state_s, CylIn cyl, int64_t capacity,
+                                                     float4 *__restrict__ mid) {
+    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (!g->valid || s >= g->n) return;
+    const double4 r = pos4[s];
+    double mx = r.x, my = r.y, mz = r.z, rad = r.w;  // a sphere: its centre and radius
+    const uint32_t id = id_s[s];
+    if (state_s[s] == 1 && int64_t(id) < capacity) {
+        const double px = cyl.px[id], py = cyl.py[id], pz = cyl.pz[id];
+        const double dx = r.x - px, dy = r.y - py, dz = r.z - pz;
+        mx = 0.5 * (px + r.x);
+        my = 0.5 * (py + r.y);
+        mz = 0.5 * (pz + r.z);
+        rad = 0.5 * __builtin_sqrt(dot3(dx, dy, dz, dx, dy, dz)) + 0.5 * cyl.dc[id];
+    }
+    mid[s] = make_float4(float(mx - double(g->cmin[0]) * g->b), float(my - double(g->cmin[1]) * g->b),
+                         float(mz - double(g->cmin[2]) * g->b), float(rad * kPretestRadius));
+}
+
 // Six wavefronts per SIMD (80 registers, a few spilled) instead of the four that the
 // compiler's 102 registers allow: measured 2.02 -> 1.95 ms per step of the neurite workload.
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_geom(GridDev *__restrict__ g, const double4 *__restrict__ pos4,
                                                  const double *__restrict__ adh_s, const uint32_t *__restrict__ id_s,
                                                  const uint8_t *__restrict__ state_s,
                                                  const uint32_t *__restrict__ start, CylIn cyl, GeomArgs a,
-                                                 bdm_soa out, uint32_t *counts) {
+                                                 bdm_soa out, uint32_t *counts, const float4 *__restrict__ mid) {
     __shared__ uint32_t s_q[kGeomQueue][kBlock];  // each lane uses its own column only
     const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (!g->valid || s >= g->n) return;
@@ -201,6 +231,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     const int cy = box_coord(ri.y, b, g->cmin[1], g->dims[1], false);
     const int cz = box_coord(ri.z, b, g->cmin[2], g->dims[2], false);
     const int nx = g->dims[0], ny = g->dims[1], nz = g->dims[2];
+    const float4 mi = mid[s];
+    const float slack = pretest_slack(g);
     double sx = 0.0, sy = 0.0, sz = 0.0;
     uint32_t contacts = 0;
     // Candidates that pass the bounding-sphere test go to the lane's queue in walk order; the
@@ -235,11 +267,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
         const uint32_t lo = start[kb] & kStartMask, hi = start[kb + uint32_t(x1 - x0) + 1u] & kStartMask;
         for (uint32_t j = lo; j < hi; ++j) {
             if (j == uint32_t(s)) continue;
-            const double4 rj = pos4[j];
-            const double dx = ri.x - rj.x, dy = ri.y - rj.y, dz = ri.z - rj.z;
-            const double reach = ri.w + rj.w;
             s_q[qn][t] = j;
-            qn += ((dx * dx + dy * dy) + dz * dz <= (reach * reach) * (1.0 + 0x1.0p-20)) ? 1u : 0u;
+            qn += maybe_touch(mi, mid[j], slack) ? 1u : 0u;
             if (__any(qn == uint32_t(kGeomQueue))) flush();  // (the wavefront together)
         }
     }
@@ -283,8 +312,11 @@ void launch_geom(const bdm_soa &s, const CylIn &cyl, const GeomArgs &a, const Ws
                  hipStream_t st) {
     int64_t nb = (a.capacity + kBlock - 1) / kBlock;
     if (nb < 1) nb = 1;
+    // the filter records go to the binary32 copy's array (the sphere build leaves it unused)
+    hipLaunchKernelGGL(k_geom_mid, dim3(unsigned(nb)), dim3(kBlock), 0, st, &w.grid[0], w.pos4, w.ids, w.state, cyl,
+                       a.capacity, w.pos4f);
     hipLaunchKernelGGL(k_geom, dim3(unsigned(nb)), dim3(kBlock), 0, st, &w.grid[0], w.pos4, w.adh, w.ids, w.state,
-                       w.start, cyl, a, s, counts);
+                       w.start, cyl, a, s, counts, w.pos4f);
 }
 
 }  // namespace bdm

@@ -244,14 +244,6 @@ __device__ __forceinline__ uint32_t load_runs(const GridDev *__restrict__ g, con
     return cnt;
 }
 
-// Conservative contact pre-test in binary32 (every real contact passes; see pretest_slack).
-__device__ __forceinline__ bool maybe_touch(const float4 &a, const float4 &c, float slack) {
-    const float dx = a.x - c.x, dy = a.y - c.y, dz = a.z - c.z;
-    const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-    const float s = a.w + c.w;  // scaled radii
-    return d2 < __builtin_fmaf(s, s, slack);
-}
-
 // Coarse all-pairs pre-test of a cooperative walk on the matrix cores: for the 64 agents of a
 // wavefront and a chunk of 64 candidate records, which pairs may pass maybe_touch.  With
 // coordinates relative to the wavefront's origin o (lane 0's record), a' = a - o, c' = c - o,
@@ -412,28 +404,6 @@ struct RecGlobal4 {
     }
 };
 
-
-// Absolute slack of the binary32 pre-test of a slot.  Stored coordinates are relative to the
-// lattice origin o and lie within M = (largest dims + 1) * b of it (plus the rounding of x / b
-// at the lattice edges), so each is off by at most 2^-24 M and a difference by at most
-// e = 2^-23 (M + b) (with b >= r_i + r_j >= the distance of any contact).  Then the binary32
-// squared distance, one product and two fused multiply-adds, exceeds the true one by at most
-// (1 + 2^-24)^3 (2 sqrt(3) d e + 3 e^2); with e doubled, 4 (b + e) e bounds that.  The copy's
-// radii are scaled by 1.0006, so after the rounding of the radii, of their sum and of the fused
-// square-and-add the threshold is at least 1.0012 (r_i + r_j)^2 + slack: the relative margin
-// covers the rounding of every exact law's own contact test.  So no pair that the exact law
-// counts as a contact can fail the pre-test.
-__device__ __forceinline__ float pretest_slack(const GridDev *__restrict__ g) {
-    const double b = g->b;
-    int dm = g->dims[0];
-    if (g->dims[1] > dm) dm = g->dims[1];
-    if (g->dims[2] > dm) dm = g->dims[2];
-    double omax = 0.0;
-    for (int a = 0; a < 3; ++a) omax = fmax(omax, fabs(double(g->cmin[a]) * b));
-    const double M = (double(dm) + 1.0) * b + 0x1p-48 * omax;
-    const double e = 0x1p-22 * (M + b);
-    return float(4.0 * (b + e) * e) * 1.001f;
-}
 
 // Walk over a lane's packed runs (column col of s_run): next() returns the offset of the next
 // candidate in canonical order.  It has no branch: the following run is read from LDS on
