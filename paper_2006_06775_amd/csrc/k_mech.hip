@@ -30,7 +30,7 @@
 namespace bdm {
 
 constexpr int kQueue = 8;          // queued candidates per lane before an exact pass
-constexpr int kQueueCrowded = 10;  // the same for crowded populations (tens of contacts per agent)
+constexpr int kQueueCrowded = 6;   // the same for crowded populations (must differ from kQueue)
 constexpr uint32_t kCullMaxBox = 8;  // agents in a box up to which its agents drop out-of-reach boxes
 
 // The pair law for agent i with record p and a candidate j at offset (dx, dy, dz) = p - q with
@@ -501,7 +501,7 @@ __device__ __forceinline__ void exact_packed(const SlotDev &S, const double4 &p,
 // With the normal queue the pairs run while the queue has room for two; the exact law then
 // empties it with every lane of the wavefront together (a lane whose queue fills early waits
 // for the others instead of running its own exact pass alone), and the last pass is the
-// packed one.  In crowded populations nearly every lane fills its longer queue within a few
+// packed one.  In crowded populations nearly every lane fills its own queue within a few
 // candidates of the others, and each lane empties it where it fills (measured faster there).
 template <bool F32, int kQ, class Rec, class Pre, class Tr>
 __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const double4 &p,
@@ -532,7 +532,7 @@ __device__ __forceinline__ void mech_forces(const SlotDev &S, uint32_t q, const 
                         if (hit) tr.hit(s_q[k][t]);
                     }
                 }
-            } else {  // the longer queue's kernel has registers to spare: two records ahead
+            } else {  // the crowded kernel's exact pass keeps two records ahead
                 const uint32_t last = qn - 1u;
                 double4 r = rec.full(s_q[0][t]);
                 double4 r1 = rec.full(s_q[min(1u, last)][t]);
@@ -831,9 +831,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     mech_plain<kPrec, kQueue, Tr, true>(sl, order, rec, adh_s, id_s, state_s, key_s, start, out, tout, sk);
 }
 
-// The crowded queue.  Its LDS (32 KB per workgroup with a queue of 10) allows five wavefronts per
-// SIMD; a queue of 16 (38 KB) allowed four and was 7 % slower over the 60-step spheroid, 1.5 %
-// faster over the 122 steps to 4.1 M cells, whose last cells have about 1100 contacts each.
+// The crowded queue.  Its LDS (28 KB per workgroup with a queue of 6) allows five wavefronts per
+// SIMD, as the registers do.  With the cooperative walk's pre-test on the matrix cores, queues of
+// 5, 6, 7 and 10 took the 60-step spheroid 0.075, 0.077, 0.080 and 0.087 s and the 122 steps to
+// 4.1 M cells 2.35, 2.33, 2.33-2.34 and 2.32-2.34 s: shorter queues leave fewer lanes idle in
+// each exact pass.
 template <int kPrec, class Tr, class Rec>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_mech_crowded(
     Slots sl, const uint32_t *__restrict__ order, Rec rec, const double *__restrict__ adh_s,
@@ -1005,7 +1007,7 @@ __global__ __launch_bounds__(1024) void k_grid_consume(GridDev *g, const uint32_
 }
 
 // crowded: a population packed so densely that agents have tens of contacts (the growing
-// spheroid); a longer queue then saves exact-law rounds, at the cost of LDS (occupancy).
+// spheroid): the kernel with the cooperative walk and its own queue length.
 void launch_mech(const bdm_soa &s, const Slots &sl, int64_t capacity, int precision, bool crowded, const Ws &w,
                  hipStream_t st, const TraceOut *trace) {
     const int64_t ntiles = (capacity + kBlock - 1) / kBlock;
