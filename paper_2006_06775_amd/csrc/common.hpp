@@ -340,15 +340,6 @@ __device__ __forceinline__ uint32_t fastdiv(uint32_t a, unsigned long long m) {
     return m ? uint32_t(__umul64hi(m, a)) : a;
 }
 
-// Box coordinates of a key (x fastest) by fast division.
-__device__ __forceinline__ void key_coords(const GridDev *__restrict__ g, uint32_t key, int &cx, int &cy, int &cz) {
-    const uint32_t row = fastdiv(key, g->div_nx);
-    cx = int(key - row * uint32_t(g->dims[0]));
-    const uint32_t z = fastdiv(row, g->div_ny);
-    cy = int(row - z * uint32_t(g->dims[1]));
-    cz = int(z);
-}
-
 // Wavefront-wide inclusive prefix sum (64 lanes).
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     const int lane = threadIdx.x & 63;

@@ -14,8 +14,8 @@
 //   scatter    ids into their box range in arrival order
 //   canon      each agent counts the smaller ids in its box (ascending-id order inside a box)
 //              and copies itself into the sorted copy: (x, y, z, r = d/2) packed as double4
-//              (halving and doubling a binary64 are exact, so d = 2r is recovered bit for bit)
-//              plus its box key, and for mechanics the records that only the conservative
+//              (halving and doubling a binary64 are exact, so d = 2r is recovered bit for bit),
+//              and for mechanics the records that only the conservative
 //              contact pre-test reads: an 8-byte fixed-point record (offsets within the box) and,
 //              for spheroid steps, a binary32 copy (x - o, y - o, z - o, r) relative to the
 //              lattice origin o
@@ -715,7 +715,8 @@ __global__ __launch_bounds__(kBlock) void k_bucket_scatter(Slots sl, int64_t nti
 //   4. each agent counts the smaller ids of its box, which gives its final position, and copies
 //      (x, y, z, r = d/2) packed as a double4 (halving and doubling a binary64 are exact, so d =
 //      2r is recovered bit for bit), its pre-test records (the 8-byte one; the binary32 copy
-//      relative to the lattice origin when asked for), adh, id, state and its box key there.
+//      relative to the lattice origin when asked for), adh, id and state there (the mechanics
+//      finds an agent's box from its position, as the key was computed).
 // A bucket holds any number of agents (the wavefront walks them 64 at a time).
 struct SortOut {
     double4 *pos4;
@@ -724,7 +725,6 @@ struct SortOut {
     double *adh;
     uint32_t *id;
     uint8_t *state;
-    uint32_t *key;       // box key of each sorted agent
     uint32_t *tile_key;  // key of every tile's first agent (plain calls only)
     uint8_t *dirty;      // stationary skip (plain calls): box marks, folded into the starts
     double *fprev;       // stationary skip: the agents' last forces in the new sorted order
@@ -834,7 +834,6 @@ __device__ __forceinline__ void sort_write(const SortCtx &c, const BucketAgent &
     }
     if (c.s.adh) c.o.adh[dst] = a.adh;
     c.o.id[dst] = a.id;
-    c.o.key[dst] = a.k;
     if (c.s.state) c.o.state[dst] = a.st;
     if (c.o.tile_key && (dst & (kBlock - 1)) == 0) c.o.tile_key[dst / kBlock] = a.k;
     if (c.fold) {
@@ -1195,14 +1194,13 @@ void launch_grid_build(const bdm_soa &s, const Slots &sl, int64_t capacity, bool
     launch_scan(w.count, w.bstart, nullptr, w.lay.nbuckets, w, 1, false, st, !sl.table);
     hipLaunchKernelGGL(k_bucket_scatter, dim3(nbk), dim3(kBlock), 0, st, sl, nt, w.key, w.rank, w.bstart, w.item,
                        capacity);
-    // per-bucket order; the sorted agents' keys go to the rank array, which nothing reads after
-    // the scatter; plain calls keep each tile's first key in the rank-by-id area; crowded
+    // per-bucket order; plain calls keep each tile's first key in the rank-by-id area; crowded
     // buckets group ids in the scratch id array and agent indices in the division-flag array
     // (free during the build: the tile order is written there afterwards)
     uint32_t *tile_key = sl.table ? nullptr : w.rankid;
     const int periodic = sl.table ? 0 : sl.one.periodic;
     SoaIn in{s.x, s.y, s.z, d, s.adh, s.id, s.state, s.fx, s.fy, s.fz};
-    SortOut o{w.pos4, f32_copy ? w.pos4f : nullptr, w.pos8, w.adh, w.ids, w.state, w.rank, tile_key,
+    SortOut o{w.pos4, f32_copy ? w.pos4f : nullptr, w.pos8, w.adh, w.ids, w.state, tile_key,
               skip ? w.dirty : nullptr, w.fprev};
     const int64_t nwg = (w.lay.nbuckets + kBlock / 64 - 1) / (kBlock / 64);
     hipLaunchKernelGGL(k_bucket_sort, dim3(unsigned(nwg)), dim3(kBlock), 0, st, sl, w.lay.nbuckets,

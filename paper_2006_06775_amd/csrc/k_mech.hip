@@ -687,7 +687,7 @@ struct SkipIO {
 template <int kPrec, int kQ, class Tr, bool kSkip = false, class Rec>
 __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const Rec &rec,
                                           const double *__restrict__ adh_s, const uint32_t *__restrict__ id_s,
-                                          const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
+                                          const uint8_t *__restrict__ state_s,
                                           const uint32_t *__restrict__ start_all, const bdm_soa &out,
                                           uint2 (*s_run)[kBlock], uint32_t (*s_q)[kBlock], typename Rec::Pre *s_stage,
                                           const TraceOut &tout, const SkipIO &sk = SkipIO{}) {
@@ -705,9 +705,13 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
     const bool f32 = kPrec == 32 || (kPrec == 0 && S.force_bits == 32);
     const uint32_t q = uint32_t(g->sorted_base + (l < g->n ? l : g->n - 1));
     const double4 p = rec.full(q * Rec::kUnit);
-    const uint32_t key = key_s[q];
-    int cx, cy, cz;
-    key_coords(g, key, cx, cy, cz);
+    // the agent's box from its position, as the build computed its key (binary64 division and
+    // floor, clamped to the lattice): no sorted key array is written or read
+    const int cx = box_coord(p.x, g->b, g->cmin[0], g->dims[0], false);
+    const int cy = box_coord(p.y, g->b, g->cmin[1], g->dims[1], false);
+    const int cz = box_coord(p.z, g->b, g->cmin[2], g->dims[2], false);
+    [[maybe_unused]] const uint32_t key =
+        uint32_t(cx) + uint32_t(g->dims[0]) * (uint32_t(cy) + uint32_t(g->dims[1]) * uint32_t(cz));
     RowUnion un;
     bool marked = false;
     uint32_t cnt = load_runs<Rec::kUnit, kQ == kQueueCrowded, kSkip>(g, start_all + S.box_off, cx, cy, cz, p, live,
@@ -786,7 +790,7 @@ __device__ __forceinline__ void mech_tile(const Slots &sl, int64_t tile, const R
 template <int kPrec, int kQ, class Tr, bool kSkip = false, class Rec>
 __device__ __forceinline__ void mech_plain(const Slots &sl, const uint32_t *__restrict__ order, const Rec &rec,
                                            const double *__restrict__ adh_s, const uint32_t *__restrict__ id_s,
-                                           const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
+                                           const uint8_t *__restrict__ state_s,
                                            const uint32_t *__restrict__ start, const bdm_soa &out,
                                            const TraceOut &tout, const SkipIO &sk = SkipIO{}) {
     __shared__ uint2 s_run[9][kBlock];
@@ -808,7 +812,7 @@ __device__ __forceinline__ void mech_plain(const Slots &sl, const uint32_t *__re
     }
     const uint32_t live_tiles = uint32_t((g0->n + kBlock - 1) / kBlock);
     if (blockIdx.x >= live_tiles) return;
-    mech_tile<kPrec, kQ, Tr, kSkip>(sl, order[xcd_tile(blockIdx.x, live_tiles)], rec, adh_s, id_s, state_s, key_s,
+    mech_tile<kPrec, kQ, Tr, kSkip>(sl, order[xcd_tile(blockIdx.x, live_tiles)], rec, adh_s, id_s, state_s,
                                     start, out, s_run, s_q, s_stage, tout, sk);
 }
 
@@ -817,18 +821,18 @@ __device__ __forceinline__ void mech_plain(const Slots &sl, const uint32_t *__re
 template <int kPrec, class Tr, class Rec>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_mech(
     Slots sl, const uint32_t *__restrict__ order, Rec rec, const double *__restrict__ adh_s,
-    const uint32_t *__restrict__ id_s, const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
+    const uint32_t *__restrict__ id_s, const uint8_t *__restrict__ state_s,
     const uint32_t *__restrict__ start, bdm_soa out, TraceOut tout) {
-    mech_plain<kPrec, kQueue, Tr>(sl, order, rec, adh_s, id_s, state_s, key_s, start, out, tout);
+    mech_plain<kPrec, kQueue, Tr>(sl, order, rec, adh_s, id_s, state_s, start, out, tout);
 }
 
 // The same with the stationary skip.
 template <int kPrec, class Tr, class Rec>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_mech_skip(
     Slots sl, const uint32_t *__restrict__ order, Rec rec, const double *__restrict__ adh_s,
-    const uint32_t *__restrict__ id_s, const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
+    const uint32_t *__restrict__ id_s, const uint8_t *__restrict__ state_s,
     const uint32_t *__restrict__ start, bdm_soa out, TraceOut tout, SkipIO sk) {
-    mech_plain<kPrec, kQueue, Tr, true>(sl, order, rec, adh_s, id_s, state_s, key_s, start, out, tout, sk);
+    mech_plain<kPrec, kQueue, Tr, true>(sl, order, rec, adh_s, id_s, state_s, start, out, tout, sk);
 }
 
 // The crowded queue.  Its LDS (28 KB per workgroup with a queue of 6) allows five wavefronts per
@@ -839,9 +843,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
 template <int kPrec, class Tr, class Rec>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_mech_crowded(
     Slots sl, const uint32_t *__restrict__ order, Rec rec, const double *__restrict__ adh_s,
-    const uint32_t *__restrict__ id_s, const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s,
+    const uint32_t *__restrict__ id_s, const uint8_t *__restrict__ state_s,
     const uint32_t *__restrict__ start, bdm_soa out, TraceOut tout) {
-    mech_plain<kPrec, kQueueCrowded, Tr>(sl, order, rec, adh_s, id_s, state_s, key_s, start, out, tout);
+    mech_plain<kPrec, kQueueCrowded, Tr>(sl, order, rec, adh_s, id_s, state_s, start, out, tout);
 }
 
 // Batch (precision per slot): the workgroups stride over the tiles (a simulation's tiles spread
@@ -851,13 +855,12 @@ __global__ __launch_bounds__(kBlock) void k_mech_batch(Slots sl, int64_t ntiles,
                                                        const double *__restrict__ adh_s,
                                                        const uint32_t *__restrict__ id_s,
                                                        const uint8_t *__restrict__ state_s,
-                                                       const uint32_t *__restrict__ key_s,
-                                                       const uint32_t *__restrict__ start, bdm_soa out,
+                                                                                                              const uint32_t *__restrict__ start, bdm_soa out,
                                                        TraceOut tout) {
     __shared__ uint2 s_run[9][kBlock];
     __shared__ uint32_t s_q[kQueue][kBlock];
     for (int64_t tile = xcd_tile(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x)
-        mech_tile<0, kQueue, Tr>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q, nullptr, tout);
+        mech_tile<0, kQueue, Tr>(sl, tile, rec, adh_s, id_s, state_s, start, out, s_run, s_q, nullptr, tout);
 }
 
 // Batch, one workgroup per tile (the work split that deals every tile its own workgroup): without
@@ -866,13 +869,13 @@ __global__ __launch_bounds__(kBlock) void k_mech_batch(Slots sl, int64_t ntiles,
 template <class Tr, class Rec>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_mech_batch_tile(
     Slots sl, int64_t ntiles, Rec rec, const double *__restrict__ adh_s, const uint32_t *__restrict__ id_s,
-    const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ key_s, const uint32_t *__restrict__ start,
+    const uint8_t *__restrict__ state_s, const uint32_t *__restrict__ start,
     bdm_soa out, TraceOut tout) {
     __shared__ uint2 s_run[9][kBlock];
     __shared__ uint32_t s_q[kQueue][kBlock];
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile < ntiles)
-        mech_tile<0, kQueue, Tr>(sl, tile, rec, adh_s, id_s, state_s, key_s, start, out, s_run, s_q, nullptr, tout);
+        mech_tile<0, kQueue, Tr>(sl, tile, rec, adh_s, id_s, state_s, start, out, s_run, s_q, nullptr, tout);
 }
 
 // Test hook: contact lists per sorted slot in force-sum order (mechanical contact, plain calls).
@@ -921,7 +924,7 @@ static void launch_mech_rec(const bdm_soa &s, const Slots &sl, int64_t ntiles, u
                             const uint32_t *order, const Rec &rec, const Ws &w, const TraceOut &tout, hipStream_t st) {
 #define BDM_MECH(K, P)                                                                                     \
     hipLaunchKernelGGL((K<P, Tr, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, order, rec, w.adh, w.ids, w.state, \
-                       w.rank, w.start, s, tout)
+                       w.start, s, tout)
     if constexpr (Rec::kF32Copy) {  // the crowded kernel
         if (precision == 32)
             BDM_MECH(k_mech_crowded, 32);
@@ -931,20 +934,20 @@ static void launch_mech_rec(const bdm_soa &s, const Slots &sl, int64_t ntiles, u
         const SkipIO sk{w.fprev, w.moved, w.dirty, w.tileskip};
         if (precision == 32)
             hipLaunchKernelGGL((k_mech_skip<32, Tr, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, order, rec, w.adh, w.ids,
-                               w.state, w.rank, w.start, s, tout, sk);
+                               w.state, w.start, s, tout, sk);
         else
             hipLaunchKernelGGL((k_mech_skip<64, Tr, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, order, rec, w.adh, w.ids,
-                               w.state, w.rank, w.start, s, tout, sk);
+                               w.state, w.start, s, tout, sk);
     } else if (precision == 32) {
         BDM_MECH(k_mech, 32);
     } else if (precision == 64) {
         BDM_MECH(k_mech, 64);
     } else if (int64_t(nb) >= ntiles) {  // a workgroup for every tile
         hipLaunchKernelGGL((k_mech_batch_tile<Tr, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, ntiles, rec, w.adh,
-                           w.ids, w.state, w.rank, w.start, s, tout);
+                           w.ids, w.state, w.start, s, tout);
     } else {
         hipLaunchKernelGGL((k_mech_batch<Tr, Rec>), dim3(nb), dim3(kBlock), 0, st, sl, ntiles, rec, w.adh, w.ids,
-                           w.state, w.rank, w.start, s, tout);
+                           w.state, w.start, s, tout);
     }
 #undef BDM_MECH
 }
