@@ -40,10 +40,16 @@ def pick(table: dict) -> dict:
 
 
 def pick_cap(row: dict, default: int = DEFAULT_CAP, margin: float = 0.02) -> int:
-    """Fastest work split, or the default unless another is faster by more than `margin`."""
+    """Fastest work split, or the default unless another is faster by more than `margin`.  Among
+    splits within `margin` of the fastest, one workgroup per tile (-1) is taken: it has no
+    striding loop and fills the device for any mix of slots, which a served stream varies more
+    than the measured batch does (the two best splits timing within 0.3 % of each other, a
+    32768-workgroup cap served the stream at 1.28x against 1.37-1.46x for one per tile)."""
     best = min(row, key=lambda c: (row[c], c))
     if default in row and row[best] > (1.0 - margin) * row[default]:
         return default
+    if -1 in row and row[-1] <= (1.0 + margin) * row[best]:
+        return -1
     return best
 
 

@@ -78,6 +78,8 @@ def test_tune_pick_and_plan_lookup():
     # one workgroup per tile (-1) competes like any other split
     assert tune.pick_cap({-1: 0.145e-9, 8192: 0.187e-9, 32768: 0.146e-9}) == -1
     assert tune.pick_cap({-1: 0.186e-9, 8192: 0.187e-9}) == 8192
+    assert tune.pick_cap({-1: 0.1453e-9, 8192: 0.187e-9, 32768: 0.145e-9}) == -1  # near-tie: one per tile
+    assert tune.pick_cap({-1: 0.16e-9, 8192: 0.187e-9, 32768: 0.145e-9}) == 32768
     assert -1 in tune.GRID_CAPS
     summary = tune.BoxPlan(15.0, {1000: 1.0}, grid_cap=-1, split_table={-1: 1e-10, 8192: 2e-10}).summary()
     assert summary["grid_cap"] == -1 and set(summary["split_ns_per_agent_update"]) == {"-1", "8192"}
